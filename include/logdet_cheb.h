@@ -1,0 +1,157 @@
+/*
+ * logdet_cheb.h -- C ABI of the MI355X (gfx950) stochastic Chebyshev log-determinant
+ * library, liblogdet_cheb.so.
+ *
+ * Method: Han, Malioutov & Shin, "Large-scale Log-determinant Computation through
+ * Stochastic Chebyshev Expansions" (arXiv 1503.06394).  For a symmetric positive
+ * definite B with spectrum inside [a, b] the library maps B onto
+ *     At = (2 B - (a + b) I) / (b - a)               (spectrum in [-1, 1], Section 4.1),
+ * interpolates f(x) = log(((b - a) x + (a + b)) / 2) at the n + 1 first-kind Chebyshev
+ * nodes (eq. (1), FP64 on the host), runs the three-term recurrence
+ *     W_1 = At V,   W_{k+1} = 2 At W_k - W_{k-1}     (eq. (2); Section 2.2)
+ * over a block V of M Rademacher probes (Section 2.2) and accumulates the moments
+ * mu[j][k] = v_j^T W_k[:, j]; the estimate is
+ *     Gamma = (1/M) sum_j sum_k c_k mu[j][k]         (Algorithm 1, final step),
+ * which equals Algorithm 1's v^T u by linearity.
+ *
+ * Conventions shared by every entry point:
+ *  - All matrix and vector pointers are DEVICE pointers owned by the caller, on the
+ *    current HIP device.  The library never frees caller memory.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on it and
+ *    the call synchronises it before returning, because results are host doubles.
+ *  - Return value: 0 success; negative = error, outputs untouched, message available
+ *    from ld_last_error(); positive = warning with the result filled in.
+ *  - CSR: row_ptr monotone with row_ptr[0] = 0 and row_ptr[rows] = nnz, column
+ *    indices in [0, cols), no duplicates.  These are trusted, not checked on device.
+ *  - Probe j (0 <= j < M) has entry v_j[r] = +1 or -1 at row r from the counter hash
+ *        ctr  = (r << 16) | (j >> 6)
+ *        word = SplitMix64 output function of (seed + (ctr + 1) * 0x9E3779B97F4A7C15)
+ *        v_j[r] = (bit (j & 63) of word) ? -1 : +1
+ *    (SplitMix64: Steele, Lea & Flood, OOPSLA 2014).  Matrix i of a batch uses seed + i.
+ *  - Nothing here throws or aborts.
+ */
+#ifndef LOGDET_CHEB_H
+#define LOGDET_CHEB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LD_OK 0
+#define LD_EINVAL (-1)     /* null pointer, rows != cols, n < 0, M < 1, bad bounds, ... */
+#define LD_EDTYPE (-2)     /* unsupported value / vector type combination */
+#define LD_EWORKSPACE (-3) /* caller workspace smaller than ld_workspace_bytes() */
+#define LD_EHIP (-4)       /* HIP runtime error (message in ld_last_error) */
+#define LD_ENOMEM (-5)     /* device allocation failed */
+#define LD_WBOUNDS 1       /* warning: some |mu[j][k]| > d (1 + 1e-6): [a, b] misses the spectrum */
+
+/* value types of ld_csr.values */
+#define LD_F64 0
+#define LD_F32 1
+#define LD_BF16 2
+
+/* Square sparse matrix on the device.  The effective matrix is values + diag_shift * I;
+ * the shift is kept as an FP64 scalar so that small shifts survive low-precision
+ * storage (e.g. 4 + 0.01 is not representable in BF16). */
+typedef struct {
+    int64_t rows, cols, nnz;
+    const int64_t *row_ptr; /* rows + 1 */
+    const int32_t *col_idx; /* nnz */
+    const void *values;     /* nnz elements of type `dtype` */
+    int32_t dtype;          /* LD_F64 | LD_F32 | LD_BF16 */
+    int32_t reserved;       /* must be 0 */
+    double diag_shift;
+} ld_csr;
+
+typedef struct {
+    double logdet;          /* Gamma */
+    double std_err;         /* sample standard deviation of the per-probe estimates / sqrt(M) */
+    double poly_bound;      /* Lemma 7 bound on |log det - tr p_n| for delta = a / (a + b) */
+    double grad_shift;      /* d Gamma / d diag_shift (gradient entry point only) */
+    double kernel_ms;       /* with ld_opts.timing: summed duration of the recurrence-step kernels */
+    int32_t kernel_launches;/* with ld_opts.timing: number of recurrence-step kernels timed */
+    int32_t n, M;
+    uint32_t flags;         /* bit 0: LD_WBOUNDS seen */
+} ld_result;
+
+typedef struct {
+    void *workspace;          /* device scratch or NULL (then the library allocates on `stream`) */
+    size_t workspace_bytes;
+    int32_t vec_f64;          /* recurrence vectors in FP64 (1) or FP32 (0) */
+    int32_t ckpt_stride;      /* gradient: checkpoint every s steps; 0 = ceil(sqrt(n)) */
+    int32_t tile;             /* kernel shape: 0 = autotuned, > 0 = rows per workgroup */
+    int32_t timing;           /* 1 = time recurrence-step kernels with HIP events on `stream` */
+    double *moments_out;      /* host, nullable: M x (n+1) moments mu[j][k] = v_j^T T_k(At) v_j */
+    double *probe_out;        /* host, nullable: M per-probe estimates s_j = sum_k c_k mu[j][k] */
+} ld_opts;
+
+/* Algorithm 1 in the [a, b] form: estimate log det(B + diag_shift I).
+ * Requires 0 < a < b finite, n >= 0, 1 <= M <= 4096.  With vec_f64 = 0 the recurrence runs
+ * in FP32 and the moments, coefficients and final sum in FP64. */
+int ld_logdet_cheb(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
+                   const ld_opts *opt, void *stream, ld_result *out);
+
+/* Algorithm 2: estimate log|det C| for a non-singular C with singular values in
+ * [smin, smax], via log|det C| = (1/2) log det(C^T C).  The recurrence applies C^T (C w)
+ * with two sparse products per step.  Ct (nullable) is C^T in CSR form with the same
+ * dtype; if NULL the library builds it on the device for the duration of the call.
+ * C's diag_shift must be 0. */
+int ld_logabsdet_cheb(const ld_csr *C, const ld_csr *Ct, double smin, double smax, int n, int M,
+                      uint64_t seed, const ld_opts *opt, void *stream, ld_result *out);
+
+/* Gradient of the ld_logdet_cheb estimate (same B, a, b, n, M, seed, with a and b held
+ * fixed) with respect to every stored entry of B, scaled by grad_output:
+ *     grad_values[t] = grad_output * dGamma/dB_{row(t), col(t)}.
+ * The adjoint recurrence y_k = c_k v + 2 At y_{k+1} - y_{k+2} runs backwards over
+ * segments recomputed from checkpoints every ckpt_stride steps.  grad_values is a device
+ * array of nnz elements of type grad_dtype (LD_F64 or LD_F32).  out->grad_shift receives
+ * grad_output * dGamma/d diag_shift and out->logdet the forward estimate. */
+int ld_logdet_cheb_grad(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
+                        double grad_output, void *grad_values, int grad_dtype,
+                        const ld_opts *opt, void *stream, ld_result *out);
+
+/* Batched Algorithm 1: matrix i (count of them, uneven sizes) uses its own bounds
+ * [a[i], b[i]], degree n[i] and probe seed seed + i, all with M probes.  The whole batch
+ * runs as one captured HIP graph.  a, b, n, outs are host arrays of `count` entries;
+ * Bs is a host array of descriptors pointing at device data.  opt->moments_out and
+ * opt->probe_out are ignored. */
+int ld_logdet_cheb_batched(int count, const ld_csr *Bs, const double *a, const double *b,
+                           const int *n, int M, uint64_t seed, const ld_opts *opt, void *stream,
+                           ld_result *outs);
+
+/* Gershgorin interval of B + diag_shift I (FP64):
+ * a = min_i (B_ii + shift - sum_{j != i} |B_ij|), b = max_i (B_ii + shift + sum_{j != i} |B_ij|). */
+int ld_gershgorin(const ld_csr *B, double *a, double *b, void *stream);
+
+/* Write the probe block: out[r * M + j] = v_j[r] (int8, +1/-1), r < rows, j < M. */
+int ld_probes(uint64_t seed, int M, int64_t rows, int8_t *out, void *stream);
+
+/* C^T of a square CSR matrix into caller buffers (row_ptr_t: rows+1, col_t and val_t:
+ * nnz, same dtype); rows of the result have ascending column indices. */
+int ld_transpose(const ld_csr *C, int64_t *row_ptr_t, int32_t *col_t, void *val_t, void *stream);
+
+/* Device bytes the entry point `mode` (0 logdet, 1 logabsdet, 2 grad) needs as workspace. */
+size_t ld_workspace_bytes(const ld_csr *B, int n, int M, int mode, int vec_f64);
+
+/* Device-to-device streaming copy with the library's own kernel (HBM bandwidth probe);
+ * returns the kernel duration in milliseconds through *ms (nullable). */
+int ld_copy(void *dst, const void *src, size_t bytes, void *stream, double *ms);
+
+/* Release the library's cached batched graphs (with their device memory) and autotuning
+ * results.  Not safe to call while another thread is inside the library. */
+int ld_clear_cache(void);
+
+/* Message for the last non-zero status returned on this thread. */
+const char *ld_last_error(void);
+
+/* Library version string. */
+const char *ld_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOGDET_CHEB_H */

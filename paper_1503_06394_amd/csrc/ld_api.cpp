@@ -1,0 +1,1103 @@
+// Host planner and C-ABI entry points of liblogdet_cheb (see include/logdet_cheb.h).
+//
+// The planner validates arguments, computes the Chebyshev coefficients of eq. (1) in
+// FP64, folds the affine map of Section 4.1 into the step scalars
+//     alpha = 4 / (b - a),  beta = -2 (a + b) / (b - a)   (2 At = alpha B + beta I),
+// picks a kernel shape (autotuned once per matrix signature), carves the workspace, and
+// enqueues the recurrence steps of Algorithm 1 (or Algorithm 2, the adjoint, or the
+// batch) on the caller's stream.  Per-probe moments come back to the host, where the
+// estimate Gamma = (1/M) sum_j sum_k c_k mu[j][k] is formed in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/logdet_cheb.h"
+#include "ld_internal.h"
+
+using namespace ld;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(LD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LD_HIP(call)                               \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return fail_hip(e_, #call); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carve of a device workspace (first pass with base == nullptr sizes it).
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
+  void* take(size_t bytes) {
+    off = align_up(off);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+// Workspace: the caller's, or a stream-ordered allocation released on scope exit.
+struct Workspace {
+  void* ptr = nullptr;
+  bool owned = false;
+  hipStream_t stream = nullptr;
+  ~Workspace() {
+    if (owned && ptr) {
+      (void)hipFreeAsync(ptr, stream);
+      (void)hipStreamSynchronize(stream);
+    }
+  }
+};
+
+int get_workspace(const ld_opts* opt, size_t need, hipStream_t s, Workspace& ws) {
+  ws.stream = s;
+  if (opt && opt->workspace) {
+    if (opt->workspace_bytes < need)
+      return fail(LD_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes needed", opt->workspace_bytes,
+                  need);
+    ws.ptr = opt->workspace;
+    return LD_OK;
+  }
+  if (need == 0) return LD_OK;
+  hipError_t e = hipMallocAsync(&ws.ptr, need, s);
+  if (e != hipSuccess) return fail(LD_ENOMEM, "hipMallocAsync(%zu): %s", need, hipGetErrorString(e));
+  ws.owned = true;
+  return LD_OK;
+}
+
+int valt_of(int32_t dtype) {
+  switch (dtype) {
+    case LD_F64: return VAL_F64;
+    case LD_F32: return VAL_F32;
+    case LD_BF16: return VAL_BF16;
+    default: return -1;
+  }
+}
+
+size_t val_bytes(int valt) { return valt == VAL_F64 ? 8 : (valt == VAL_F32 ? 4 : 2); }
+
+int check_csr(const ld_csr* B, const char* name) {
+  if (!B) return fail(LD_EINVAL, "%s is NULL", name);
+  if (B->rows < 0 || B->rows != B->cols) return fail(LD_EINVAL, "%s must be square (rows=%lld cols=%lld)", name,
+                                                     (long long)B->rows, (long long)B->cols);
+  if (B->nnz < 0 || (B->rows > 0 && B->nnz > B->rows * B->cols))
+    return fail(LD_EINVAL, "%s has invalid nnz %lld", name, (long long)B->nnz);
+  if (B->rows > 0 && !B->row_ptr) return fail(LD_EINVAL, "%s->row_ptr is NULL", name);
+  if (B->nnz > 0 && (!B->col_idx || !B->values)) return fail(LD_EINVAL, "%s has NULL col_idx or values", name);
+  if (B->rows > (int64_t)0x7FFFFFFF) return fail(LD_EINVAL, "%s has more than 2^31-1 rows", name);
+  if (valt_of(B->dtype) < 0) return fail(LD_EDTYPE, "%s has unknown dtype %d", name, B->dtype);
+  if (B->reserved != 0) return fail(LD_EINVAL, "%s->reserved must be 0", name);
+  if (!std::isfinite(B->diag_shift)) return fail(LD_EINVAL, "%s->diag_shift is not finite", name);
+  return LD_OK;
+}
+
+int check_common(double a, double b, int n, int M) {
+  if (!std::isfinite(a) || !std::isfinite(b) || !(a > 0.0) || !(b > a))
+    return fail(LD_EINVAL, "bounds must satisfy 0 < a < b (finite); got a=%g b=%g", a, b);
+  if (n < 0 || n > 100000) return fail(LD_EINVAL, "degree n=%d out of range [0, 100000]", n);
+  if (M < 1 || M > 4096) return fail(LD_EINVAL, "probe count M=%d out of range [1, 4096]", M);
+  return LD_OK;
+}
+
+// eq. (1): interpolant of f(x) = log(((b - a) x + (a + b)) / 2) at x_k = cos(pi (k + 1/2) / (n + 1)),
+// using T_i(cos t) = cos(i t).
+std::vector<double> cheb_coeffs(double a, double b, int n) {
+  const double pi = 3.14159265358979323846;
+  std::vector<double> fx(n + 1), th(n + 1), c(n + 1);
+  for (int k = 0; k <= n; ++k) {
+    th[k] = pi * (k + 0.5) / (n + 1);
+    fx[k] = std::log(((b - a) * std::cos(th[k]) + (a + b)) / 2.0);
+  }
+  for (int i = 0; i <= n; ++i) {
+    double s = 0.0;
+    for (int k = 0; k <= n; ++k) s += fx[k] * std::cos(i * th[k]);
+    c[i] = (i == 0 ? 1.0 : 2.0) / (n + 1) * s;
+  }
+  return c;
+}
+
+// Lemma 7: 20 d log(2 (1/delta - 1)) / ((K - 1) K^n), delta = a / (a + b).
+double lemma_bound(double a, double b, int n, int64_t d) {
+  const double delta = a / (a + b);
+  const double K = (std::sqrt(2.0 - delta) + std::sqrt(delta)) / (std::sqrt(2.0 - delta) - std::sqrt(delta));
+  return 20.0 * (double)d * std::log(2.0 * (1.0 / delta - 1.0)) / ((K - 1.0) * std::pow(K, n));
+}
+
+// ------------------------------------------------------------------------------------
+// kernel shape planning and autotuning
+// ------------------------------------------------------------------------------------
+
+Shape base_shape(int vec_f64, int M) {
+  Shape sh{};
+  if (!vec_f64)
+    sh.vpl = (M % 4 == 0) ? 4 : ((M % 2 == 0) ? 2 : 1);
+  else
+    sh.vpl = (M % 2 == 0) ? 2 : 1;
+  int lanes = (M + sh.vpl - 1) / sh.vpl;
+  int lg = 0;
+  while ((1 << lg) < lanes && lg < 6) ++lg;
+  sh.lpr_log2 = lg;
+  const int tile_probes = (1 << lg) * sh.vpl;
+  sh.probe_tiles = (M + tile_probes - 1) / tile_probes;
+  return sh;
+}
+
+int rows_per_iter(const Shape& sh) { return 4 * (64 >> sh.lpr_log2); }
+
+Shape with_tile(Shape sh, int64_t d, int tile_override) {
+  const int rpi = rows_per_iter(sh);
+  if (tile_override > 0) {
+    sh.tile_rows = (tile_override + rpi - 1) / rpi * rpi;
+    return sh;
+  }
+  int64_t u = d / ((int64_t)rpi * 8192);
+  u = std::max<int64_t>(1, std::min<int64_t>(u, 64));
+  sh.tile_rows = (int)(rpi * u);
+  return sh;
+}
+
+struct TuneKey {
+  int vec, valt, M, mode;
+  int64_t d, nnz;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(vec, valt, M, mode, d, nnz) < std::tie(o.vec, o.valt, o.M, o.mode, o.d, o.nnz);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;  // -> tile_rows
+
+bool autotune_enabled() {
+  const char* e = std::getenv("LD_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+// Time the general recurrence step (k >= 2 form) for candidate tile heights on the
+// caller's data and return the fastest.  Buffers are scratch; their contents do not
+// matter for timing.
+int autotune_tile(const ld_csr* B, const Shape& base, int vec_f64, int valt, int M, void* bufA, void* bufB,
+                  double* part, hipStream_t s) {
+  const int rpi = rows_per_iter(base);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return 0;
+  }
+  float best = 1e30f;
+  int best_rows = 0;
+  for (int u : {1, 2, 4, 8, 16, 32, 64}) {
+    Shape sh = base;
+    sh.tile_rows = rpi * u;
+    const int64_t ntiles = (B->rows + sh.tile_rows - 1) / sh.tile_rows;
+    if (ntiles < 512 && u > 1) break;  // keep the chip full
+    StepLaunch L{};
+    L.nmat = 1;
+    L.ntiles = ntiles;
+    L.tile_rows = sh.tile_rows;
+    L.M = M;
+    L.shape = sh;
+    StepDesc& D = L.d0;
+    D.row_ptr = B->row_ptr;
+    D.col = B->col_idx;
+    D.val = B->values;
+    D.G = bufA;
+    D.P = bufB;
+    D.out = bufB;
+    D.ag = 1.0;
+    D.bd = 0.0;
+    D.cp = -1.0;
+    D.d = B->rows;
+    D.mu_part = part;
+    D.active = 1;
+    float tot = 0.f;
+    bool ok = true;
+    for (int rep = 0; rep < 4 && ok; ++rep) {
+      ok = hipEventRecord(e0, s) == hipSuccess &&
+           launch_step(L, vec_f64, valt, SRC_BUF, SRC_SAME, SRC_BUF, true, s) == hipSuccess &&
+           hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+      float ms = 0.f;
+      if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && rep > 0) tot += ms;
+    }
+    if (ok && tot < best) {
+      best = tot;
+      best_rows = sh.tile_rows;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best_rows;
+}
+
+// ------------------------------------------------------------------------------------
+// step timing (HIP events on the launch stream)
+// ------------------------------------------------------------------------------------
+
+struct StepTimer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<char> timed;  // whether interval i is a recurrence step
+  ~StepTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  hipError_t mark(bool step_interval) {
+    if (!on) return hipSuccess;
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ev.push_back(e);
+    if (ev.size() > 1) timed.push_back(step_interval ? 1 : 0);
+    return hipEventRecord(e, s);
+  }
+  void report(ld_result* out) {
+    out->kernel_ms = 0.0;
+    out->kernel_launches = 0;
+    if (!on) return;
+    for (size_t i = 0; i + 1 < ev.size(); ++i) {
+      if (!timed[i]) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
+        out->kernel_ms += ms;
+        out->kernel_launches += 1;
+      }
+    }
+  }
+};
+
+// Combine FP64 moments into the estimate (host, FP64).  mu is M x (n+1) row-major.
+void combine(const std::vector<double>& mu, const std::vector<double>& c, int n, int M, int64_t d, double half,
+             ld_result* out, const ld_opts* opt) {
+  std::vector<double> sj(M);
+  uint32_t flags = 0;
+  const double lim = (double)d * (1.0 + 1e-6);
+  for (int j = 0; j < M; ++j) {
+    double s = 0.0;
+    for (int k = 0; k <= n; ++k) {
+      const double m = mu[(size_t)j * (n + 1) + k];
+      if (!(std::fabs(m) <= lim)) flags |= 1u;
+      s += c[k] * m;
+    }
+    sj[j] = s * half;
+  }
+  double mean = 0.0;
+  for (int j = 0; j < M; ++j) mean += sj[j];
+  mean /= M;
+  double var = 0.0;
+  for (int j = 0; j < M; ++j) var += (sj[j] - mean) * (sj[j] - mean);
+  out->logdet = mean;
+  out->std_err = M > 1 ? std::sqrt(var / (M - 1) / M) : NAN;
+  out->flags = flags;
+  out->n = n;
+  out->M = M;
+  if (opt && opt->moments_out) std::memcpy(opt->moments_out, mu.data(), sizeof(double) * mu.size());
+  if (opt && opt->probe_out) std::memcpy(opt->probe_out, sj.data(), sizeof(double) * M);
+}
+
+int vec_f64_of(const ld_opts* opt, int valt) {
+  if (!opt || opt->vec_f64 == 0) return valt == VAL_F64 ? 1 : 0;
+  return opt->vec_f64 == 1 ? 1 : 0;
+}
+
+// ------------------------------------------------------------------------------------
+// Algorithm 1 / Algorithm 2 forward driver
+// ------------------------------------------------------------------------------------
+
+struct FwdPlan {
+  Shape sh;
+  int64_t ntiles;
+  size_t vb;
+};
+
+FwdPlan plan_fwd(const ld_csr* B, int vec_f64, int M, const ld_opts* opt) {
+  FwdPlan p;
+  p.sh = with_tile(base_shape(vec_f64, M), B->rows, opt ? opt->tile : 0);
+  p.ntiles = B->rows > 0 ? (B->rows + p.sh.tile_rows - 1) / p.sh.tile_rows : 0;
+  p.vb = vec_f64 ? 8 : 4;
+  return p;
+}
+
+size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, int tile_override) {
+  ld_opts o{};
+  o.tile = tile_override;
+  FwdPlan p = plan_fwd(B, vec_f64, M, &o);
+  // worst case over autotuned tile heights: the smallest tile gives the most tiles
+  Shape small = base_shape(vec_f64, M);
+  const int64_t max_tiles = B->rows > 0 ? (B->rows + rows_per_iter(small) - 1) / rows_per_iter(small) : 0;
+  const int64_t tiles = tile_override > 0 ? p.ntiles : max_tiles;
+  Carve c;
+  const size_t vecb = (size_t)B->rows * M * p.vb;
+  c.take(vecb);  // A
+  c.take(vecb);  // B
+  if (ns) {
+    c.take(vecb);                                   // T
+    c.take((size_t)(B->rows + 1) * 8);              // Ct row_ptr
+    c.take((size_t)B->nnz * 4);                     // Ct col
+    c.take((size_t)B->nnz * val_bytes(valt_of(B->dtype)));
+    c.take((size_t)B->rows * 8);                    // cursor
+    c.take(transpose_scratch_bytes(B->rows));
+  }
+  c.take((size_t)std::max(n, 1) * tiles * M * 8);  // partials for degrees 1..n
+  c.take((size_t)M * (n + 1) * 8);                 // moments
+  return align_up(c.off);
+}
+
+// Shared body of ld_logdet_cheb and ld_logabsdet_cheb.
+int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double b, int n, int M, uint64_t seed,
+                const ld_opts* opt, hipStream_t s, ld_result* out) {
+  const int valt = valt_of(B->dtype);
+  const int vec_f64 = vec_f64_of(opt, valt);
+  const int64_t d = B->rows;
+  const size_t need = fwd_workspace(B, n, M, vec_f64, ns, opt ? opt->tile : 0);
+  Workspace ws;
+  int rc = get_workspace(opt, need, s, ws);
+  if (rc) return rc;
+
+  FwdPlan p = plan_fwd(B, vec_f64, M, opt);
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  const size_t vecb = (size_t)d * M * p.vb;
+  void* bufA = cv.take(vecb);
+  void* bufB = cv.take(vecb);
+  void* bufT = nullptr;
+  ld_csr Ct{};
+  if (ns) {
+    bufT = cv.take(vecb);
+    int64_t* rpt = static_cast<int64_t*>(cv.take((size_t)(d + 1) * 8));
+    int32_t* colt = static_cast<int32_t*>(cv.take((size_t)B->nnz * 4));
+    void* valt_ = cv.take((size_t)B->nnz * val_bytes(valt));
+    int64_t* cursor = static_cast<int64_t*>(cv.take((size_t)d * 8));
+    void* scan = cv.take(transpose_scratch_bytes(d));
+    if (Ct_in) {
+      Ct = *Ct_in;
+    } else {
+      LD_HIP(launch_transpose(B->row_ptr, B->col_idx, B->values, valt, d, B->nnz, rpt, colt, valt_, cursor, scan,
+                              transpose_scratch_bytes(d), s));
+      Ct = *B;
+      Ct.row_ptr = rpt;
+      Ct.col_idx = colt;
+      Ct.values = valt_;
+    }
+  }
+  const bool tune = (!opt || opt->tile == 0) && autotune_enabled() && d >= 65536;
+  double* part_base = nullptr;
+  {
+    // partial buffer is sized for the smallest tile; carve it now
+    Shape small = base_shape(vec_f64, M);
+    const int64_t max_tiles = d > 0 ? (d + rows_per_iter(small) - 1) / rows_per_iter(small) : 0;
+    const int64_t tiles = (opt && opt->tile > 0) ? p.ntiles : max_tiles;
+    part_base = static_cast<double*>(cv.take((size_t)std::max(n, 1) * tiles * M * 8));
+  }
+  double* mu_dev = static_cast<double*>(cv.take((size_t)M * (n + 1) * 8));
+
+  if (tune && !ns) {
+    TuneKey key{vec_f64, valt, M, 0, d, B->nnz};
+    int rows = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) rows = it->second;
+    }
+    if (!rows) {
+      rows = autotune_tile(B, p.sh, vec_f64, valt, M, bufA, bufB, part_base, s);
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = rows;
+    }
+    if (rows > 0) {
+      p.sh.tile_rows = rows;
+      p.ntiles = (d + rows - 1) / rows;
+    }
+  }
+
+  const std::vector<double> c = cheb_coeffs(a, b, n);
+  const double alpha = 4.0 / (b - a);
+  const double beta = -2.0 * (a + b) / (b - a);
+  const double shift = ns ? 0.0 : B->diag_shift;
+  const double beff = beta + alpha * shift;
+  const int64_t kstride = p.ntiles * M;
+
+  StepTimer tm;
+  tm.on = opt && opt->timing;
+  tm.s = s;
+
+  StepLaunch L{};
+  L.nmat = 1;
+  L.ntiles = p.ntiles;
+  L.tile_rows = p.sh.tile_rows;
+  L.M = M;
+  L.shape = p.sh;
+
+  auto base_desc = [&](const ld_csr* X) {
+    StepDesc D{};
+    D.row_ptr = X->row_ptr;
+    D.col = X->col_idx;
+    D.val = X->values;
+    D.seed = seed;
+    D.d = d;
+    D.active = 1;
+    return D;
+  };
+
+  // W_k lives in: k = 0 -> probe hash, odd k -> A, even k >= 2 -> B.
+  auto wbuf = [&](int k) -> void* { return k == 0 ? nullptr : ((k & 1) ? bufA : bufB); };
+  LD_HIP(tm.mark(false));
+  for (int k = 0; k < n && d > 0; ++k) {
+    const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
+    const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
+    const double h = k == 0 ? 0.5 : 1.0;  // W_1 = At V carries half of 2 At
+    if (!ns) {
+      StepDesc D = base_desc(B);
+      D.G = wbuf(k);
+      D.P = k >= 2 ? wbuf(k - 1) : nullptr;
+      D.out = wbuf(k + 1);
+      D.ag = h * alpha;
+      D.bd = h * beff;
+      D.cp = k == 0 ? 0.0 : -1.0;
+      D.mu_part = part_base + (int64_t)k * kstride;
+      L.d0 = D;
+      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, true, s));
+      LD_HIP(tm.mark(true));
+    } else {
+      // T = C W_k
+      StepDesc D1 = base_desc(B);
+      D1.G = wbuf(k);
+      D1.out = bufT;
+      D1.ag = 1.0;
+      L.d0 = D1;
+      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_NONE, SRC_NONE, false, s));
+      LD_HIP(tm.mark(true));
+      // W_{k+1} = alpha C^T T + beta W_k - W_{k-1}   (halved at k = 0)
+      StepDesc D2 = base_desc(&Ct);
+      D2.G = bufT;
+      D2.D = wbuf(k);
+      D2.P = k >= 2 ? wbuf(k - 1) : nullptr;
+      D2.out = wbuf(k + 1);
+      D2.ag = h * alpha;
+      D2.bd = h * beta;
+      D2.cp = k == 0 ? 0.0 : -1.0;
+      D2.mu_part = part_base + (int64_t)k * kstride;
+      L.d0 = D2;
+      LD_HIP(launch_step(L, vec_f64, valt, SRC_BUF, k == 0 ? SRC_HASH : SRC_BUF, psrc, true, s));
+      LD_HIP(tm.mark(true));
+    }
+  }
+  if (n >= 1 && d > 0) LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 1, n, kstride, mu_dev, n + 1, s));
+  std::vector<double> mu((size_t)M * (n + 1), 0.0);
+  if (n >= 1 && d > 0) LD_HIP(hipMemcpyAsync(mu.data(), mu_dev, mu.size() * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < M; ++j) mu[(size_t)j * (n + 1)] = (double)d;  // v^T v = d for Rademacher probes
+  combine(mu, c, n, M, d, ns ? 0.5 : 1.0, out, opt);
+  out->poly_bound = lemma_bound(a, b, n, d) * (ns ? 0.5 : 1.0);
+  out->grad_shift = 0.0;
+  tm.report(out);
+  return out->flags ? LD_WBOUNDS : LD_OK;
+}
+
+}  // namespace
+
+// ======================================================================================
+// gradient
+// ======================================================================================
+
+namespace {
+
+struct GradPlan {
+  int s;                    // checkpoint stride
+  int nseg;                 // segments
+  std::vector<int> slot_of; // W_k -> checkpoint slot (or -1), k = 0..n
+  int nslots;
+  int nseg_buf;             // segment scratch buffers
+};
+
+GradPlan plan_grad(int n, int stride) {
+  GradPlan g;
+  g.s = stride > 0 ? stride : (int)std::ceil(std::sqrt((double)std::max(n, 1)));
+  if (g.s < 2) g.s = 2;
+  g.nseg = n >= 1 ? (n - 1) / g.s + 1 : 0;  // segments cover k = 0..n-1
+  g.slot_of.assign(n + 2, -1);
+  g.nslots = 0;
+  for (int q = 0; q < g.nseg; ++q) {
+    const int k0 = q * g.s;
+    if (k0 >= 1 && k0 <= n - 1) g.slot_of[k0] = g.nslots++;
+    if (k0 + 1 <= n - 1) g.slot_of[k0 + 1] = g.nslots++;
+  }
+  g.nseg_buf = std::max(g.s - 2, 2);
+  return g;
+}
+
+size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, int stride) {
+  const size_t vb = vec_f64 ? 8 : 4;
+  GradPlan g = plan_grad(n, stride);
+  Shape sh = with_tile(base_shape(vec_f64, M), B->rows, 0);
+  const int64_t ntiles = B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
+  Carve c;
+  const size_t vecb = (size_t)B->rows * M * vb;
+  for (int i = 0; i < g.nslots + g.nseg_buf + 2; ++i) c.take(vecb);
+  c.take((size_t)B->nnz * vb);                    // gradient accumulators
+  c.take((size_t)std::max<int64_t>(ntiles, 1) * 8);  // diagonal partials
+  c.take(8);                                      // diagonal total
+  c.take((size_t)std::max(n, 1) * ntiles * M * 8);
+  c.take((size_t)M * (n + 1) * 8);
+  return align_up(c.off);
+}
+
+
+}  // namespace
+
+// ======================================================================================
+// batched
+// ======================================================================================
+
+namespace {
+
+// One captured graph for one batch signature, with the device memory it refers to.
+struct BatchEntry {
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  void* mem = nullptr;
+  double* mu_dev = nullptr;
+  int kmax = 0;
+  std::vector<std::vector<double>> coeffs;
+  ~BatchEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (mem) (void)hipFree(mem);
+  }
+};
+std::mutex g_batch_mu;
+std::map<std::vector<double>, std::unique_ptr<BatchEntry>> g_batch;
+
+double bits_of(const void* p) {
+  uint64_t u = (uint64_t)(uintptr_t)p;
+  double x;
+  std::memcpy(&x, &u, 8);
+  return x;
+}
+
+int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M, uint64_t seed,
+                int vec_f64, int valt, const Shape& sh, BatchEntry& E) {
+  const size_t vb = vec_f64 ? 8 : 4;
+  int kmax = 0;
+  for (int i = 0; i < count; ++i) kmax = std::max(kmax, n[i]);
+  E.kmax = kmax;
+  std::vector<int64_t> tile_begin(count + 1, 0);
+  for (int i = 0; i < count; ++i) tile_begin[i + 1] = tile_begin[i] + (Bs[i].rows + sh.tile_rows - 1) / sh.tile_rows;
+  const int64_t ntiles = tile_begin[count];
+  std::vector<int32_t> tile_mat(ntiles);
+  std::vector<int64_t> tile_row0(ntiles);
+  for (int i = 0; i < count; ++i)
+    for (int64_t t = tile_begin[i]; t < tile_begin[i + 1]; ++t) {
+      tile_mat[t] = i;
+      tile_row0[t] = (t - tile_begin[i]) * sh.tile_rows;
+    }
+  // device layout
+  Carve c;
+  std::vector<void*> bufA(count), bufB(count);
+  std::vector<size_t> offA(count), offB(count);
+  for (int i = 0; i < count; ++i) {
+    c.take((size_t)Bs[i].rows * M * vb);
+    offA[i] = c.off - (size_t)Bs[i].rows * M * vb;
+    c.take((size_t)Bs[i].rows * M * vb);
+    offB[i] = c.off - (size_t)Bs[i].rows * M * vb;
+  }
+  const int64_t kstride = ntiles * M;
+  c.take((size_t)std::max(kmax, 1) * kstride * 8);
+  const size_t off_part = c.off - (size_t)std::max(kmax, 1) * kstride * 8;
+  c.take((size_t)count * M * (kmax + 1) * 8);
+  const size_t off_mu = c.off - (size_t)count * M * (kmax + 1) * 8;
+  c.take((size_t)std::max(kmax, 1) * count * sizeof(StepDesc));
+  const size_t off_desc = c.off - (size_t)std::max(kmax, 1) * count * sizeof(StepDesc);
+  c.take((size_t)ntiles * 4);
+  const size_t off_tm = c.off - (size_t)ntiles * 4;
+  c.take((size_t)ntiles * 8);
+  const size_t off_tr = c.off - (size_t)ntiles * 8;
+  c.take((size_t)(count + 1) * 8);
+  const size_t off_tb = c.off - (size_t)(count + 1) * 8;
+  c.take((size_t)count * 4);
+  const size_t off_n = c.off - (size_t)count * 4;
+  hipError_t e = hipMalloc(&E.mem, align_up(c.off));
+  if (e != hipSuccess) return fail(LD_ENOMEM, "hipMalloc(%zu) for the batch: %s", align_up(c.off), hipGetErrorString(e));
+  char* base = static_cast<char*>(E.mem);
+  for (int i = 0; i < count; ++i) {
+    bufA[i] = base + offA[i];
+    bufB[i] = base + offB[i];
+  }
+  double* part = reinterpret_cast<double*>(base + off_part);
+  E.mu_dev = reinterpret_cast<double*>(base + off_mu);
+  StepDesc* descs = reinterpret_cast<StepDesc*>(base + off_desc);
+  int32_t* d_tm = reinterpret_cast<int32_t*>(base + off_tm);
+  int64_t* d_tr = reinterpret_cast<int64_t*>(base + off_tr);
+  int64_t* d_tb = reinterpret_cast<int64_t*>(base + off_tb);
+  int* d_n = reinterpret_cast<int*>(base + off_n);
+
+  std::vector<StepDesc> hd((size_t)std::max(kmax, 1) * count);
+  E.coeffs.resize(count);
+  for (int i = 0; i < count; ++i) {
+    E.coeffs[i] = cheb_coeffs(a[i], b[i], n[i]);
+    const double alpha = 4.0 / (b[i] - a[i]);
+    const double beta = -2.0 * (a[i] + b[i]) / (b[i] - a[i]);
+    const double beff = beta + alpha * Bs[i].diag_shift;
+    auto wbuf = [&](int k) -> void* { return k == 0 ? nullptr : ((k & 1) ? bufA[i] : bufB[i]); };
+    for (int k = 0; k < kmax; ++k) {
+      StepDesc& D = hd[(size_t)k * count + i];
+      D = StepDesc{};
+      D.row_ptr = Bs[i].row_ptr;
+      D.col = Bs[i].col_idx;
+      D.val = Bs[i].values;
+      D.seed = seed + (uint64_t)i;
+      D.d = Bs[i].rows;
+      D.active = k < n[i] ? 1 : 0;
+      const double h = k == 0 ? 0.5 : 1.0;
+      D.G = wbuf(k);
+      D.P = k >= 2 ? wbuf(k - 1) : nullptr;
+      D.out = wbuf(k + 1);
+      D.ag = h * alpha;
+      D.bd = h * beff;
+      D.cp = k == 0 ? 0.0 : -1.0;
+      D.mu_part = part + (int64_t)k * kstride + tile_begin[i] * M;
+      D.tile0 = tile_begin[i];
+    }
+  }
+  LD_HIP(hipMemcpy(descs, hd.data(), hd.size() * sizeof(StepDesc), hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(d_tm, tile_mat.data(), tile_mat.size() * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(d_tr, tile_row0.data(), tile_row0.size() * 8, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(d_tb, tile_begin.data(), tile_begin.size() * 8, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(d_n, n, (size_t)count * 4, hipMemcpyHostToDevice));
+
+  // capture every step and the reduction on a private stream
+  hipStream_t cs;
+  LD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  for (int k = 0; k < kmax && err == hipSuccess; ++k) {
+    StepLaunch L{};
+    L.descs = descs + (size_t)k * count;
+    L.nmat = count;
+    L.tile_mat = d_tm;
+    L.tile_row0 = d_tr;
+    L.ntiles = ntiles;
+    L.tile_rows = sh.tile_rows;
+    L.M = M;
+    L.shape = sh;
+    const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
+    const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
+    err = launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, true, cs);
+  }
+  if (err == hipSuccess) err = launch_reduce_batched(part, d_tb, d_n, count, M, kmax, kstride, E.mu_dev, cs);
+  hipError_t e2 = hipStreamEndCapture(cs, &E.graph);
+  (void)hipStreamDestroy(cs);
+  if (err != hipSuccess) return fail_hip(err, "batched step capture");
+  if (e2 != hipSuccess) return fail_hip(e2, "hipStreamEndCapture");
+  LD_HIP(hipGraphInstantiate(&E.exec, E.graph, nullptr, nullptr, 0));
+  return LD_OK;
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+
+extern "C" {
+
+const char* ld_last_error(void) { return g_err.c_str(); }
+
+const char* ld_version(void) { return "logdet_cheb 1.0 (gfx950)"; }
+
+size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) {
+  if (!B || n < 0 || M < 1) return 0;
+  const int valt = valt_of(B->dtype);
+  ld_opts o{};
+  o.vec_f64 = vec_f64 ? 1 : 2;
+  const int v64 = vec_f64_of(&o, valt);
+  if (mode == 2) return grad_workspace(B, n, M, v64, 0);
+  return fwd_workspace(B, n, M, v64, mode == 1, 0);
+}
+
+int ld_logdet_cheb(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
+                   void* stream, ld_result* out) {
+  int rc = check_csr(B, "B");
+  if (rc) return rc;
+  rc = check_common(a, b, n, M);
+  if (rc) return rc;
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  ld_result r{};
+  rc = run_forward(B, nullptr, false, a, b, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
+  if (rc < 0) return rc;
+  *out = r;
+  return rc;
+}
+
+int ld_logabsdet_cheb(const ld_csr* C, const ld_csr* Ct, double smin, double smax, int n, int M, uint64_t seed,
+                      const ld_opts* opt, void* stream, ld_result* out) {
+  int rc = check_csr(C, "C");
+  if (rc) return rc;
+  if (Ct) {
+    rc = check_csr(Ct, "Ct");
+    if (rc) return rc;
+    if (Ct->rows != C->rows || Ct->nnz != C->nnz || Ct->dtype != C->dtype)
+      return fail(LD_EINVAL, "Ct does not match C in size, nnz or dtype");
+  }
+  if (C->diag_shift != 0.0) return fail(LD_EINVAL, "C->diag_shift must be 0 for Algorithm 2");
+  if (!std::isfinite(smin) || !std::isfinite(smax) || !(smin > 0.0) || !(smax > smin))
+    return fail(LD_EINVAL, "singular-value bounds must satisfy 0 < smin < smax; got %g, %g", smin, smax);
+  rc = check_common(smin * smin, smax * smax, n, M);
+  if (rc) return rc;
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  ld_result r{};
+  rc = run_forward(C, Ct, true, smin * smin, smax * smax, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
+  if (rc < 0) return rc;
+  *out = r;
+  return rc;
+}
+
+int ld_gershgorin(const ld_csr* B, double* a, double* b, void* stream) {
+  int rc = check_csr(B, "B");
+  if (rc) return rc;
+  if (!a || !b) return fail(LD_EINVAL, "a or b is NULL");
+  if (B->rows == 0) return fail(LD_EINVAL, "empty matrix has no spectrum");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = (int)std::min<int64_t>(1024, (B->rows + 255) / 256);
+  Workspace ws;
+  rc = get_workspace(nullptr, (size_t)nb * 16, s, ws);
+  if (rc) return rc;
+  double* lo = static_cast<double*>(ws.ptr);
+  double* hi = lo + nb;
+  LD_HIP(launch_gershgorin(B->row_ptr, B->col_idx, B->values, valt_of(B->dtype), B->diag_shift, B->rows, lo, hi, nb,
+                           s));
+  std::vector<double> h(2 * (size_t)nb);
+  LD_HIP(hipMemcpyAsync(h.data(), lo, h.size() * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  double l = INFINITY, u = -INFINITY;
+  for (int i = 0; i < nb; ++i) {
+    l = std::min(l, h[i]);
+    u = std::max(u, h[nb + i]);
+  }
+  *a = l;
+  *b = u;
+  return LD_OK;
+}
+
+int ld_probes(uint64_t seed, int M, int64_t rows, int8_t* out, void* stream) {
+  if (M < 1 || rows < 0 || (!out && rows > 0)) return fail(LD_EINVAL, "invalid probe block arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LD_HIP(launch_probes(seed, M, rows, out, s));
+  LD_HIP(hipStreamSynchronize(s));
+  return LD_OK;
+}
+
+int ld_transpose(const ld_csr* C, int64_t* row_ptr_t, int32_t* col_t, void* val_t, void* stream) {
+  int rc = check_csr(C, "C");
+  if (rc) return rc;
+  if (!row_ptr_t || (C->nnz > 0 && (!col_t || !val_t))) return fail(LD_EINVAL, "NULL output buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  rc = get_workspace(nullptr, align_up((size_t)C->rows * 8) + transpose_scratch_bytes(C->rows), s, ws);
+  if (rc) return rc;
+  int64_t* cursor = static_cast<int64_t*>(ws.ptr);
+  void* scan = static_cast<char*>(ws.ptr) + align_up((size_t)C->rows * 8);
+  LD_HIP(launch_transpose(C->row_ptr, C->col_idx, C->values, valt_of(C->dtype), C->rows, C->nnz, row_ptr_t, col_t,
+                          val_t, cursor, scan, transpose_scratch_bytes(C->rows), s));
+  LD_HIP(hipStreamSynchronize(s));
+  return LD_OK;
+}
+
+int ld_copy(void* dst, const void* src, size_t bytes, void* stream, double* ms) {
+  if ((!dst || !src) && bytes) return fail(LD_EINVAL, "NULL pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  LD_HIP(hipEventCreate(&e0));
+  LD_HIP(hipEventCreate(&e1));
+  LD_HIP(hipEventRecord(e0, s));
+  LD_HIP(launch_copy(dst, src, bytes, s));
+  LD_HIP(hipEventRecord(e1, s));
+  LD_HIP(hipEventSynchronize(e1));
+  float t = 0.f;
+  LD_HIP(hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ms) *ms = t;
+  return LD_OK;
+}
+
+int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, double grad_output,
+                        void* grad_values, int grad_dtype, const ld_opts* opt, void* stream, ld_result* out) {
+  int rc = check_csr(B, "B");
+  if (rc) return rc;
+  rc = check_common(a, b, n, M);
+  if (rc) return rc;
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (grad_dtype != LD_F64 && grad_dtype != LD_F32) return fail(LD_EDTYPE, "grad_dtype must be LD_F64 or LD_F32");
+  if (!grad_values && B->nnz > 0) return fail(LD_EINVAL, "grad_values is NULL");
+  if (!std::isfinite(grad_output)) return fail(LD_EINVAL, "grad_output is not finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int valt = valt_of(B->dtype);
+  const int vec_f64 = vec_f64_of(opt, valt);
+  const int64_t d = B->rows;
+  const size_t vb = vec_f64 ? 8 : 4;
+  Shape sh = with_tile(base_shape(vec_f64, M), d, 0);
+  if (sh.probe_tiles != 1)
+    return fail(LD_EINVAL, "gradient needs M <= %d probes per call with these vectors", (1 << sh.lpr_log2) * sh.vpl);
+  const int64_t ntiles = d > 0 ? (d + sh.tile_rows - 1) / sh.tile_rows : 0;
+  const GradPlan g = plan_grad(n, opt ? opt->ckpt_stride : 0);
+  const size_t need = grad_workspace(B, n, M, vec_f64, opt ? opt->ckpt_stride : 0);
+  Workspace ws;
+  rc = get_workspace(opt, need, s, ws);
+  if (rc) return rc;
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  const size_t vecb = (size_t)d * M * vb;
+  std::vector<void*> slots(g.nslots), seg(g.nseg_buf);
+  for (auto& p : slots) p = cv.take(vecb);
+  for (auto& p : seg) p = cv.take(vecb);
+  void* Ya = cv.take(vecb);
+  void* Yb = cv.take(vecb);
+  void* Gacc = cv.take((size_t)B->nnz * vb);
+  double* gdiag_part = static_cast<double*>(cv.take((size_t)std::max<int64_t>(ntiles, 1) * 8));
+  double* gdiag_tot = static_cast<double*>(cv.take(8));
+  double* part = static_cast<double*>(cv.take((size_t)std::max(n, 1) * ntiles * M * 8));
+  double* mu_dev = static_cast<double*>(cv.take((size_t)M * (n + 1) * 8));
+  const int64_t kstride = ntiles * M;
+
+  const std::vector<double> c = cheb_coeffs(a, b, n);
+  const double alpha = 4.0 / (b - a);
+  const double beta = -2.0 * (a + b) / (b - a);
+  const double beff = beta + alpha * B->diag_shift;
+
+  StepTimer tm;
+  tm.on = opt && opt->timing;
+  tm.s = s;
+  LD_HIP(launch_fill_zero(Gacc, (size_t)B->nnz * vb, s));
+  LD_HIP(launch_fill_zero(gdiag_part, (size_t)std::max<int64_t>(ntiles, 1) * 8, s));
+  LD_HIP(tm.mark(false));
+
+  StepLaunch L{};
+  L.nmat = 1;
+  L.ntiles = ntiles;
+  L.tile_rows = sh.tile_rows;
+  L.M = M;
+  L.shape = sh;
+  auto step = [&](int gsrc, int psrc, bool mu, const void* G, const void* P, void* o, double h, double cp,
+                  double* mp) -> hipError_t {
+    StepDesc D{};
+    D.row_ptr = B->row_ptr;
+    D.col = B->col_idx;
+    D.val = B->values;
+    D.seed = seed;
+    D.d = d;
+    D.active = 1;
+    D.G = G;
+    D.P = P;
+    D.out = o;
+    D.ag = h * alpha;
+    D.bd = h * beff;
+    D.cp = cp;
+    D.mu_part = mp;
+    L.d0 = D;
+    return launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu, s);
+  };
+
+  // forward recurrence with checkpoints: W_k lives in bufW[k] (nullptr = probe hash)
+  std::vector<void*> bufW(n + 2, nullptr);
+  void* R0 = seg[0];
+  void* R1 = seg[1];
+  for (int k = 0; k < n && d > 0; ++k) {
+    void* o;
+    if (g.slot_of[k + 1] >= 0) {
+      o = slots[g.slot_of[k + 1]];
+    } else {
+      void* prev = k >= 1 ? bufW[k - 1] : nullptr;
+      if (prev == R0 || prev == R1)
+        o = prev;
+      else
+        o = (bufW[k] == R0) ? R1 : R0;
+    }
+    const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
+    const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
+    LD_HIP(step(gsrc, psrc, true, bufW[k], k >= 2 ? bufW[k - 1] : nullptr, o, k == 0 ? 0.5 : 1.0,
+                k == 0 ? 0.0 : -1.0, part + (int64_t)k * kstride));
+    LD_HIP(tm.mark(true));
+    bufW[k + 1] = o;
+  }
+  if (n >= 1 && d > 0) LD_HIP(launch_reduce_moments(part, ntiles, M, 1, n, kstride, mu_dev, n + 1, s));
+
+  // backward: y_n = c_n V; y_k = c_k V + 2 At y_{k+1} - y_{k+2}; SDDMM with w_k
+  if (n >= 1 && d > 0) {
+    LD_HIP(launch_fill_probe(Ya, vec_f64, c[n], seed, d, M, s));
+    void* y1 = Ya;       // y_{k+1}
+    void* y2 = nullptr;  // y_{k+2}
+    AdjDesc A{};
+    A.row_ptr = B->row_ptr;
+    A.col = B->col_idx;
+    A.val = B->values;
+    A.Gacc = Gacc;
+    A.gdiag_part = gdiag_part;
+    A.seed = seed;
+    A.d = d;
+    A.ag = alpha;
+    A.bd = beff;
+    A.cp = -1.0;
+    for (int q = g.nseg - 1; q >= 0; --q) {
+      const int k_lo = q * g.s;
+      const int k_hi = std::min((q + 1) * g.s, n) - 1;
+      std::vector<void*> segW(k_hi - k_lo + 1, nullptr);
+      segW[0] = k_lo == 0 ? nullptr : slots[g.slot_of[k_lo]];
+      if (k_hi >= k_lo + 1) segW[1] = slots[g.slot_of[k_lo + 1]];
+      for (int i = 2; i <= k_hi - k_lo; ++i) {
+        const bool p_hash = (k_lo + i - 2) == 0;
+        LD_HIP(step(SRC_BUF, p_hash ? SRC_HASH : SRC_BUF, false, segW[i - 1], p_hash ? nullptr : segW[i - 2],
+                    seg[i - 2], 1.0, -1.0, nullptr));
+        segW[i] = seg[i - 2];
+      }
+      for (int k = k_hi; k >= std::max(k_lo, 1); --k) {
+        void* o = y2 ? y2 : (y1 == Ya ? Yb : Ya);
+        A.Y1 = y1;
+        A.Y2 = y2;
+        A.out = o;
+        A.W = segW[k - k_lo];
+        A.cv = c[k];
+        A.gw = 2.0;
+        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, true, false, y2 != nullptr, s));
+        y2 = y1;
+        y1 = o;
+      }
+      if (k_lo == 0) {
+        // the y_1 w_0^T term, w_0 = v
+        A.Y1 = y1;
+        A.Y2 = nullptr;
+        A.out = nullptr;
+        A.W = nullptr;
+        A.cv = 0.0;
+        A.gw = 1.0;
+        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, false, true, false, s));
+      }
+    }
+  }
+  const double scale = grad_output * (2.0 / (b - a)) / M;
+  if (B->nnz > 0) LD_HIP(launch_scale_grad(Gacc, vec_f64, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
+  double gd = 0.0;
+  if (ntiles > 0) {
+    LD_HIP(launch_sum_doubles(gdiag_part, ntiles, gdiag_tot, s));
+    LD_HIP(hipMemcpyAsync(&gd, gdiag_tot, 8, hipMemcpyDeviceToHost, s));
+  }
+  std::vector<double> mu((size_t)M * (n + 1), 0.0);
+  if (n >= 1 && d > 0) LD_HIP(hipMemcpyAsync(mu.data(), mu_dev, mu.size() * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(tm.mark(false));
+  LD_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < M; ++j) mu[(size_t)j * (n + 1)] = (double)d;
+  ld_result r{};
+  combine(mu, c, n, M, d, 1.0, &r, opt);
+  r.poly_bound = lemma_bound(a, b, n, d);
+  r.grad_shift = scale * gd;
+  tm.report(&r);
+  *out = r;
+  return r.flags ? LD_WBOUNDS : LD_OK;
+}
+
+int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M,
+                           uint64_t seed, const ld_opts* opt, void* stream, ld_result* outs) {
+  if (count < 1 || !Bs || !a || !b || !n || !outs) return fail(LD_EINVAL, "invalid batch arguments");
+  if (M < 1 || M > 4096) return fail(LD_EINVAL, "probe count M=%d out of range [1, 4096]", M);
+  for (int i = 0; i < count; ++i) {
+    char name[32];
+    snprintf(name, sizeof(name), "Bs[%d]", i);
+    int rc = check_csr(&Bs[i], name);
+    if (rc) return rc;
+    rc = check_common(a[i], b[i], n[i], M);
+    if (rc) return rc;
+    if (Bs[i].rows < 1) return fail(LD_EINVAL, "Bs[%d] is empty", i);
+    if (Bs[i].dtype != Bs[0].dtype) return fail(LD_EDTYPE, "all batch matrices must share one dtype");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int valt = valt_of(Bs[0].dtype);
+  const int vec_f64 = vec_f64_of(opt, valt);
+  Shape sh = base_shape(vec_f64, M);
+  const int rpi = rows_per_iter(sh);
+  const int tile = (opt && opt->tile > 0) ? opt->tile : rpi * 16;
+  sh.tile_rows = (tile + rpi - 1) / rpi * rpi;
+
+  std::vector<double> key = {(double)count, (double)M, (double)(seed >> 32), (double)(seed & 0xffffffffu),
+                             (double)vec_f64, (double)sh.tile_rows};
+  for (int i = 0; i < count; ++i) {
+    const double v[] = {bits_of(Bs[i].row_ptr), bits_of(Bs[i].col_idx), bits_of(Bs[i].values), (double)Bs[i].rows,
+                        (double)Bs[i].nnz, (double)Bs[i].dtype, Bs[i].diag_shift, a[i], b[i], (double)n[i]};
+    key.insert(key.end(), v, v + 10);
+  }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto it = g_batch.find(key);
+  BatchEntry* E;
+  if (it == g_batch.end()) {
+    auto ent = std::make_unique<BatchEntry>();
+    int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, sh, *ent);
+    if (rc) return rc;
+    E = ent.get();
+    g_batch[key] = std::move(ent);
+  } else {
+    E = it->second.get();
+  }
+  StepTimer tm;
+  tm.on = opt && opt->timing;
+  tm.s = s;
+  LD_HIP(tm.mark(false));
+  LD_HIP(hipGraphLaunch(E->exec, s));
+  LD_HIP(tm.mark(true));
+  const int kmax = E->kmax;
+  std::vector<double> mu_all((size_t)count * M * (kmax + 1));
+  LD_HIP(hipMemcpyAsync(mu_all.data(), E->mu_dev, mu_all.size() * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  int status = LD_OK;
+  for (int i = 0; i < count; ++i) {
+    std::vector<double> mu((size_t)M * (n[i] + 1));
+    for (int j = 0; j < M; ++j) {
+      mu[(size_t)j * (n[i] + 1)] = (double)Bs[i].rows;
+      for (int k = 1; k <= n[i]; ++k) mu[(size_t)j * (n[i] + 1) + k] = mu_all[((size_t)i * M + j) * (kmax + 1) + k];
+    }
+    ld_result r{};
+    combine(mu, E->coeffs[i], n[i], M, Bs[i].rows, 1.0, &r, nullptr);
+    r.poly_bound = lemma_bound(a[i], b[i], n[i], Bs[i].rows);
+    tm.report(&r);
+    if (tm.on) r.kernel_launches = kmax;
+    outs[i] = r;
+    if (r.flags) status = LD_WBOUNDS;
+  }
+  return status;
+}
+
+int ld_clear_cache(void) {
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    g_batch.clear();
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return LD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal interfaces of liblogdet_cheb: step descriptors, kernel launchers and the host
+// planner's helpers.  Not part of the public C ABI (include/logdet_cheb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ld {
+
+// Where an operand of the fused recurrence step comes from.
+enum Src : int {
+  SRC_NONE = 0,  // operand absent (coefficient treated as 0)
+  SRC_BUF = 1,   // device vector block, d x M row-major (probe index contiguous)
+  SRC_HASH = 2,  // the Rademacher probe block V, regenerated from the counter hash
+  SRC_SAME = 3,  // (diagonal operand only) same as the gathered operand: the diagonal
+                 // coefficient is folded into the matrix entry with col == row
+};
+
+// One matrix's share of one recurrence step:
+//   out[r, :] = ag * sum_t val[t] * G[col[t], :] + bd * D[r, :] + cp * P[r, :] + cv * V[r, :]
+// for every row r, plus (optionally) per-tile partial sums of V[r, p] * out[r, p].
+// `out` may alias `P` (in-place update); it never aliases G or D.
+struct StepDesc {
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const void* val;
+  const void* G;
+  const void* D;
+  const void* P;
+  void* out;
+  double ag, bd, cp, cv;
+  uint64_t seed;
+  int64_t d;
+  double* mu_part;  // [tiles of this matrix][M] doubles for this degree, or nullptr
+  int64_t tile0;    // global index of this matrix's first tile
+  int32_t active;   // 0: skip this matrix at this step
+  int32_t pad_;
+};
+
+// Kernel shape chosen by the planner (or the autotuner).
+struct Shape {
+  int vpl;          // vector elements per lane (1, 2 or 4; divides M)
+  int lpr_log2;     // log2 lanes per row (LPR * vpl >= min(M, 64 * vpl))
+  int tile_rows;    // rows per workgroup tile (multiple of 4 * (64 / LPR))
+  int probe_tiles;  // gridDim.y: ceil(M / (LPR * vpl))
+};
+
+// Launch configuration for a whole step over a tile list.
+struct StepLaunch {
+  StepDesc d0;              // the matrix when descs == nullptr (single-matrix launches)
+  const StepDesc* descs;    // device array, one per matrix, or nullptr
+  int nmat;
+  const int32_t* tile_mat;  // device [ntiles] matrix of each tile, or nullptr (single matrix)
+  const int64_t* tile_row0; // device [ntiles] first row of each tile, or nullptr
+  int64_t ntiles;
+  int64_t tile_rows;
+  int M;
+  Shape shape;
+};
+
+// Value type tags
+enum ValT : int { VAL_F64 = 0, VAL_F32 = 1, VAL_BF16 = 2 };
+
+// Launch one fused step.  gsrc/dsrc/psrc select the operand sources (uniform across
+// matrices), mu selects the probe-moment epilogue.  Returns a hipError_t.
+hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, bool mu,
+                       hipStream_t s);
+
+// Adjoint step (gradient): for row r with y1 = Y_{k+1}:
+//   if spmm: out[r,:] = cv * V[r,:] + ag * sum_t val[t] y1[col[t],:] + bd * y1[r,:] + cp * Y2[r,:]
+//   G[t] += gw * sum_p y1[r,p] * W[col[t],p]    (SDDMM on the pattern of the matrix)
+//   gdiag_part[tile] += gw * sum_p y1[r,p] * W[r,p]
+struct AdjDesc {
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const void* val;
+  const void* Y1;  // y_{k+1}
+  const void* Y2;  // y_{k+2} (or nullptr)
+  void* out;       // y_k (may alias Y2), or nullptr when spmm is off
+  const void* W;   // w_k (nullptr => probe hash, k = 0)
+  void* Gacc;      // nnz accumulators (float for FP32 vectors, double for FP64)
+  double* gdiag_part;  // [tiles] doubles
+  double ag, bd, cp, cv, gw;
+  uint64_t seed;
+  int64_t d;
+};
+
+hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64, int valt, bool spmm,
+                          bool w_hash, bool y2, hipStream_t s);
+
+// Deterministic reduction of per-tile partials:
+// mu[j * ldmu + k] = sum_{t < ntiles} part[k][t][j] for k in [k_lo, k_hi].
+// part is laid out as part + (k - k_lo) * kstride + t * M + j.
+hipError_t launch_reduce_moments(const double* part, int64_t ntiles, int M, int k_lo, int k_hi, int64_t kstride,
+                                 double* mu, int ldmu, hipStream_t s);
+
+// Batched reduction: for matrix i, tiles [tile_begin[i], tile_begin[i+1]) of degree k (k <= n[i])
+// into mu[i][j][k].  part[(k-1) * kstride + tile * M + j].
+hipError_t launch_reduce_batched(const double* part, const int64_t* tile_begin, const int* n, int count, int M,
+                                 int kmax, int64_t kstride, double* mu, hipStream_t s);
+
+hipError_t launch_sum_doubles(const double* x, int64_t n, double* out, hipStream_t s);
+
+hipError_t launch_gershgorin(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, double shift,
+                             int64_t d, double* lo_part, double* hi_part, int nblocks, hipStream_t s);
+
+hipError_t launch_probes(uint64_t seed, int M, int64_t rows, int8_t* out, hipStream_t s);
+
+hipError_t launch_transpose(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, int64_t d,
+                            int64_t nnz, int64_t* row_ptr_t, int32_t* col_t, void* val_t, int64_t* cursor,
+                            void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
+size_t transpose_scratch_bytes(int64_t d);
+
+hipError_t launch_scale_grad(const void* Gacc, int acc_f64, int64_t nnz, double scale, void* out, int out_f64,
+                             hipStream_t s);
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// out[r, j] = c * v_j[r] (the adjoint's starting vector y_n = c_n V)
+hipError_t launch_fill_probe(void* out, int vec_f64, double c, uint64_t seed, int64_t d, int M, hipStream_t s);
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace ld

@@ -1,0 +1,929 @@
+// HIP kernels for gfx950 (CDNA4) of the stochastic Chebyshev log-determinant estimator
+// (Han, Malioutov & Shin, arXiv 1503.06394).
+//
+// The hot loop is the three-term recurrence W_{k+1} = 2 At W_k - W_{k-1} (Section 2.2,
+// eq. (2)) over a block of M Rademacher probes: a sparse-matrix x dense-block product
+// whose arithmetic intensity (about 1-2 flop/byte) puts it far below the MFMA and even
+// the FP32-vector ridge points, so nothing here uses matrix cores.  Design points:
+//  * Vector blocks are d x M row-major (probe index contiguous): the LPR lanes of a row
+//    group read a whole row of W_k (M * 4 bytes) as VPL-wide vector loads, so every
+//    gathered row is one fully coalesced segment.
+//  * A row's column indices and values are loaded once, cooperatively, by the LPR lanes
+//    of its group and broadcast with cross-lane shuffles.
+//  * The diagonal term of 2 At = alpha B + beta I is folded into the coefficient of the
+//    stored diagonal entry, so W_k[r] is not read twice.
+//  * Probes are never stored: v_j[r] is regenerated from a SplitMix64 counter hash.
+//  * The probe moments v_j^T W_{k+1} are fused into the step's epilogue: FP64 per-lane
+//    sums, a wave butterfly, a fixed-order sum over waves and one partial per tile, later
+//    reduced in a fixed order (deterministic, no floating-point atomics).
+//  * One workgroup per row tile; workgroup ids are remapped so that each of the eight
+//    XCDs walks a contiguous range of tiles in order, which keeps the W_k rows that
+//    banded patterns reuse (neighbours at +-N, +-N^2) inside that XCD's L2.
+#include <type_traits>
+
+#include "ld_internal.h"
+
+namespace ld {
+
+// ------------------------------------------------------------------------------------
+// small device helpers
+// ------------------------------------------------------------------------------------
+
+// SplitMix64 output function at generator state seed + (ctr + 1) * gamma, with
+// ctr = (row << 16) | (probe >> 6); bit (probe & 63) is the probe's sign bit.
+__device__ __forceinline__ uint64_t probe_word(uint64_t seed, uint64_t row, uint32_t blk) {
+  uint64_t ctr = (row << 16) | (uint64_t)blk;
+  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename VT, int N>
+__device__ __forceinline__ void probe_signs(uint64_t seed, int64_t row, int p0, VT* r) {
+  const uint64_t w = probe_word(seed, (uint64_t)row, (uint32_t)(p0 >> 6));
+  const uint32_t bits = (uint32_t)(w >> (p0 & 63));
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = ((bits >> i) & 1u) ? VT(-1) : VT(1);
+}
+
+template <int VALT>
+struct Val;
+template <>
+struct Val<VAL_F64> {
+  typedef double T;
+  __device__ static double get(const void* p, int64_t t) { return static_cast<const double*>(p)[t]; }
+};
+template <>
+struct Val<VAL_F32> {
+  typedef float T;
+  __device__ static float get(const void* p, int64_t t) { return static_cast<const float*>(p)[t]; }
+};
+template <>
+struct Val<VAL_BF16> {
+  typedef float T;
+  __device__ static float get(const void* p, int64_t t) {
+    const uint32_t u = static_cast<const uint16_t*>(p)[t];
+    return __uint_as_float(u << 16);
+  }
+};
+
+template <typename VT, int N>
+__device__ __forceinline__ void vload(const VT* p, VT* r) {
+  if constexpr (N == 1) {
+    r[0] = p[0];
+  } else {
+    typedef VT vec_t __attribute__((ext_vector_type(N)));
+    const vec_t x = *reinterpret_cast<const vec_t*>(p);
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = x[i];
+  }
+}
+
+template <typename VT, int N>
+__device__ __forceinline__ void vstore(VT* p, const VT* r) {
+  if constexpr (N == 1) {
+    p[0] = r[0];
+  } else {
+    typedef VT vec_t __attribute__((ext_vector_type(N)));
+    vec_t x;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = r[i];
+    *reinterpret_cast<vec_t*>(p) = x;
+  }
+}
+
+// Physical workgroup id -> logical tile: XCD x (= id mod 8) walks tiles
+// [x * per, (x + 1) * per) in dispatch order.
+__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
+  const int64_t per = (ntiles + 7) >> 3;
+  const int64_t b = blockIdx.x;
+  return (b & 7) * per + (b >> 3);
+}
+
+constexpr int kBlock = 256;  // 4 waves of 64
+constexpr int kWaves = kBlock / 64;
+
+// ------------------------------------------------------------------------------------
+// fused recurrence step
+// ------------------------------------------------------------------------------------
+
+template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, bool MU>
+__global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
+  typedef typename Val<VALT>::T MV;
+  const int64_t tile = xcd_tile(L.ntiles);
+  if (tile >= L.ntiles) return;
+  const int mat = L.tile_mat ? L.tile_mat[tile] : 0;
+  const StepDesc& D = L.descs ? L.descs[mat] : L.d0;
+  if (!D.active) return;
+  const int64_t row0 = L.tile_row0 ? L.tile_row0[tile] : tile * L.tile_rows;
+  const int64_t row_end = min(D.d, row0 + L.tile_rows);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lg = L.shape.lpr_log2;
+  const int LPR = 1 << lg;
+  const int RPW = 64 >> lg;
+  const int sub = lane & (LPR - 1);
+  const int grp = lane >> lg;
+  const int gbase = lane & ~(LPR - 1);
+  const int M = L.M;
+  const int tile_probes = LPR * VPL;
+  int p0 = (int)blockIdx.y * tile_probes + sub * VPL;
+  const bool pact = p0 < M;
+  if (!pact) p0 = 0;  // keep addresses valid; results of these lanes are discarded
+
+  const VT ag = (VT)D.ag, bd = (VT)D.bd, cp = (VT)D.cp;
+  const VT* __restrict__ G = static_cast<const VT*>(D.G);
+  const VT* __restrict__ Dv = static_cast<const VT*>(D.D);
+  const VT* P = static_cast<const VT*>(D.P);
+  VT* out = static_cast<VT*>(D.out);
+  const int64_t* __restrict__ rp = D.row_ptr;
+  const int32_t* __restrict__ ci = D.col;
+
+  double mu[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) mu[i] = 0.0;
+
+  for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
+    const int64_t row = base + grp;
+    const bool has = row < row_end;
+    int64_t s = 0, e = 0;
+    if (has) {
+      s = rp[row];
+      e = rp[row + 1];
+    }
+    VT acc[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
+    bool hd = false;
+
+    if (LPR >= 4) {
+      // cooperative: lane `sub` of the group loads entry cb + sub of the row
+      for (int64_t cb = s; cb < e; cb += LPR) {
+        const int64_t t = cb + sub;
+        int cl = 0;
+        MV vl = MV(0);
+        if (t < e) {
+          cl = ci[t];
+          vl = Val<VALT>::get(D.val, t);
+        }
+        const int cnt = (int)min((int64_t)LPR, e - cb);
+        for (int q = 0; q < cnt; q += 4) {
+          int cc[4];
+          VT aa[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const bool ok = q + u < cnt;
+            const int srcl = gbase + (ok ? q + u : 0);
+            const int cu = __shfl(cl, srcl, 64);
+            const MV vu = __shfl(vl, srcl, 64);
+            VT a = ok ? ag * (VT)vu : VT(0);
+            if constexpr (DSRC == SRC_SAME) {
+              if (ok && cu == row) {
+                a += bd;
+                hd = true;
+              }
+            }
+            aa[u] = a;
+            cc[u] = ok ? cu : (int)row;
+          }
+          VT gg[4][VPL];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if constexpr (GSRC == SRC_BUF)
+              vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
+            else
+              probe_signs<VT, VPL>(D.seed, cc[u], p0, gg[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
+        }
+      }
+    } else {
+      // narrow groups: every lane reads the row's entries itself
+      for (int64_t t = s; t < e; t += 4) {
+        int cc[4];
+        VT aa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = t + u < e;
+          const int cu = ok ? ci[t + u] : (int)row;
+          VT a = ok ? ag * (VT)Val<VALT>::get(D.val, t + u) : VT(0);
+          if constexpr (DSRC == SRC_SAME) {
+            if (ok && cu == row) {
+              a += bd;
+              hd = true;
+            }
+          }
+          aa[u] = a;
+          cc[u] = cu;
+        }
+        VT gg[4][VPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if constexpr (GSRC == SRC_BUF)
+            vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
+          else
+            probe_signs<VT, VPL>(D.seed, cc[u], p0, gg[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
+      }
+    }
+
+    if (has) {
+      const int64_t off = row * (int64_t)M + p0;
+      if constexpr (DSRC == SRC_SAME) {
+        if (!hd) {  // pattern without a stored diagonal in this row
+          VT dv[VPL];
+          if constexpr (GSRC == SRC_BUF)
+            vload<VT, VPL>(G + off, dv);
+          else
+            probe_signs<VT, VPL>(D.seed, row, p0, dv);
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
+        }
+      } else if constexpr (DSRC == SRC_BUF) {
+        VT dv[VPL];
+        vload<VT, VPL>(Dv + off, dv);
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
+      } else if constexpr (DSRC == SRC_HASH) {
+        VT dv[VPL];
+        probe_signs<VT, VPL>(D.seed, row, p0, dv);
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
+      }
+      if constexpr (PSRC == SRC_BUF) {
+        VT pv[VPL];
+        vload<VT, VPL>(P + off, pv);
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
+      } else if constexpr (PSRC == SRC_HASH) {
+        VT pv[VPL];
+        probe_signs<VT, VPL>(D.seed, row, p0, pv);
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
+      }
+      if (pact) {
+        vstore<VT, VPL>(out + off, acc);
+        if constexpr (MU) {
+          const uint64_t w = probe_word(D.seed, (uint64_t)row, (uint32_t)(p0 >> 6));
+          const uint32_t bits = (uint32_t)(w >> (p0 & 63));
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) {
+            const double x = (double)acc[i];
+            mu[i] += ((bits >> i) & 1u) ? -x : x;
+          }
+        }
+      }
+    }
+  }
+
+  if constexpr (MU) {
+    __shared__ double smu[kWaves][256];
+    for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) mu[i] += __shfl_xor(mu[i], o, 64);
+    if (grp == 0)
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) smu[wave][sub * VPL + i] = mu[i];
+    __syncthreads();
+    double* dst = D.mu_part + (tile - D.tile0) * (int64_t)M;
+    for (int j = threadIdx.x; j < tile_probes; j += kBlock) {
+      const int pj = (int)blockIdx.y * tile_probes + j;
+      if (pj < M) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) sum += smu[w][j];
+        dst[pj] = sum;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// adjoint step (gradient): Clenshaw-type backward recurrence fused with the SDDMM
+// ------------------------------------------------------------------------------------
+
+template <typename VT, int VALT, int VPL, bool SPMM, bool WHASH, bool Y2>
+__global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows,
+                                                         int64_t ntiles) {
+  typedef typename Val<VALT>::T MV;
+  const int64_t tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int64_t row0 = tile * tile_rows;
+  const int64_t row_end = min(A.d, row0 + tile_rows);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int LPR = 1 << lpr_log2;
+  const int RPW = 64 >> lpr_log2;
+  const int sub = lane & (LPR - 1);
+  const int grp = lane >> lpr_log2;
+  const int gbase = lane & ~(LPR - 1);
+  int p0 = sub * VPL;
+  const bool pact = p0 < M;
+  if (!pact) p0 = 0;
+
+  const VT ag = (VT)A.ag, bd = (VT)A.bd, cp = (VT)A.cp, cv = (VT)A.cv, gw = (VT)A.gw;
+  const VT* __restrict__ Y1 = static_cast<const VT*>(A.Y1);
+  const VT* Y2p = static_cast<const VT*>(A.Y2);
+  VT* out = static_cast<VT*>(A.out);
+  const VT* __restrict__ W = static_cast<const VT*>(A.W);
+  VT* __restrict__ Gacc = static_cast<VT*>(A.Gacc);
+  const int64_t* __restrict__ rp = A.row_ptr;
+  const int32_t* __restrict__ ci = A.col;
+
+  double gdiag = 0.0;
+  for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
+    const int64_t row = base + grp;
+    const bool has = row < row_end;
+    int64_t s = 0, e = 0;
+    if (has) {
+      s = rp[row];
+      e = rp[row + 1];
+    }
+    const int64_t roff = (has ? row : row0) * (int64_t)M + p0;
+    VT yown[VPL];
+    vload<VT, VPL>(Y1 + roff, yown);
+    if (!pact || !has)
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) yown[i] = VT(0);
+    VT acc[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
+    bool hd = false;
+    VT wdiag[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) wdiag[i] = VT(0);
+
+    for (int64_t cb = s; cb < e; cb += LPR) {
+      const int64_t t = cb + sub;
+      int cl = 0;
+      MV vl = MV(0);
+      if (t < e) {
+        cl = ci[t];
+        vl = Val<VALT>::get(A.val, t);
+      }
+      const int cnt = (int)min((int64_t)LPR, e - cb);
+      for (int q = 0; q < cnt; ++q) {
+        const int srcl = gbase + q;
+        const int cu = __shfl(cl, srcl, 64);
+        const MV vu = __shfl(vl, srcl, 64);
+        VT wv[VPL];
+        if constexpr (WHASH)
+          probe_signs<VT, VPL>(A.seed, cu, p0, wv);
+        else
+          vload<VT, VPL>(W + (int64_t)cu * M + p0, wv);
+        if constexpr (SPMM) {
+          VT yv[VPL];
+          vload<VT, VPL>(Y1 + (int64_t)cu * M + p0, yv);
+          const VT a = ag * (VT)vu;
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(a, yv[i], acc[i]);
+        }
+        VT dp = VT(0);
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) dp = fma(yown[i], wv[i], dp);
+        for (int o = 1; o < LPR; o <<= 1) dp += __shfl_xor(dp, o, 64);
+        if (cu == row) {
+          hd = true;
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) wdiag[i] = wv[i];
+        }
+        if (sub == 0) Gacc[cb + q] += gw * dp;
+      }
+    }
+    if (has) {
+      if (!hd) {
+        if constexpr (WHASH)
+          probe_signs<VT, VPL>(A.seed, row, p0, wdiag);
+        else
+          vload<VT, VPL>(W + roff, wdiag);
+      }
+      double dd = 0.0;
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) dd += (double)yown[i] * (double)wdiag[i];
+      gdiag += (double)A.gw * dd;
+      if constexpr (SPMM) {
+        VT vv[VPL];
+        probe_signs<VT, VPL>(A.seed, row, p0, vv);
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+          VT o = fma(bd, yown[i], acc[i]);
+          o = fma(cv, vv[i], o);
+          acc[i] = o;
+        }
+        if constexpr (Y2) {
+          VT y2v[VPL];
+          vload<VT, VPL>(Y2p + roff, y2v);
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, y2v[i], acc[i]);
+        }
+        if (pact) vstore<VT, VPL>(out + roff, acc);
+      }
+    }
+  }
+  // tile partial of the diagonal term (fixed-order block reduction)
+  __shared__ double sg[kWaves];
+  for (int o = 1; o < 64; o <<= 1) gdiag += __shfl_xor(gdiag, o, 64);
+  if (lane == 0) sg[wave] = gdiag;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < kWaves; ++w) sum += sg[w];
+    A.gdiag_part[tile] += sum;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// reductions and utilities
+// ------------------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(1024) reduce_moments_kernel(const double* part, int64_t ntiles, int M, int k_lo,
+                                                              int64_t kstride, double* mu, int ldmu) {
+  const int k = k_lo + blockIdx.x;
+  const int j = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;  // 16 slices over tiles
+  double s = 0.0;
+  if (j < M) {
+    const double* p = part + (int64_t)blockIdx.x * kstride + j;
+    for (int64_t t = q; t < ntiles; t += 16) s += p[t * M];
+  }
+  __shared__ double sh[16][64];
+  sh[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q == 0 && j < M) {
+    double sum = 0.0;
+    for (int r = 0; r < 16; ++r) sum += sh[r][threadIdx.x & 63];
+    mu[(int64_t)j * ldmu + k] = sum;
+  }
+}
+
+__global__ void __launch_bounds__(1024) reduce_batched_kernel(const double* part, const int64_t* tile_begin,
+                                                              const int* nvec, int M, int64_t kstride, double* mu,
+                                                              int kmax) {
+  const int i = blockIdx.x;        // matrix
+  const int k = 1 + blockIdx.y;    // degree
+  const int j = blockIdx.z * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  if (k > nvec[i]) return;
+  double s = 0.0;
+  if (j < M) {
+    const double* p = part + (int64_t)(k - 1) * kstride + j;
+    for (int64_t t = tile_begin[i] + q; t < tile_begin[i + 1]; t += 16) s += p[t * M];
+  }
+  __shared__ double sh[16][64];
+  sh[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q == 0 && j < M) {
+    double sum = 0.0;
+    for (int r = 0; r < 16; ++r) sum += sh[r][threadIdx.x & 63];
+    mu[((int64_t)i * M + j) * (kmax + 1) + k] = sum;
+  }
+}
+
+__global__ void __launch_bounds__(1024) sum_doubles_kernel(const double* x, int64_t n, double* out) {
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += 1024) s += x[t];
+  __shared__ double sh[1024];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+template <int VALT>
+__global__ void __launch_bounds__(256) gershgorin_kernel(const int64_t* row_ptr, const int32_t* col, const void* val,
+                                                         double shift, int64_t d, double* lo_part, double* hi_part) {
+  double lo = __builtin_inf(), hi = -__builtin_inf();
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
+    double diag = 0.0, off = 0.0;
+    for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t) {
+      const double v = (double)Val<VALT>::get(val, t);
+      if (col[t] == r)
+        diag += v;
+      else
+        off += fabs(v);
+    }
+    diag += shift;
+    lo = fmin(lo, diag - off);
+    hi = fmax(hi, diag + off);
+  }
+  __shared__ double sl[256], sh[256];
+  sl[threadIdx.x] = lo;
+  sh[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + w]);
+      sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    lo_part[blockIdx.x] = sl[0];
+    hi_part[blockIdx.x] = sh[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) probes_kernel(uint64_t seed, int M, int64_t rows, int8_t* out) {
+  const int64_t total = rows * (int64_t)M;
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
+    const int64_t r = x / M;
+    const int j = (int)(x - r * M);
+    const uint64_t w = probe_word(seed, (uint64_t)r, (uint32_t)(j >> 6));
+    out[x] = ((w >> (j & 63)) & 1u) ? (int8_t)-1 : (int8_t)1;
+  }
+}
+
+// --- transpose (setup for Algorithm 2) ---
+
+__global__ void __launch_bounds__(256) count_cols_kernel(const int32_t* col, int64_t nnz, int64_t* cnt) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * 256)
+    atomicAdd(reinterpret_cast<unsigned long long*>(cnt + col[t]), 1ull);
+}
+
+// exclusive scan in three passes: block sums, scan of block sums (one block), add-back
+constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 8;  // per thread
+constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanItems;
+
+__device__ int64_t block_exclusive_scan(int64_t x, int64_t* sh, int64_t* total) {
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int64_t y = ((int)threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += y;
+    __syncthreads();
+  }
+  const int64_t incl = sh[threadIdx.x];
+  *total = sh[kScanBlock - 1];
+  __syncthreads();
+  return incl - x;
+}
+
+__global__ void __launch_bounds__(kScanBlock) scan_tiles_kernel(const int64_t* in, int64_t n, int64_t* out,
+                                                                int64_t* tile_sums) {
+  __shared__ int64_t sh[kScanBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t local = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    local += v[i];
+  }
+  int64_t total;
+  int64_t run = block_exclusive_scan(local, sh, &total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) scan_sums_kernel(int64_t* sums, int64_t nt) {
+  __shared__ int64_t sh[kScanBlock];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nt; base += kScanBlock) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t x = i < nt ? sums[i] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(x, sh, &total);
+    if (i < nt) sums[i] = carry + ex;
+    carry += total;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) scan_add_kernel(int64_t* out, int64_t n, const int64_t* sums) {
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256)
+    out[x] += sums[x / kScanTile];
+}
+
+template <int VALT>
+__global__ void __launch_bounds__(256) scatter_t_kernel(const int64_t* row_ptr, const int32_t* col, const void* val,
+                                                        int64_t d, int64_t* cursor, int32_t* col_t, void* val_t) {
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
+    for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t) {
+      const int c = col[t];
+      const int64_t pos = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(cursor + c), 1ull);
+      col_t[pos] = (int32_t)r;
+      if constexpr (VALT == VAL_F64)
+        static_cast<double*>(val_t)[pos] = static_cast<const double*>(val)[t];
+      else if constexpr (VALT == VAL_F32)
+        static_cast<float*>(val_t)[pos] = static_cast<const float*>(val)[t];
+      else
+        static_cast<uint16_t*>(val_t)[pos] = static_cast<const uint16_t*>(val)[t];
+    }
+  }
+}
+
+template <int VALT>
+__global__ void __launch_bounds__(256) sort_rows_kernel(const int64_t* row_ptr, int64_t d, int32_t* col, void* val) {
+  typedef typename std::conditional<VALT == VAL_F64, double,
+                                    typename std::conditional<VALT == VAL_F32, float, uint16_t>::type>::type T;
+  T* v = static_cast<T*>(val);
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
+    const int64_t s = row_ptr[r], e = row_ptr[r + 1];
+    for (int64_t i = s + 1; i < e; ++i) {  // insertion sort: rows are short
+      const int32_t kc = col[i];
+      const T kv = v[i];
+      int64_t j = i - 1;
+      while (j >= s && col[j] > kc) {
+        col[j + 1] = col[j];
+        v[j + 1] = v[j];
+        --j;
+      }
+      col[j + 1] = kc;
+      v[j + 1] = kv;
+    }
+  }
+}
+
+template <typename TA, typename TO>
+__global__ void __launch_bounds__(256) scale_kernel(const TA* a, int64_t n, double scale, TO* out) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256)
+    out[t] = (TO)((double)a[t] * scale);
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256) fill_probe_kernel(VT* out, double c, uint64_t seed, int64_t d, int M) {
+  const int64_t total = d * (int64_t)M;
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
+    const int64_t r = x / M;
+    const int j = (int)(x - r * M);
+    const uint64_t w = probe_word(seed, (uint64_t)r, (uint32_t)(j >> 6));
+    out[x] = (VT)(((w >> (j & 63)) & 1u) ? -c : c);
+  }
+}
+
+__global__ void __launch_bounds__(256) copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n16; t += (int64_t)gridDim.x * 256) dst[t] = src[t];
+}
+
+__global__ void __launch_bounds__(256) copy_tail_kernel(const uint8_t* src, uint8_t* dst, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) dst[t] = src[t];
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(uint4* p, int64_t n16) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n16; t += (int64_t)gridDim.x * 256)
+    p[t] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) zero_tail_kernel(uint8_t* p, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) p[t] = 0;
+}
+
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+
+static unsigned grid_for(int64_t work, int per_block, unsigned cap = 65536u) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, bool MU>
+static hipError_t go_step(const StepLaunch& L, hipStream_t s) {
+  const int64_t per = (L.ntiles + 7) / 8;
+  dim3 grid((unsigned)(per * 8), (unsigned)L.shape.probe_tiles);
+  hipLaunchKernelGGL((step_kernel<VT, VALT, VPL, GSRC, DSRC, PSRC, MU>), grid, dim3(kBlock), 0, s, L);
+  return hipGetLastError();
+}
+
+template <typename VT, int VALT, int VPL>
+static hipError_t step_by_src(const StepLaunch& L, int g, int d, int p, bool mu, hipStream_t s) {
+#define LD_CASE(G_, D_, P_, MU_) \
+  if (g == G_ && d == D_ && p == P_ && mu == MU_) return go_step<VT, VALT, VPL, G_, D_, P_, MU_>(L, s);
+  // Algorithm 1 forward: k = 0, k = 1, k >= 2 (also used for recomputation without moments)
+  LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, true)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, true)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, true)
+  LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, false)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, false)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, false)
+  // Algorithm 2: T = C X, then W_{k+1} = alpha C^T T + beta W_k - W_{k-1}
+  LD_CASE(SRC_HASH, SRC_NONE, SRC_NONE, false)
+  LD_CASE(SRC_BUF, SRC_NONE, SRC_NONE, false)
+  LD_CASE(SRC_BUF, SRC_HASH, SRC_NONE, true)
+  LD_CASE(SRC_BUF, SRC_BUF, SRC_HASH, true)
+  LD_CASE(SRC_BUF, SRC_BUF, SRC_BUF, true)
+#undef LD_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename VT, int VALT>
+static hipError_t step_by_vpl(const StepLaunch& L, int g, int d, int p, bool mu, hipStream_t s) {
+  switch (L.shape.vpl) {
+    case 1: return step_by_src<VT, VALT, 1>(L, g, d, p, mu, s);
+    case 2: return step_by_src<VT, VALT, 2>(L, g, d, p, mu, s);
+    case 4:
+      if constexpr (sizeof(VT) == 4) return step_by_src<VT, VALT, 4>(L, g, d, p, mu, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, bool mu,
+                       hipStream_t s) {
+  if (L.ntiles <= 0) return hipSuccess;
+  if (vec_f64) {
+    if (valt == VAL_F64) return step_by_vpl<double, VAL_F64>(L, gsrc, dsrc, psrc, mu, s);
+    if (valt == VAL_F32) return step_by_vpl<double, VAL_F32>(L, gsrc, dsrc, psrc, mu, s);
+    if (valt == VAL_BF16) return step_by_vpl<double, VAL_BF16>(L, gsrc, dsrc, psrc, mu, s);
+  } else {
+    if (valt == VAL_F64) return step_by_vpl<float, VAL_F64>(L, gsrc, dsrc, psrc, mu, s);
+    if (valt == VAL_F32) return step_by_vpl<float, VAL_F32>(L, gsrc, dsrc, psrc, mu, s);
+    if (valt == VAL_BF16) return step_by_vpl<float, VAL_BF16>(L, gsrc, dsrc, psrc, mu, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename VT, int VALT, int VPL>
+static hipError_t adj_by_flags(const AdjDesc& A, int M, const Shape& sh, bool spmm, bool wh, bool y2, hipStream_t s) {
+  const int64_t ntiles = (A.d + sh.tile_rows - 1) / sh.tile_rows;
+  const int64_t per = (ntiles + 7) / 8;
+  dim3 grid((unsigned)(per * 8));
+#define LD_ADJ(S_, W_, Y_)                                                                                        \
+  if (spmm == S_ && wh == W_ && y2 == Y_) {                                                                      \
+    hipLaunchKernelGGL((adjoint_kernel<VT, VALT, VPL, S_, W_, Y_>), grid, dim3(kBlock), 0, s, A, M, sh.lpr_log2, \
+                       (int64_t)sh.tile_rows, ntiles);                                                          \
+    return hipGetLastError();                                                                                   \
+  }
+  LD_ADJ(true, false, true)
+  LD_ADJ(true, false, false)
+  LD_ADJ(false, true, false)
+#undef LD_ADJ
+  return hipErrorInvalidValue;
+}
+
+template <typename VT, int VALT>
+static hipError_t adj_by_vpl(const AdjDesc& A, int M, const Shape& sh, bool spmm, bool wh, bool y2, hipStream_t s) {
+  switch (sh.vpl) {
+    case 1: return adj_by_flags<VT, VALT, 1>(A, M, sh, spmm, wh, y2, s);
+    case 2: return adj_by_flags<VT, VALT, 2>(A, M, sh, spmm, wh, y2, s);
+    case 4:
+      if constexpr (sizeof(VT) == 4) return adj_by_flags<VT, VALT, 4>(A, M, sh, spmm, wh, y2, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64, int valt, bool spmm, bool w_hash,
+                          bool y2, hipStream_t s) {
+  if (A.d <= 0) return hipSuccess;
+  if (vec_f64) {
+    if (valt == VAL_F64) return adj_by_vpl<double, VAL_F64>(A, M, sh, spmm, w_hash, y2, s);
+    if (valt == VAL_F32) return adj_by_vpl<double, VAL_F32>(A, M, sh, spmm, w_hash, y2, s);
+    if (valt == VAL_BF16) return adj_by_vpl<double, VAL_BF16>(A, M, sh, spmm, w_hash, y2, s);
+  } else {
+    if (valt == VAL_F64) return adj_by_vpl<float, VAL_F64>(A, M, sh, spmm, w_hash, y2, s);
+    if (valt == VAL_F32) return adj_by_vpl<float, VAL_F32>(A, M, sh, spmm, w_hash, y2, s);
+    if (valt == VAL_BF16) return adj_by_vpl<float, VAL_BF16>(A, M, sh, spmm, w_hash, y2, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_moments(const double* part, int64_t ntiles, int M, int k_lo, int k_hi, int64_t kstride,
+                                 double* mu, int ldmu, hipStream_t s) {
+  if (k_hi < k_lo) return hipSuccess;
+  dim3 grid((unsigned)(k_hi - k_lo + 1), (unsigned)((M + 63) / 64));
+  hipLaunchKernelGGL(reduce_moments_kernel, grid, dim3(1024), 0, s, part, ntiles, M, k_lo, kstride, mu, ldmu);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_batched(const double* part, const int64_t* tile_begin, const int* n, int count, int M,
+                                 int kmax, int64_t kstride, double* mu, hipStream_t s) {
+  if (count <= 0 || kmax < 1) return hipSuccess;
+  dim3 grid((unsigned)count, (unsigned)kmax, (unsigned)((M + 63) / 64));
+  hipLaunchKernelGGL(reduce_batched_kernel, grid, dim3(1024), 0, s, part, tile_begin, n, M, kstride, mu, kmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_doubles(const double* x, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_doubles_kernel, dim3(1), dim3(1024), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gershgorin(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, double shift,
+                             int64_t d, double* lo_part, double* hi_part, int nblocks, hipStream_t s) {
+  dim3 grid((unsigned)nblocks);
+  if (valt == VAL_F64)
+    hipLaunchKernelGGL(gershgorin_kernel<VAL_F64>, grid, dim3(256), 0, s, row_ptr, col, val, shift, d, lo_part, hi_part);
+  else if (valt == VAL_F32)
+    hipLaunchKernelGGL(gershgorin_kernel<VAL_F32>, grid, dim3(256), 0, s, row_ptr, col, val, shift, d, lo_part, hi_part);
+  else
+    hipLaunchKernelGGL(gershgorin_kernel<VAL_BF16>, grid, dim3(256), 0, s, row_ptr, col, val, shift, d, lo_part,
+                       hi_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_probes(uint64_t seed, int M, int64_t rows, int8_t* out, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(probes_kernel, dim3(grid_for(rows * (int64_t)M, 256)), dim3(256), 0, s, seed, M, rows, out);
+  return hipGetLastError();
+}
+
+size_t transpose_scratch_bytes(int64_t d) {
+  const int64_t n = d + 1;
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  return (size_t)(n + nt + 8) * sizeof(int64_t);
+}
+
+hipError_t launch_transpose(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, int64_t d,
+                            int64_t nnz, int64_t* row_ptr_t, int32_t* col_t, void* val_t, int64_t* cursor,
+                            void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s) {
+  const int64_t n = d + 1;
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  if (scan_tmp_bytes < transpose_scratch_bytes(d)) return hipErrorInvalidValue;
+  int64_t* cnt = static_cast<int64_t*>(scan_tmp);
+  int64_t* sums = cnt + n;
+  hipError_t e = launch_fill_zero(cnt, (size_t)n * sizeof(int64_t), s);
+  if (e != hipSuccess) return e;
+  if (nnz > 0) hipLaunchKernelGGL(count_cols_kernel, dim3(grid_for(nnz, 256)), dim3(256), 0, s, col, nnz, cnt);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)nt), dim3(kScanBlock), 0, s, cnt, n, row_ptr_t, sums);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, s, sums, nt);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, row_ptr_t, n, sums);
+  e = hipMemcpyAsync(cursor, row_ptr_t, (size_t)d * sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  const unsigned g = grid_for(d, 256);
+  if (valt == VAL_F64) {
+    hipLaunchKernelGGL(scatter_t_kernel<VAL_F64>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t, val_t);
+    hipLaunchKernelGGL(sort_rows_kernel<VAL_F64>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t);
+  } else if (valt == VAL_F32) {
+    hipLaunchKernelGGL(scatter_t_kernel<VAL_F32>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t, val_t);
+    hipLaunchKernelGGL(sort_rows_kernel<VAL_F32>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t);
+  } else {
+    hipLaunchKernelGGL(scatter_t_kernel<VAL_BF16>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t,
+                       val_t);
+    hipLaunchKernelGGL(sort_rows_kernel<VAL_BF16>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_grad(const void* Gacc, int acc_f64, int64_t nnz, double scale, void* out, int out_f64,
+                             hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  const unsigned g = grid_for(nnz, 256);
+  if (acc_f64 && out_f64)
+    hipLaunchKernelGGL((scale_kernel<double, double>), dim3(g), dim3(256), 0, s, (const double*)Gacc, nnz, scale,
+                       (double*)out);
+  else if (acc_f64)
+    hipLaunchKernelGGL((scale_kernel<double, float>), dim3(g), dim3(256), 0, s, (const double*)Gacc, nnz, scale,
+                       (float*)out);
+  else if (out_f64)
+    hipLaunchKernelGGL((scale_kernel<float, double>), dim3(g), dim3(256), 0, s, (const float*)Gacc, nnz, scale,
+                       (double*)out);
+  else
+    hipLaunchKernelGGL((scale_kernel<float, float>), dim3(g), dim3(256), 0, s, (const float*)Gacc, nnz, scale,
+                       (float*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 > 0)
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16, 256, 1u << 20)), dim3(256), 0, s,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  const int64_t tail = (int64_t)(bytes - (size_t)n16 * 16);
+  if (tail > 0)
+    hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(256), 0, s, static_cast<const uint8_t*>(src) + n16 * 16,
+                       static_cast<uint8_t*>(dst) + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_probe(void* out, int vec_f64, double c, uint64_t seed, int64_t d, int M, hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  const unsigned g = grid_for(d * (int64_t)M, 256, 1u << 20);
+  if (vec_f64)
+    hipLaunchKernelGGL(fill_probe_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(out), c, seed, d, M);
+  else
+    hipLaunchKernelGGL(fill_probe_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(out), c, seed, d, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 > 0)
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n16, 256, 1u << 20)), dim3(256), 0, s, static_cast<uint4*>(p), n16);
+  const int64_t tail = (int64_t)(bytes - (size_t)n16 * 16);
+  if (tail > 0)
+    hipLaunchKernelGGL(zero_tail_kernel, dim3(1), dim3(256), 0, s, static_cast<uint8_t*>(p) + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+}  // namespace ld

@@ -1,0 +1,237 @@
+"""GPU parity of the forward estimator (Algorithm 1, [a, b] form) against the CPU oracle.
+
+Tolerances (relative, from the stated precision targets): 1e-10 on the FP64 path, 1e-4 on the
+FP32/BF16 path; both sides see identical probes (same counter hash) and identically rounded
+matrix values.  Moments are compared element by element (B-form, |mu| <= d scale).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests import _ref
+from tests._gpu import FLOOR, b_form_moments, dev, normwise, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1503_06394_amd as pkg
+
+    pkg.lib()
+    return pkg
+
+
+def _compare(r, o, tol, d, label):
+    # relative error with the floor FLOOR * d, so that an estimate of log det = 0 is not divided by ~0
+    assert rel(r["logdet"], o["gamma"], FLOOR * d) <= tol, (label, r["logdet"], o["gamma"])
+    assert np.max(np.abs(np.asarray(r["s"]) - o["s"])) <= tol * max(np.max(np.abs(o["s"])), FLOOR * d), label
+    if "moments" in r and "moments" in o:
+        mo = b_form_moments(o["moments"])
+        assert np.max(np.abs(r["moments"] - mo)) <= tol * d, label
+
+
+def test_probe_block_bit_exact(ld, oracle_lib):
+    rng = np.random.default_rng(0)
+    for seed in (0, 1, 12345, 2**63 + 5):
+        for M in (1, 50, 64, 65, 130):
+            rows = 1000
+            say(f"probes seed={seed} M={M} rows={rows}")
+            V = ld.ld_probes(seed, M, rows).cpu().numpy()
+            for _ in range(300):
+                r, j = int(rng.integers(rows)), int(rng.integers(M))
+                assert V[r, j] == oracle_lib.probe_sign(seed, j, r)
+    # large row indices exercise the (row << 16) part of the counter
+    say("probes at rows up to 2^24")
+    V = ld.ld_probes(7, 3, 1 << 24)
+    idx = rng.integers(0, 1 << 24, size=200)
+    Vh = V[idx.tolist()].cpu().numpy()
+    for t, r in enumerate(idx):
+        for j in range(3):
+            assert Vh[t, j] == oracle_lib.probe_sign(7, j, int(r))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_gershgorin_matches_oracle(ld, oracle_lib, storage):
+    B = synth.random_sparse_spd(5003, k_off=4, mseed=3, storage=storage)
+    say(f"gershgorin {storage}")
+    a, b = ld.ld_gershgorin(dev(B, shift=0.37))
+    ea, eb = oracle_lib.gershgorin(B, shift=0.37)
+    assert a == ea and b == eb
+
+
+def test_cfg0_fp64_parity(ld, oracle_lib):
+    """32x32 Dirichlet grid + 0.1 I, a = 0.1, b = 8.1, M = 50, n = 30, FP64 (rel 1e-10)."""
+    B = synth.grid_laplacian_2d(32)
+    say("cfg0 fp64")
+    r = ld.ld_logdet_cheb(dev(B, shift=0.1), 0.1, 8.1, 30, 50, 1, want_moments=True, want_probes=True)
+    o = oracle_lib.logdet(B, 0.1, 8.1, 30, 50, seed=1, shift=0.1, want_moments=True)
+    _compare(r, o, TOL64, B.d, "cfg0")
+    assert r["status"] == 0 and r["flags"] == 0
+    # and the estimate is within its standard error of the exact value (Cholesky, eigen-sum)
+    assert abs(r["logdet"] - 1259.922427278947) < 4 * r["std_err"]
+
+
+CASES32 = [
+    # (name, builder, shift, a, b, n, M, storage)
+    ("grid2d-40 f32", lambda: synth.grid_laplacian_2d(40, "f32"), 0.05, 0.05, 8.05, 50, 32),
+    ("grid3d-12 bf16", lambda: synth.grid_laplacian_3d(12, "bf16"), 0.09, 0.09, 12.09, 60, 32),
+    ("random-3001 f32", lambda: synth.random_sparse_spd(3001, 5, 2, 1.0, "f32"), 0.0, None, None, 50, 64),
+    ("random-2500 bf16", lambda: synth.random_sparse_spd(2500, 3, 5, 1.0, "bf16"), 0.0, None, None, 40, 48),
+]
+
+
+@pytest.mark.parametrize("case", CASES32, ids=[c[0] for c in CASES32])
+def test_fp32_path_parity(ld, oracle_lib, case):
+    name, build, shift, a, b, n, M = case
+    B = build()
+    if a is None:
+        a, b = oracle_lib.gershgorin(B, shift)
+    say(f"fp32 parity {name}")
+    r = ld.ld_logdet_cheb(dev(B, shift=shift), a, b, n, M, 11, want_moments=True, want_probes=True)
+    o = oracle_lib.logdet(B, a, b, n, M, seed=11, shift=shift, want_moments=True)
+    _compare(r, o, TOL32, B.d, name)
+
+
+def test_fp64_vectors_with_fp32_values(ld, oracle_lib):
+    B = synth.random_sparse_spd(4000, 5, 7, 1.0, "f32")
+    a, b = oracle_lib.gershgorin(B)
+    say("fp64 vectors, f32 values")
+    r = ld.ld_logdet_cheb(dev(B), a, b, 25, 16, 3, vec_f64=True, want_probes=True)
+    o = oracle_lib.logdet(B, a, b, 25, 16, seed=3)
+    _compare(r, o, TOL64, B.d, "f64vec")
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 7, 33, 64, 130, 300])
+@pytest.mark.parametrize("vec64", [True, False])
+def test_probe_counts_and_tiles(ld, oracle_lib, M, vec64):
+    """Probe counts that leave lanes idle, need narrow groups, or span several probe tiles."""
+    B = synth.random_sparse_spd(777, 3, 9, 1.0, "f64" if vec64 else "f32")
+    a, b = oracle_lib.gershgorin(B)
+    say(f"M={M} vec64={vec64}")
+    r = ld.ld_logdet_cheb(dev(B), a, b, 12, M, 5, vec_f64=vec64, want_moments=True, want_probes=True)
+    o = oracle_lib.logdet(B, a, b, 12, M, seed=5, want_moments=True)
+    _compare(r, o, TOL64 if vec64 else TOL32, B.d, f"M={M}")
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3])
+def test_low_degrees(ld, oracle_lib, n):
+    """n = 0 (Gamma = d log((a+b)/2)) and the first steps of the recurrence."""
+    B = synth.grid_laplacian_2d(9)
+    say(f"n={n}")
+    r = ld.ld_logdet_cheb(dev(B, shift=0.2), 0.2, 8.2, n, 6, 4, want_moments=True, want_probes=True)
+    o = oracle_lib.logdet(B, 0.2, 8.2, n, 6, seed=4, shift=0.2, want_moments=True)
+    _compare(r, o, TOL64, B.d, f"n={n}")
+    if n == 0:
+        assert rel(r["logdet"], B.d * math.log(4.2)) <= 1e-15
+
+
+@pytest.mark.parametrize("d", [1, 2, 5, 37])
+@pytest.mark.parametrize("tile", [0, 1, 4096])
+def test_tiny_and_ragged(ld, oracle_lib, d, tile):
+    B = synth.diagonal_matrix(np.linspace(1.0, 3.0, d)) if d < 5 else synth.random_sparse_spd(d, 2, d, 1.0, "f64")
+    a, b = oracle_lib.gershgorin(B)
+    a, b = 0.5 * a, 1.5 * b
+    say(f"d={d} tile={tile}")
+    r = ld.ld_logdet_cheb(dev(B), a, b, 9, 5, 2, tile=tile, want_probes=True, want_moments=True)
+    o = oracle_lib.logdet(B, a, b, 9, 5, seed=2, want_moments=True)
+    _compare(r, o, TOL64, B.d, f"d={d}")
+
+
+def test_rows_without_stored_diagonal(ld, oracle_lib):
+    """Rows whose pattern lacks the diagonal take the diagonal term from the shift alone."""
+    B = synth.random_sparse_spd(1500, 3, 4, 1.0, "f64")
+    rows = B.row_of_entry()
+    keep = ~((rows % 3 == 0) & (B.col == rows))
+    counts = np.bincount(rows[keep], minlength=B.d)
+    rp = np.zeros(B.d + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    C = synth.CSR(B.d, rp, B.col[keep], B.val[keep], "f64")
+    shift = 15.0
+    a, b = oracle_lib.gershgorin(C, shift)
+    assert a > 0
+    for vec64 in (True, False):
+        Cx = C if vec64 else synth.CSR(C.d, C.row_ptr, C.col, synth.round_to(C.val, "f32"), "f32")
+        say(f"no-diagonal rows vec64={vec64}")
+        r = ld.ld_logdet_cheb(dev(Cx, shift=shift), a, b, 20, 8, 6, vec_f64=vec64, want_probes=True)
+        o = oracle_lib.logdet(Cx, a, b, 20, 8, seed=6, shift=shift)
+        _compare(r, o, TOL64 if vec64 else TOL32, C.d, "nodiag")
+
+
+def test_diagonal_matrix_exact(ld):
+    """A diagonal matrix with entries at the mapped Chebyshev nodes gives sum log b_ii exactly."""
+    a, b, n = 0.5, 9.0, 12
+    x = np.cos(math.pi * (np.arange(n + 1) + 0.5) / (n + 1))
+    diag = np.resize(((b - a) * x + (a + b)) / 2.0, 300)
+    say("diagonal at nodes")
+    r = ld.ld_logdet_cheb(dev(synth.diagonal_matrix(diag)), a, b, n, 4, 9)
+    assert rel(r["logdet"], np.log(diag).sum()) <= 1e-13
+
+
+def test_bounds_warning(ld):
+    """b below lambda_max makes |mu_k| exceed d: the call warns (status 1) but still returns."""
+    B = synth.grid_laplacian_2d(32)
+    say("bounds warning")
+    r = ld.ld_logdet_cheb(dev(B, shift=0.1), 0.1, 7.0, 40, 4, 1)
+    assert r["status"] == ld.LD_WBOUNDS and r["flags"] & 1
+    r = ld.ld_logdet_cheb(dev(B, shift=0.1), 0.1, 8.1, 40, 4, 1)
+    assert r["status"] == 0
+
+
+def test_bitwise_reproducible(ld):
+    B = synth.random_sparse_spd(20000, 5, 1, 1.0, "f32")
+    D = dev(B)
+    a, b = ld.ld_gershgorin(D)
+    say("reproducibility")
+    r1 = ld.ld_logdet_cheb(D, a, b, 30, 64, 8, tile=64, want_moments=True)
+    r2 = ld.ld_logdet_cheb(D, a, b, 30, 64, 8, tile=64, want_moments=True)
+    assert r1["logdet"] == r2["logdet"]
+    assert np.array_equal(r1["moments"], r2["moments"])
+
+
+def test_caller_workspace_and_timing(ld, oracle_lib):
+    import torch
+
+    B = synth.grid_laplacian_2d(50, "f32")
+    D = dev(B, shift=0.3)
+    n, M = 20, 32
+    nbytes = ld.ld_workspace_bytes(D, n, M, 0)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    say("caller workspace")
+    r = ld.ld_logdet_cheb(D, 0.3, 8.3, n, M, 3, workspace=ws, timing=True)
+    o = oracle_lib.logdet(B, 0.3, 8.3, n, M, seed=3, shift=0.3)
+    assert rel(r["logdet"], o["gamma"]) <= TOL32
+    assert r["kernel_launches"] == n and r["kernel_ms"] > 0
+    small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ld.LogdetChebError):
+        ld.ld_logdet_cheb(D, 0.3, 8.3, n, M, 3, workspace=small)
+
+
+def test_autotuned_large_matrix(ld, oracle_lib):
+    """d >= 65536 goes through the tile autotuner; parity must not depend on the tile."""
+    B = synth.random_sparse_spd(100_000, 5, 12, 1.0, "f32")
+    D = dev(B)
+    a, b = oracle_lib.gershgorin(B)
+    say("autotuned d=1e5")
+    r = ld.ld_logdet_cheb(D, a, b, 10, 32, 21, want_probes=True)
+    o = oracle_lib.logdet(B, a, b, 10, 32, seed=21)
+    _compare(r, o, TOL32, B.d, "autotune")
+
+
+def test_python_convenience_gershgorin_default(ld, oracle_lib):
+    B = synth.random_sparse_spd(3000, 4, 13, 1.0, "f64")
+    say("logdet_cheb default bounds")
+    r = ld.logdet_cheb(dev(B), 20, 8, seed=5)
+    a, b = oracle_lib.gershgorin(B)
+    o = oracle_lib.logdet(B, a, b, 20, 8, seed=5)
+    assert rel(r["logdet"], o["gamma"]) <= TOL64

@@ -1,0 +1,106 @@
+"""GPU parity of the gradient (adjoint recurrence with checkpoints) against the oracle's reverse
+mode, plus the torch.autograd wrapper and the GMRF chain rule through (tau, kappa)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from tests._gpu import dev, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_1503_06394_amd as pkg
+
+    pkg.lib()
+    return pkg
+
+
+def _nw(g, ref):
+    g = np.asarray(g, dtype=np.float64)
+    return float(np.max(np.abs(g - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 30])
+@pytest.mark.parametrize("stride", [0, 2, 3, 5, 100])
+def test_grad_fp64_parity(ld, oracle_lib, n, stride):
+    B = synth.random_sparse_spd(2000, 4, 17, 1.0, "f64")
+    a, b = oracle_lib.gershgorin(B)
+    M, seed, shift, go = 16, 9, 0.25, 1.7
+    say(f"grad fp64 n={n} stride={stride}")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a + shift, b + shift, n, M, seed, go, ckpt_stride=stride)
+    o = oracle_lib.logdet_grad(B, a + shift, b + shift, n, M, seed=seed, shift=shift)
+    assert _nw(g.cpu().numpy(), go * o["grad"]) <= 1e-10
+    assert rel(r["grad_shift"], go * o["grad_shift"]) <= 1e-10
+    assert rel(r["logdet"], o["gamma"]) <= 1e-10
+
+
+def test_grad_rows_without_diagonal(ld, oracle_lib):
+    B = synth.random_sparse_spd(900, 3, 5, 1.0, "f64")
+    rows = B.row_of_entry()
+    keep = ~((rows % 2 == 0) & (B.col == rows))
+    rp = np.zeros(B.d + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows[keep], minlength=B.d), out=rp[1:])
+    C = synth.CSR(B.d, rp, B.col[keep], B.val[keep], "f64")
+    shift = 12.0
+    a, b = oracle_lib.gershgorin(C, shift)
+    say("grad no-diagonal rows")
+    r, g = ld.ld_logdet_cheb_grad(dev(C, shift=shift), a, b, 15, 8, 2)
+    o = oracle_lib.logdet_grad(C, a, b, 15, 8, seed=2, shift=shift)
+    assert _nw(g.cpu().numpy(), o["grad"]) <= 1e-10
+    assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-10
+
+
+@pytest.mark.parametrize("M", [1, 3, 32, 64])
+def test_grad_fp32_gmrf_parity(ld, oracle_lib, M):
+    """3-D GMRF precision Q = tau (kappa^2 I + L) in FP32 with the kappa^2 shift kept in FP64."""
+    N, tau, kappa, n = 10, 1.0, 0.3, 60
+    L = synth.grid_laplacian_3d(N, "f32")
+    shift = tau * kappa ** 2
+    a, b = tau * kappa ** 2, tau * (kappa ** 2 + 12.0)
+    say(f"grad fp32 gmrf M={M}")
+    r, g = ld.ld_logdet_cheb_grad(dev(L, shift=shift), a, b, n, M, 3)
+    o = oracle_lib.logdet_grad(L, a, b, n, M, seed=3, shift=shift)
+    assert _nw(g.cpu().numpy(), o["grad"]) <= 1e-4
+    assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-4
+    assert rel(r["logdet"], o["gamma"]) <= 1e-4
+
+
+def test_grad_rejects_too_many_probes(ld):
+    B = synth.grid_laplacian_2d(8, "f32")
+    with pytest.raises(ld.LogdetChebError):
+        ld.ld_logdet_cheb_grad(dev(B, shift=0.1), 0.1, 8.1, 5, 300, 0)
+
+
+def test_autograd_function_and_gmrf_chain_rule(ld, oracle_lib):
+    """LogdetCheb backward gives d/dvalues and d/dshift; the chain rule through Q = tau(kappa^2 I + L)
+    gives dGamma/dtau = sum_t grad_t L_t + grad_shift kappa^2 and dGamma/dkappa = grad_shift 2 tau kappa."""
+    import torch
+
+    N, n, M, seed = 8, 40, 32, 5
+    L = synth.grid_laplacian_3d(N, "f64")
+    tau = torch.tensor(1.3, dtype=torch.float64, device="cuda", requires_grad=True)
+    kappa = torch.tensor(0.4, dtype=torch.float64, device="cuda", requires_grad=True)
+    Lv = torch.tensor(L.val, dtype=torch.float64, device="cuda")
+    rp = torch.tensor(L.row_ptr, device="cuda")
+    col = torch.tensor(L.col, device="cuda")
+    a = float(tau * kappa ** 2)
+    b = float(tau * (kappa ** 2 + 12.0))
+    say("autograd gmrf")
+    vals = tau * Lv
+    shift = tau * kappa ** 2
+    out = ld.LogdetCheb.apply(vals, shift, rp, col, a, b, n, M, seed)
+    out.backward()
+    Q = synth.CSR(L.d, L.row_ptr, L.col, 1.3 * L.val)
+    o = oracle_lib.logdet_grad(Q, a, b, n, M, seed=seed, shift=1.3 * 0.16)
+    dtau = float((o["grad"] * L.val).sum() + o["grad_shift"] * 0.16)
+    dkap = float(o["grad_shift"] * 2 * 1.3 * 0.4)
+    assert rel(float(out), o["gamma"]) <= 1e-10
+    assert rel(float(tau.grad), dtau) <= 1e-9
+    assert rel(float(kappa.grad), dkap) <= 1e-9

@@ -1,0 +1,81 @@
+"""GPU parity of Algorithm 2 (log|det C| via C^T C) and of the device transpose it uses."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from tests._gpu import FLOOR, dev, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_1503_06394_amd as pkg
+
+    pkg.lib()
+    return pkg
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_transpose_matches_scipy(ld, storage):
+    C = synth.random_nonsingular(7001, 8, 3, 3.0, storage)
+    say(f"transpose {storage}")
+    T = ld.ld_transpose(dev(C))
+    S = sp.csr_matrix((C.val, C.col, C.row_ptr), shape=(C.d, C.d)).T.tocsr()
+    S.sort_indices()
+    assert np.array_equal(T.row_ptr.cpu().numpy(), S.indptr)
+    assert np.array_equal(T.col.cpu().numpy(), S.indices)
+    vals = T.values.float().cpu().numpy().astype(np.float64) if storage == "bf16" else T.values.cpu().numpy()
+    assert np.array_equal(vals, S.data)
+
+
+def _bounds(C):
+    Cd = synth.dense(C)
+    sv = np.linalg.svd(Cd, compute_uv=False)
+    smax = float(np.sqrt(np.abs(Cd).sum(0).max() * np.abs(Cd).sum(1).max()))  # sqrt(|C|_1 |C|_inf)
+    return 0.9 * float(sv.min()), smax
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-4), ("bf16", 1e-4)])
+@pytest.mark.parametrize("given_t", [False, True])
+def test_alg2_parity(ld, oracle_lib, storage, tol, given_t):
+    C = synth.random_nonsingular(1200, 8, 6, 3.0, storage)
+    smin, smax = _bounds(C)
+    n, M = 60, 32
+    D = dev(C)
+    Ct = ld.ld_transpose(D) if given_t else None
+    say(f"alg2 {storage} given_t={given_t}")
+    r = ld.ld_logabsdet_cheb(D, Ct, smin, smax, n, M, 6, want_probes=True)
+    o = oracle_lib.logabsdet(C, smin, smax, n, M, seed=6)
+    assert rel(r["logdet"], o["gamma"], FLOOR * C.d) <= tol, (r["logdet"], o["gamma"])
+    assert np.max(np.abs(r["s"] - o["s"])) <= tol * np.max(np.abs(o["s"]))
+    assert r["status"] == 0
+
+
+def test_alg2_accuracy_against_lu(ld):
+    """The estimate lands within its standard error of log|det C| from a dense LU."""
+    import scipy.linalg
+
+    C = synth.random_nonsingular(1000, 4, 8, 4.0, "f64")
+    smin, smax = _bounds(C)
+    say("alg2 vs LU")
+    r = ld.ld_logabsdet_cheb(dev(C), None, smin, smax, 80, 256, 1)
+    lu, _ = scipy.linalg.lu_factor(synth.dense(C))
+    exact = float(np.log(np.abs(np.diag(lu))).sum())
+    assert abs(r["logdet"] - exact) < 4 * r["std_err"] + 1e-3 * abs(exact)
+
+
+def test_alg2_rejects_bad_arguments(ld):
+    C = synth.random_nonsingular(100, 3, 1, 3.0, "f64")
+    D = dev(C)
+    with pytest.raises(ld.LogdetChebError):
+        ld.ld_logabsdet_cheb(D, None, 2.0, 1.0, 10, 4, 0)
+    D.diag_shift = 1.0
+    with pytest.raises(ld.LogdetChebError):
+        ld.ld_logabsdet_cheb(D, None, 0.5, 10.0, 10, 4, 0)
