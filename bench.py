@@ -1,0 +1,281 @@
+"""Benchmark of the stochastic Chebyshev log-determinant hot path on one MI355X.
+
+A step is one pass of the whole path over the workload with inputs resident in HBM:
+Gershgorin bounds on the device, then the forward estimate and its gradient on the
+sparsity pattern (ld_logdet_cheb_grad: forward recurrence with checkpoints, recomputation,
+adjoint recurrence fused with the SDDMM).  The metric counts M * n * nnz matrix-vector
+nonzeros per logdet (the forward work of Algorithm 1) per second of fwd+grad time.
+
+Default workload: random sparse symmetric diagonally dominant matrix, d = 1,000,000, about
+11 stored entries per row (Section 5.1 recipe with diagonal = sum |offdiag| + 1), FP32
+values and recurrence, M = 64 probes in one block, degree n = 50.
+
+Prints ONE JSON line.  Runs on one GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+METRIC = "logdet fwd+grad matvec-nnz/s and HBM GB/s vs peak, at stated rel. error"
+KERNEL_SRC = os.path.join(ROOT, "paper_1503_06394_amd", "csrc", "ld_kernels.hip")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------------------
+
+def workload(name: str):
+    import synth
+
+    if name == "random1m":
+        B = synth.random_sparse_spd(1_000_000, k_off=5, mseed=2, diag_add=1.0, storage="f32")
+        return dict(B=B, shift=0.0, a=None, b=None, n=50, M=64, seed=2, grad=True,
+                    desc="random sparse SPD d=1e6, ~11 nnz/row, U[-1,1] offdiag, diag=sum|off|+1, FP32, "
+                         "M=64, n=50, Gershgorin bounds")
+    if name == "grid32":
+        B = synth.grid_laplacian_2d(32, "f64")
+        return dict(B=B, shift=0.1, a=0.1, b=8.1, n=30, M=50, seed=1, grad=True,
+                    desc="2D Dirichlet grid 32x32 + 0.1 I, FP64, M=50, n=30")
+    if name == "gmrf128":
+        B = synth.grid_laplacian_3d(128, "f32")
+        kappa = 0.3
+        return dict(B=B, shift=kappa ** 2, a=kappa ** 2, b=kappa ** 2 + 12.0, n=60, M=32, seed=3, grad=True,
+                    desc="3D GMRF Q=tau(kappa^2 I+L) 128^3, tau=1, kappa=0.3, FP32, M=32, n=60")
+    if name == "grid4096":
+        B = synth.grid_laplacian_2d(4096, "bf16")
+        return dict(B=B, shift=0.01, a=0.01, b=8.01, n=100, M=32, seed=5, grad=False,
+                    desc="2D Dirichlet grid 4096x4096 + 0.01 I, BF16 values, FP32 recurrence, M=32, n=100")
+    raise SystemExit(f"unknown workload {name}")
+
+
+# ----------------------------------------------------------------------------------------
+# algorithmic bytes of the dominant kernels (per launch)
+# ----------------------------------------------------------------------------------------
+
+def step_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int) -> int:
+    """Compulsory bytes of one recurrence step: the CSR matrix once (values, int32 columns, int64
+    row pointers), W_k read once, W_{k-1} read, W_{k+1} written."""
+    return nnz * (val_bytes + 4) + (d + 1) * 8 + 3 * d * M * vec_bytes
+
+
+def adjoint_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int) -> int:
+    """Compulsory bytes of one adjoint step: the CSR matrix, y_{k+1} and w_k read once each, y_{k+2}
+    read, y_k written, and the nnz gradient accumulators read and written."""
+    return nnz * (val_bytes + 4) + (d + 1) * 8 + 4 * d * M * vec_bytes + 2 * nnz * acc_bytes
+
+
+def traffic_from_profiles(kernel_tag: str, workload_name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when absent or
+    when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"counters_{kernel_tag}_{workload_name}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t:
+        return None
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if cur != m.group(1):
+        return None
+    return float(t.group(1))
+
+
+# ----------------------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample
+# ----------------------------------------------------------------------------------------
+
+def cpu_baseline(W: dict, a: float, b: float, gpu_probe_values) -> tuple:
+    import numpy as np
+
+    import oracle
+
+    oracle.build()
+    B, n, M = W["B"], W["n"], W["M"]
+    # one probe at a time (probe ids 0, 1, ...) until about 10 s of single-core work
+    secs, done = 0.0, 0
+    while done < M and (secs < 10.0 or done == 0):
+        t0 = time.perf_counter()
+        if W["grad"]:
+            oracle.logdet_grad(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
+        else:
+            oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
+        secs += time.perf_counter() - t0
+        done += 1
+    r = oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]), shift=W["shift"])
+    work = done * n * B.nnz
+    kind = "fwd+grad" if W["grad"] else "fwd"
+    base = {"value": work / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"{kind} of probes 0..{done - 1} of {M} on the full matrix (degree {n}), single-threaded "
+                      f"FP64 C oracle, {secs:.1f} s"}
+    parity = None
+    if gpu_probe_values is not None:
+        ref = float(r["s"][0])
+        parity = abs(float(gpu_probe_values[0]) - ref) / max(abs(ref), 1e-3 * B.d)
+    return base, parity
+
+
+# ----------------------------------------------------------------------------------------
+# main
+# ----------------------------------------------------------------------------------------
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="random1m", choices=["random1m", "grid32", "gmrf128", "grid4096"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fwd-only", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run the library's streaming copy kernel on this many bytes (HBM calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (probes would shard "
+              "across GPUs with one all-reduce of the moment table; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1503_06394_amd as ld
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    copy_gbps = None
+    if args.copy_bytes:
+        src = torch.empty(args.copy_bytes, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        ts = [ld.ld_copy(dst, src) for _ in range(4)]
+        copy_gbps = 2 * args.copy_bytes / (min(ts[1:]) / 1e3) / 1e9
+        log(f"copy kernel: {args.copy_bytes} bytes, best {min(ts[1:]):.4f} ms, {copy_gbps:.1f} GB/s (read+write)")
+        del src, dst
+    log(f"building workload {args.workload}")
+    W = workload(args.workload)
+    B = W["B"]
+    d, nnz, M, n = B.d, B.nnz, W["M"], W["n"]
+    D = ld.DeviceCSR.from_host(B, device="cuda:0", diag_shift=W["shift"])
+    vec_f64 = B.storage == "f64"
+    val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[B.storage]
+    vec_bytes = 8 if vec_f64 else 4
+    do_grad = W["grad"] and not args.fwd_only
+    log(f"d={d} nnz={nnz} M={M} n={n} storage={B.storage} grad={do_grad}")
+
+    ws_fwd = torch.empty(ld.ld_workspace_bytes(D, n, M, 0), dtype=torch.uint8, device="cuda:0")
+    ws_grad = torch.empty(ld.ld_workspace_bytes(D, n, M, 2), dtype=torch.uint8, device="cuda:0") if do_grad else None
+    gdt = torch.float64 if vec_f64 else torch.float32
+
+    def bounds():
+        if W["a"] is not None:
+            return W["a"], W["b"]
+        return ld.ld_gershgorin(D)
+
+    def one_step(timing: bool):
+        a, b = bounds()
+        if do_grad:
+            r, g = ld.ld_logdet_cheb_grad(D, a, b, n, M, W["seed"], 1.0, grad_dtype=gdt, workspace=ws_grad,
+                                          timing=timing)
+            return r
+        return ld.ld_logdet_cheb(D, a, b, n, M, W["seed"], workspace=ws_fwd, timing=timing)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    step_ms = adj_ms = 0.0
+    step_n = adj_n = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = one_step(True)
+        step_ms += r["kernel_ms"]
+        step_n += r["kernel_launches"]
+        adj_ms += r["adjoint_ms"]
+        adj_n += r["adjoint_launches"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    work = M * n * nnz
+    value = work / (ms_per_step / 1e3)
+
+    # forward-only throughput on the same inputs (context)
+    a, b = bounds()
+    fwd_ms = None
+    if do_grad:
+        for _ in range(2):
+            ld.ld_logdet_cheb(D, a, b, n, M, W["seed"], workspace=ws_fwd)
+        torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        kf = max(3, args.steps)
+        for _ in range(kf):
+            rf = ld.ld_logdet_cheb(D, a, b, n, M, W["seed"], workspace=ws_fwd)
+        torch.cuda.synchronize()
+        fwd_ms = (time.perf_counter() - tf0) * 1e3 / kf
+    rp = ld.ld_logdet_cheb(D, a, b, n, M, W["seed"], workspace=ws_fwd, want_probes=True)
+
+    # dominant kernel: the larger of the summed step and adjoint kernel times
+    sb = step_bytes(d, nnz, M, val_bytes, vec_bytes)
+    ab_ = adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes)
+    if adj_ms > step_ms and adj_n > 0:
+        tag, avg_ms, bytes_ = "adjoint", adj_ms / adj_n, ab_
+    else:
+        tag, avg_ms, bytes_ = "step", step_ms / max(step_n, 1), sb
+    achieved = bytes_ / (avg_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(tag, args.workload)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": f"{tag} kernel",
+            "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_}
+    extra = {
+        "step_kernel": {"avg_ms": round(step_ms / max(step_n, 1), 5), "launches_per_step": step_n // args.steps,
+                        "algorithmic_GBps": round(sb / (step_ms / max(step_n, 1) / 1e3) / 1e9, 1)},
+    }
+    if adj_n:
+        extra["adjoint_kernel"] = {"avg_ms": round(adj_ms / adj_n, 5), "launches_per_step": adj_n // args.steps,
+                                   "algorithmic_GBps": round(ab_ / (adj_ms / adj_n / 1e3) / 1e9, 1)}
+    if fwd_ms is not None:
+        extra["forward_only"] = {"ms": round(fwd_ms, 3), "matvec_nnz_per_s": work / (fwd_ms / 1e3)}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one probe)")
+        cpu, parity = cpu_baseline(W, a, b, rp["s"])
+    accuracy = {"logdet": r["logdet"], "std_err_rel": abs(r["std_err"] / r["logdet"]),
+                "lemma7_bound_rel": abs(r["poly_bound"] / r["logdet"]),
+                "oracle_parity_rel_probe0": parity, "parity_tolerance": 1e-10 if vec_f64 else 1e-4}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "matvec-nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if vec_f64 else "f32", "data": "synthetic",
+        "config": {"workload": W["desc"], "d": d, "nnz": nnz, "M": M, "n": n, "values": B.storage,
+                   "step": "gershgorin bounds + forward + gradient" if do_grad else "bounds + forward",
+                   "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "accuracy": accuracy, "kernels": extra,
+    }
+    if copy_gbps is not None:
+        out["copy_kernel_GBps"] = round(copy_gbps, 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -45,7 +45,8 @@ class _CSR(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [
         ("logdet", ctypes.c_double), ("std_err", ctypes.c_double), ("poly_bound", ctypes.c_double),
-        ("grad_shift", ctypes.c_double), ("kernel_ms", ctypes.c_double), ("kernel_launches", ctypes.c_int32),
+        ("grad_shift", ctypes.c_double), ("kernel_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double),
+        ("kernel_launches", ctypes.c_int32), ("adjoint_launches", ctypes.c_int32),
         ("n", ctypes.c_int32), ("M", ctypes.c_int32), ("flags", ctypes.c_uint32),
     ]
 
@@ -160,7 +161,8 @@ def _opts(vec_f64=None, tile=0, timing=False, workspace=None, ckpt_stride=0, mom
 
 def _result(r: _Result, rc: int) -> dict:
     return {"logdet": r.logdet, "std_err": r.std_err, "poly_bound": r.poly_bound, "grad_shift": r.grad_shift,
-            "kernel_ms": r.kernel_ms, "kernel_launches": r.kernel_launches, "n": r.n, "M": r.M,
+            "kernel_ms": r.kernel_ms, "kernel_launches": r.kernel_launches, "adjoint_ms": r.adjoint_ms,
+            "adjoint_launches": r.adjoint_launches, "n": r.n, "M": r.M,
             "flags": r.flags, "status": rc}
 
 

@@ -195,6 +195,12 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;  // -> tile_rows
 
+// LD_GRAD_SYM=0 forces the two-gather adjoint even for symmetric patterns (for testing).
+bool sym_enabled() {
+  const char* e = std::getenv("LD_GRAD_SYM");
+  return !(e && e[0] == '0');
+}
+
 bool autotune_enabled() {
   const char* e = std::getenv("LD_AUTOTUNE");
   return !(e && e[0] == '0');
@@ -261,33 +267,42 @@ int autotune_tile(const ld_csr* B, const Shape& base, int vec_f64, int valt, int
 // step timing (HIP events on the launch stream)
 // ------------------------------------------------------------------------------------
 
+// Interval kinds recorded by StepTimer::mark: what ran since the previous mark.
+enum : int { T_OTHER = 0, T_STEP = 1, T_ADJ = 2 };
+
 struct StepTimer {
   bool on = false;
   hipStream_t s = nullptr;
   std::vector<hipEvent_t> ev;
-  std::vector<char> timed;  // whether interval i is a recurrence step
+  std::vector<int> kind;  // kind of interval i (between events i and i+1)
   ~StepTimer() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
-  hipError_t mark(bool step_interval) {
+  hipError_t mark(int interval_kind) {
     if (!on) return hipSuccess;
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return r;
     ev.push_back(e);
-    if (ev.size() > 1) timed.push_back(step_interval ? 1 : 0);
+    if (ev.size() > 1) kind.push_back(interval_kind);
     return hipEventRecord(e, s);
   }
   void report(ld_result* out) {
     out->kernel_ms = 0.0;
     out->kernel_launches = 0;
+    out->adjoint_ms = 0.0;
+    out->adjoint_launches = 0;
     if (!on) return;
     for (size_t i = 0; i + 1 < ev.size(); ++i) {
-      if (!timed[i]) continue;
+      if (kind[i] == T_OTHER) continue;
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) continue;
+      if (kind[i] == T_STEP) {
         out->kernel_ms += ms;
         out->kernel_launches += 1;
+      } else {
+        out->adjoint_ms += ms;
+        out->adjoint_launches += 1;
       }
     }
   }
@@ -468,7 +483,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
 
   // W_k lives in: k = 0 -> probe hash, odd k -> A, even k >= 2 -> B.
   auto wbuf = [&](int k) -> void* { return k == 0 ? nullptr : ((k & 1) ? bufA : bufB); };
-  LD_HIP(tm.mark(false));
+  LD_HIP(tm.mark(T_OTHER));
   for (int k = 0; k < n && d > 0; ++k) {
     const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
     const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
@@ -484,7 +499,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       D.mu_part = part_base + (int64_t)k * kstride;
       L.d0 = D;
       LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, true, s));
-      LD_HIP(tm.mark(true));
+      LD_HIP(tm.mark(T_STEP));
     } else {
       // T = C W_k
       StepDesc D1 = base_desc(B);
@@ -493,7 +508,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       D1.ag = 1.0;
       L.d0 = D1;
       LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_NONE, SRC_NONE, false, s));
-      LD_HIP(tm.mark(true));
+      LD_HIP(tm.mark(T_STEP));
       // W_{k+1} = alpha C^T T + beta W_k - W_{k-1}   (halved at k = 0)
       StepDesc D2 = base_desc(&Ct);
       D2.G = bufT;
@@ -506,7 +521,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       D2.mu_part = part_base + (int64_t)k * kstride;
       L.d0 = D2;
       LD_HIP(launch_step(L, vec_f64, valt, SRC_BUF, k == 0 ? SRC_HASH : SRC_BUF, psrc, true, s));
-      LD_HIP(tm.mark(true));
+      LD_HIP(tm.mark(T_STEP));
     }
   }
   if (n >= 1 && d > 0) LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 1, n, kstride, mu_dev, n + 1, s));
@@ -562,6 +577,8 @@ size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, int stride) {
   const size_t vecb = (size_t)B->rows * M * vb;
   for (int i = 0; i < g.nslots + g.nseg_buf + 2; ++i) c.take(vecb);
   c.take((size_t)B->nnz * vb);                    // gradient accumulators
+  c.take((size_t)B->nnz * 8);                     // transposed-entry index
+  c.take(256);                                    // missing-transpose flag
   c.take((size_t)std::max<int64_t>(ntiles, 1) * 8);  // diagonal partials
   c.take(8);                                      // diagonal total
   c.take((size_t)std::max(n, 1) * ntiles * M * 8);
@@ -880,6 +897,8 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   void* Ya = cv.take(vecb);
   void* Yb = cv.take(vecb);
   void* Gacc = cv.take((size_t)B->nnz * vb);
+  int64_t* perm = static_cast<int64_t*>(cv.take((size_t)B->nnz * 8));
+  int* missing = static_cast<int*>(cv.take(256));
   double* gdiag_part = static_cast<double*>(cv.take((size_t)std::max<int64_t>(ntiles, 1) * 8));
   double* gdiag_tot = static_cast<double*>(cv.take(8));
   double* part = static_cast<double*>(cv.take((size_t)std::max(n, 1) * ntiles * M * 8));
@@ -895,8 +914,10 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   tm.on = opt && opt->timing;
   tm.s = s;
   LD_HIP(launch_fill_zero(Gacc, (size_t)B->nnz * vb, s));
+  LD_HIP(launch_fill_zero(missing, 256, s));
+  LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, perm, missing, s));
   LD_HIP(launch_fill_zero(gdiag_part, (size_t)std::max<int64_t>(ntiles, 1) * 8, s));
-  LD_HIP(tm.mark(false));
+  LD_HIP(tm.mark(T_OTHER));
 
   StepLaunch L{};
   L.nmat = 1;
@@ -943,14 +964,23 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
     const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
     LD_HIP(step(gsrc, psrc, true, bufW[k], k >= 2 ? bufW[k - 1] : nullptr, o, k == 0 ? 0.5 : 1.0,
                 k == 0 ? 0.0 : -1.0, part + (int64_t)k * kstride));
-    LD_HIP(tm.mark(true));
+    LD_HIP(tm.mark(T_STEP));
     bufW[k + 1] = o;
   }
   if (n >= 1 && d > 0) LD_HIP(launch_reduce_moments(part, ntiles, M, 1, n, kstride, mu_dev, n + 1, s));
 
-  // backward: y_n = c_n V; y_k = c_k V + 2 At y_{k+1} - y_{k+2}; SDDMM with w_k
+  // backward: y_n = c_n V; y_k = c_k V + 2 At y_{k+1} - y_{k+2}; SDDMM with w_k.
+  // A symmetric pattern lets each row accumulate its transposed entries from the rows of
+  // y_{k+1} that the SpMM gathers anyway (one gather per nonzero instead of two).
+  int miss = 1;
+  if (B->nnz > 0) {
+    LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
+    LD_HIP(hipStreamSynchronize(s));
+  }
+  const bool sym = (miss == 0) && sym_enabled();
   if (n >= 1 && d > 0) {
     LD_HIP(launch_fill_probe(Ya, vec_f64, c[n], seed, d, M, s));
+    LD_HIP(tm.mark(T_OTHER));
     void* y1 = Ya;       // y_{k+1}
     void* y2 = nullptr;  // y_{k+2}
     AdjDesc A{};
@@ -974,6 +1004,7 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
         const bool p_hash = (k_lo + i - 2) == 0;
         LD_HIP(step(SRC_BUF, p_hash ? SRC_HASH : SRC_BUF, false, segW[i - 1], p_hash ? nullptr : segW[i - 2],
                     seg[i - 2], 1.0, -1.0, nullptr));
+        LD_HIP(tm.mark(T_STEP));
         segW[i] = seg[i - 2];
       }
       for (int k = k_hi; k >= std::max(k_lo, 1); --k) {
@@ -984,7 +1015,8 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
         A.W = segW[k - k_lo];
         A.cv = c[k];
         A.gw = 2.0;
-        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, true, false, y2 != nullptr, s));
+        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, true, false, y2 != nullptr, sym, s));
+        LD_HIP(tm.mark(T_ADJ));
         y2 = y1;
         y1 = o;
       }
@@ -996,12 +1028,18 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
         A.W = nullptr;
         A.cv = 0.0;
         A.gw = 1.0;
-        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, false, true, false, s));
+        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, false, true, false, sym, s));
+        LD_HIP(tm.mark(T_ADJ));
       }
     }
   }
   const double scale = grad_output * (2.0 / (b - a)) / M;
-  if (B->nnz > 0) LD_HIP(launch_scale_grad(Gacc, vec_f64, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
+  if (B->nnz > 0) {
+    if (sym)
+      LD_HIP(launch_permute_scale(Gacc, vec_f64, perm, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
+    else
+      LD_HIP(launch_scale_grad(Gacc, vec_f64, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
+  }
   double gd = 0.0;
   if (ntiles > 0) {
     LD_HIP(launch_sum_doubles(gdiag_part, ntiles, gdiag_tot, s));
@@ -1009,7 +1047,7 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   }
   std::vector<double> mu((size_t)M * (n + 1), 0.0);
   if (n >= 1 && d > 0) LD_HIP(hipMemcpyAsync(mu.data(), mu_dev, mu.size() * 8, hipMemcpyDeviceToHost, s));
-  LD_HIP(tm.mark(false));
+  LD_HIP(tm.mark(T_OTHER));
   LD_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < M; ++j) mu[(size_t)j * (n + 1)] = (double)d;
   ld_result r{};
@@ -1065,9 +1103,9 @@ int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const d
   StepTimer tm;
   tm.on = opt && opt->timing;
   tm.s = s;
-  LD_HIP(tm.mark(false));
+  LD_HIP(tm.mark(T_OTHER));
   LD_HIP(hipGraphLaunch(E->exec, s));
-  LD_HIP(tm.mark(true));
+  LD_HIP(tm.mark(T_STEP));
   const int kmax = E->kmax;
   std::vector<double> mu_all((size_t)count * M * (kmax + 1));
   LD_HIP(hipMemcpyAsync(mu_all.data(), E->mu_dev, mu_all.size() * 8, hipMemcpyDeviceToHost, s));

@@ -87,8 +87,17 @@ struct AdjDesc {
   int64_t d;
 };
 
+// sym: the pattern is symmetric and A.Gacc accumulates the transposed entries (see the kernel).
 hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64, int valt, bool spmm,
-                          bool w_hash, bool y2, hipStream_t s);
+                          bool w_hash, bool y2, bool sym, hipStream_t s);
+
+// perm[t] = index of the stored entry (col[t], row(t)); *missing |= 1 if some is absent.
+hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t* perm,
+                                  int* missing, hipStream_t s);
+
+// out[t] = scale * a[perm[t]]
+hipError_t launch_permute_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,
+                                int out_f64, hipStream_t s);
 
 // Deterministic reduction of per-tile partials:
 // mu[j * ldmu + k] = sum_{t < ntiles} part[k][t][j] for k in [k_lo, k_hi].

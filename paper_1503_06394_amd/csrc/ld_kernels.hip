@@ -23,6 +23,13 @@
 
 #include "ld_internal.h"
 
+#ifndef LD_UNROLL
+#define LD_UNROLL 8
+#endif
+#ifndef LD_NT
+#define LD_NT 1
+#endif
+
 namespace ld {
 
 // ------------------------------------------------------------------------------------
@@ -93,6 +100,41 @@ __device__ __forceinline__ void vstore(VT* p, const VT* r) {
   }
 }
 
+// Non-temporal variants for the streamed operands (read or written once per step), so that
+// they do not displace the gathered W_k rows from L2 and the Infinity Cache.
+template <typename VT, int N>
+__device__ __forceinline__ void vload_nt(const VT* p, VT* r) {
+#if LD_NT
+  if constexpr (N == 1) {
+    r[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef VT vec_t __attribute__((ext_vector_type(N)));
+    const vec_t x = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(p));
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = x[i];
+  }
+#else
+  vload<VT, N>(p, r);
+#endif
+}
+
+template <typename VT, int N>
+__device__ __forceinline__ void vstore_nt(VT* p, const VT* r) {
+#if LD_NT
+  if constexpr (N == 1) {
+    __builtin_nontemporal_store(r[0], p);
+  } else {
+    typedef VT vec_t __attribute__((ext_vector_type(N)));
+    vec_t x;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = r[i];
+    __builtin_nontemporal_store(x, reinterpret_cast<vec_t*>(p));
+  }
+#else
+  vstore<VT, N>(p, r);
+#endif
+}
+
 // Physical workgroup id -> logical tile: XCD x (= id mod 8) walks tiles
 // [x * per, (x + 1) * per) in dispatch order.
 __device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
@@ -103,6 +145,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
 
 constexpr int kBlock = 256;  // 4 waves of 64
 constexpr int kWaves = kBlock / 64;
+constexpr int kUnroll = LD_UNROLL;  // nonzeros whose gathers are in flight together per row group
 
 // ------------------------------------------------------------------------------------
 // fused recurrence step
@@ -158,6 +201,28 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
     for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
     bool hd = false;
 
+    // Gather kUnroll rows of G (or probe rows) per pass; padding slots (past the row's end)
+    // issue no load and contribute nothing.
+    auto gather_pass = [&](const int* cc, const VT* aa, const bool* ok) {
+      VT gg[kUnroll][VPL];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (ok[u]) {
+          if constexpr (GSRC == SRC_BUF)
+            vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
+          else
+            probe_signs<VT, VPL>(D.seed, cc[u], p0, gg[u]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) gg[u][i] = VT(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
+    };
+
     if (LPR >= 4) {
       // cooperative: lane `sub` of the group loads entry cb + sub of the row
       for (int64_t cb = s; cb < e; cb += LPR) {
@@ -169,51 +234,42 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
           vl = Val<VALT>::get(D.val, t);
         }
         const int cnt = (int)min((int64_t)LPR, e - cb);
-        for (int q = 0; q < cnt; q += 4) {
-          int cc[4];
-          VT aa[4];
+        for (int q = 0; q < cnt; q += kUnroll) {
+          int cc[kUnroll];
+          VT aa[kUnroll];
+          bool ok[kUnroll];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const bool ok = q + u < cnt;
-            const int srcl = gbase + (ok ? q + u : 0);
+          for (int u = 0; u < kUnroll; ++u) {
+            ok[u] = q + u < cnt;
+            const int srcl = gbase + ((q + u) & (LPR - 1));
             const int cu = __shfl(cl, srcl, 64);
             const MV vu = __shfl(vl, srcl, 64);
-            VT a = ok ? ag * (VT)vu : VT(0);
+            VT a = ok[u] ? ag * (VT)vu : VT(0);
             if constexpr (DSRC == SRC_SAME) {
-              if (ok && cu == row) {
+              if (ok[u] && cu == row) {
                 a += bd;
                 hd = true;
               }
             }
             aa[u] = a;
-            cc[u] = ok ? cu : (int)row;
+            cc[u] = cu;
           }
-          VT gg[4][VPL];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if constexpr (GSRC == SRC_BUF)
-              vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
-            else
-              probe_signs<VT, VPL>(D.seed, cc[u], p0, gg[u]);
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
+          gather_pass(cc, aa, ok);
         }
       }
     } else {
       // narrow groups: every lane reads the row's entries itself
-      for (int64_t t = s; t < e; t += 4) {
-        int cc[4];
-        VT aa[4];
+      for (int64_t t = s; t < e; t += kUnroll) {
+        int cc[kUnroll];
+        VT aa[kUnroll];
+        bool ok[kUnroll];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const bool ok = t + u < e;
-          const int cu = ok ? ci[t + u] : (int)row;
-          VT a = ok ? ag * (VT)Val<VALT>::get(D.val, t + u) : VT(0);
+        for (int u = 0; u < kUnroll; ++u) {
+          ok[u] = t + u < e;
+          const int cu = ok[u] ? ci[t + u] : 0;
+          VT a = ok[u] ? ag * (VT)Val<VALT>::get(D.val, t + u) : VT(0);
           if constexpr (DSRC == SRC_SAME) {
-            if (ok && cu == row) {
+            if (ok[u] && cu == row) {
               a += bd;
               hd = true;
             }
@@ -221,18 +277,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
           aa[u] = a;
           cc[u] = cu;
         }
-        VT gg[4][VPL];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if constexpr (GSRC == SRC_BUF)
-            vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
-          else
-            probe_signs<VT, VPL>(D.seed, cc[u], p0, gg[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
+        gather_pass(cc, aa, ok);
       }
     }
 
@@ -261,7 +306,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
       }
       if constexpr (PSRC == SRC_BUF) {
         VT pv[VPL];
-        vload<VT, VPL>(P + off, pv);
+        vload_nt<VT, VPL>(P + off, pv);
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
       } else if constexpr (PSRC == SRC_HASH) {
@@ -271,7 +316,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
         for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
       }
       if (pact) {
-        vstore<VT, VPL>(out + off, acc);
+        vstore_nt<VT, VPL>(out + off, acc);
         if constexpr (MU) {
           const uint64_t w = probe_word(D.seed, (uint64_t)row, (uint32_t)(p0 >> 6));
           const uint32_t bits = (uint32_t)(w >> (p0 & 63));
@@ -311,7 +356,13 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
 // adjoint step (gradient): Clenshaw-type backward recurrence fused with the SDDMM
 // ------------------------------------------------------------------------------------
 
-template <typename VT, int VALT, int VPL, bool SPMM, bool WHASH, bool Y2>
+// Two forms of the SDDMM term G_ij += gw * sum_p y1[i,p] w[j,p] for stored (i, j):
+//  * general pattern: gather w[j] next to y1[j] (two gathers per nonzero);
+//  * symmetric pattern (SYM): row i computes, for each stored (i, j), the value of the
+//    TRANSPOSED entry, H_t = gw * sum_p y1[j,p] w[i,p] = G_ji contribution, from the y1[j]
+//    row that the SpMM gathers anyway and the row's own w[i]; H is permuted once at the end
+//    (entry (i, j) takes H at the index of (j, i)).  One gather per nonzero.
+template <typename VT, int VALT, int VPL, bool SPMM, bool WHASH, bool Y2, bool SYM>
 __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows,
                                                          int64_t ntiles) {
   typedef typename Val<VALT>::T MV;
@@ -335,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
   const VT* Y2p = static_cast<const VT*>(A.Y2);
   VT* out = static_cast<VT*>(A.out);
   const VT* __restrict__ W = static_cast<const VT*>(A.W);
-  VT* __restrict__ Gacc = static_cast<VT*>(A.Gacc);
+  VT* __restrict__ Hacc = static_cast<VT*>(A.Gacc);
   const int64_t* __restrict__ rp = A.row_ptr;
   const int32_t* __restrict__ ci = A.col;
 
@@ -349,66 +400,98 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
       e = rp[row + 1];
     }
     const int64_t roff = (has ? row : row0) * (int64_t)M + p0;
-    VT yown[VPL];
+    VT yown[VPL], wown[VPL];
     vload<VT, VPL>(Y1 + roff, yown);
-    if (!pact || !has)
+    if constexpr (WHASH)
+      probe_signs<VT, VPL>(A.seed, has ? row : row0, p0, wown);
+    else
+      vload_nt<VT, VPL>(W + roff, wown);
+    if (!pact || !has) {
 #pragma unroll
-      for (int i = 0; i < VPL; ++i) yown[i] = VT(0);
+      for (int i = 0; i < VPL; ++i) yown[i] = wown[i] = VT(0);
+    }
     VT acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
-    bool hd = false;
-    VT wdiag[VPL];
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) wdiag[i] = VT(0);
 
-    for (int64_t cb = s; cb < e; cb += LPR) {
-      const int64_t t = cb + sub;
-      int cl = 0;
-      MV vl = MV(0);
-      if (t < e) {
-        cl = ci[t];
-        vl = Val<VALT>::get(A.val, t);
-      }
-      const int cnt = (int)min((int64_t)LPR, e - cb);
-      for (int q = 0; q < cnt; ++q) {
-        const int srcl = gbase + q;
-        const int cu = __shfl(cl, srcl, 64);
-        const MV vu = __shfl(vl, srcl, 64);
-        VT wv[VPL];
-        if constexpr (WHASH)
-          probe_signs<VT, VPL>(A.seed, cu, p0, wv);
-        else
-          vload<VT, VPL>(W + (int64_t)cu * M + p0, wv);
-        if constexpr (SPMM) {
-          VT yv[VPL];
-          vload<VT, VPL>(Y1 + (int64_t)cu * M + p0, yv);
-          const VT a = ag * (VT)vu;
+    // one pass over up to kUnroll nonzeros starting at entry index t0
+    auto pass = [&](int64_t t0, const int* cc, const MV* vv, const bool* ok) {
+      VT dot[kUnroll];
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(a, yv[i], acc[i]);
+      for (int u = 0; u < kUnroll; ++u) {
+        VT yg[VPL], wg[VPL];
+        if (ok[u]) {
+          if constexpr (SPMM || SYM) vload<VT, VPL>(Y1 + (int64_t)cc[u] * M + p0, yg);
+          if constexpr (!SYM) {
+            if constexpr (WHASH)
+              probe_signs<VT, VPL>(A.seed, cc[u], p0, wg);
+            else
+              vload<VT, VPL>(W + (int64_t)cc[u] * M + p0, wg);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) yg[i] = wg[i] = VT(0);
+        }
+        if constexpr (SPMM) {
+          const VT a = ag * (VT)vv[u];
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(a, yg[i], acc[i]);
         }
         VT dp = VT(0);
 #pragma unroll
-        for (int i = 0; i < VPL; ++i) dp = fma(yown[i], wv[i], dp);
-        for (int o = 1; o < LPR; o <<= 1) dp += __shfl_xor(dp, o, 64);
-        if (cu == row) {
-          hd = true;
+        for (int i = 0; i < VPL; ++i) dp = SYM ? fma(yg[i], wown[i], dp) : fma(yown[i], wg[i], dp);
+        dot[u] = dp;
+      }
+      for (int o = 1; o < LPR; o <<= 1)
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) wdiag[i] = wv[i];
+        for (int u = 0; u < kUnroll; ++u) dot[u] += __shfl_xor(dot[u], o, 64);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (ok[u] && sub == (u & (LPR - 1))) Hacc[t0 + u] += gw * dot[u];
+    };
+
+    if (LPR >= 4) {
+      for (int64_t cb = s; cb < e; cb += LPR) {
+        const int64_t t = cb + sub;
+        int cl = 0;
+        MV vl = MV(0);
+        if (t < e) {
+          cl = ci[t];
+          vl = Val<VALT>::get(A.val, t);
         }
-        if (sub == 0) Gacc[cb + q] += gw * dp;
+        const int cnt = (int)min((int64_t)LPR, e - cb);
+        for (int q = 0; q < cnt; q += kUnroll) {
+          int cc[kUnroll];
+          MV vv[kUnroll];
+          bool ok[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            ok[u] = q + u < cnt;
+            const int srcl = gbase + ((q + u) & (LPR - 1));
+            cc[u] = __shfl(cl, srcl, 64);
+            vv[u] = __shfl(vl, srcl, 64);
+          }
+          pass(cb + q, cc, vv, ok);
+        }
+      }
+    } else {
+      for (int64_t t = s; t < e; t += kUnroll) {
+        int cc[kUnroll];
+        MV vv[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          ok[u] = t + u < e;
+          cc[u] = ok[u] ? ci[t + u] : 0;
+          vv[u] = ok[u] ? Val<VALT>::get(A.val, t + u) : MV(0);
+        }
+        pass(t, cc, vv, ok);
       }
     }
     if (has) {
-      if (!hd) {
-        if constexpr (WHASH)
-          probe_signs<VT, VPL>(A.seed, row, p0, wdiag);
-        else
-          vload<VT, VPL>(W + roff, wdiag);
-      }
       double dd = 0.0;
 #pragma unroll
-      for (int i = 0; i < VPL; ++i) dd += (double)yown[i] * (double)wdiag[i];
+      for (int i = 0; i < VPL; ++i) dd += (double)yown[i] * (double)wown[i];
       gdiag += (double)A.gw * dd;
       if constexpr (SPMM) {
         VT vv[VPL];
@@ -416,16 +499,15 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
           VT o = fma(bd, yown[i], acc[i]);
-          o = fma(cv, vv[i], o);
-          acc[i] = o;
+          acc[i] = fma(cv, vv[i], o);
         }
         if constexpr (Y2) {
           VT y2v[VPL];
-          vload<VT, VPL>(Y2p + roff, y2v);
+          vload_nt<VT, VPL>(Y2p + roff, y2v);
 #pragma unroll
           for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, y2v[i], acc[i]);
         }
-        if (pact) vstore<VT, VPL>(out + roff, acc);
+        if (pact) vstore_nt<VT, VPL>(out + roff, acc);
       }
     }
   }
@@ -439,6 +521,31 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
     for (int w = 0; w < kWaves; ++w) sum += sg[w];
     A.gdiag_part[tile] += sum;
   }
+}
+
+// perm[t] = index of the entry (col[t], row(t)); flag set when some transposed entry is missing.
+__global__ void __launch_bounds__(256) transpose_index_kernel(const int64_t* row_ptr, const int32_t* col, int64_t d,
+                                                              int64_t* perm, int* missing) {
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
+    for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t) {
+      const int64_t j = col[t];
+      int64_t found = -1;
+      for (int64_t u = row_ptr[j]; u < row_ptr[j + 1]; ++u)
+        if (col[u] == r) {
+          found = u;
+          break;
+        }
+      perm[t] = found;
+      if (found < 0) atomicOr(missing, 1);
+    }
+  }
+}
+
+template <typename TA, typename TO>
+__global__ void __launch_bounds__(256) permute_scale_kernel(const TA* a, const int64_t* perm, int64_t n, double scale,
+                                                            TO* out) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256)
+    out[t] = (TO)((double)a[perm[t]] * scale);
 }
 
 // ------------------------------------------------------------------------------------
@@ -754,48 +861,79 @@ hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int
 }
 
 template <typename VT, int VALT, int VPL>
-static hipError_t adj_by_flags(const AdjDesc& A, int M, const Shape& sh, bool spmm, bool wh, bool y2, hipStream_t s) {
+static hipError_t adj_by_flags(const AdjDesc& A, int M, const Shape& sh, bool spmm, bool wh, bool y2, bool sym,
+                               hipStream_t s) {
   const int64_t ntiles = (A.d + sh.tile_rows - 1) / sh.tile_rows;
   const int64_t per = (ntiles + 7) / 8;
   dim3 grid((unsigned)(per * 8));
-#define LD_ADJ(S_, W_, Y_)                                                                                        \
-  if (spmm == S_ && wh == W_ && y2 == Y_) {                                                                      \
-    hipLaunchKernelGGL((adjoint_kernel<VT, VALT, VPL, S_, W_, Y_>), grid, dim3(kBlock), 0, s, A, M, sh.lpr_log2, \
-                       (int64_t)sh.tile_rows, ntiles);                                                          \
+#define LD_ADJ(S_, W_, Y_, X_)                                                                                    \
+  if (spmm == S_ && wh == W_ && y2 == Y_ && sym == X_) {                                                         \
+    hipLaunchKernelGGL((adjoint_kernel<VT, VALT, VPL, S_, W_, Y_, X_>), grid, dim3(kBlock), 0, s, A, M,          \
+                       sh.lpr_log2, (int64_t)sh.tile_rows, ntiles);                                             \
     return hipGetLastError();                                                                                   \
   }
-  LD_ADJ(true, false, true)
-  LD_ADJ(true, false, false)
-  LD_ADJ(false, true, false)
+  LD_ADJ(true, false, true, false)
+  LD_ADJ(true, false, false, false)
+  LD_ADJ(false, true, false, false)
+  LD_ADJ(true, false, true, true)
+  LD_ADJ(true, false, false, true)
+  LD_ADJ(false, true, false, true)
 #undef LD_ADJ
   return hipErrorInvalidValue;
 }
 
 template <typename VT, int VALT>
-static hipError_t adj_by_vpl(const AdjDesc& A, int M, const Shape& sh, bool spmm, bool wh, bool y2, hipStream_t s) {
+static hipError_t adj_by_vpl(const AdjDesc& A, int M, const Shape& sh, bool spmm, bool wh, bool y2, bool sym,
+                             hipStream_t s) {
   switch (sh.vpl) {
-    case 1: return adj_by_flags<VT, VALT, 1>(A, M, sh, spmm, wh, y2, s);
-    case 2: return adj_by_flags<VT, VALT, 2>(A, M, sh, spmm, wh, y2, s);
+    case 1: return adj_by_flags<VT, VALT, 1>(A, M, sh, spmm, wh, y2, sym, s);
+    case 2: return adj_by_flags<VT, VALT, 2>(A, M, sh, spmm, wh, y2, sym, s);
     case 4:
-      if constexpr (sizeof(VT) == 4) return adj_by_flags<VT, VALT, 4>(A, M, sh, spmm, wh, y2, s);
+      if constexpr (sizeof(VT) == 4) return adj_by_flags<VT, VALT, 4>(A, M, sh, spmm, wh, y2, sym, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64, int valt, bool spmm, bool w_hash,
-                          bool y2, hipStream_t s) {
+                          bool y2, bool sym, hipStream_t s) {
   if (A.d <= 0) return hipSuccess;
   if (vec_f64) {
-    if (valt == VAL_F64) return adj_by_vpl<double, VAL_F64>(A, M, sh, spmm, w_hash, y2, s);
-    if (valt == VAL_F32) return adj_by_vpl<double, VAL_F32>(A, M, sh, spmm, w_hash, y2, s);
-    if (valt == VAL_BF16) return adj_by_vpl<double, VAL_BF16>(A, M, sh, spmm, w_hash, y2, s);
+    if (valt == VAL_F64) return adj_by_vpl<double, VAL_F64>(A, M, sh, spmm, w_hash, y2, sym, s);
+    if (valt == VAL_F32) return adj_by_vpl<double, VAL_F32>(A, M, sh, spmm, w_hash, y2, sym, s);
+    if (valt == VAL_BF16) return adj_by_vpl<double, VAL_BF16>(A, M, sh, spmm, w_hash, y2, sym, s);
   } else {
-    if (valt == VAL_F64) return adj_by_vpl<float, VAL_F64>(A, M, sh, spmm, w_hash, y2, s);
-    if (valt == VAL_F32) return adj_by_vpl<float, VAL_F32>(A, M, sh, spmm, w_hash, y2, s);
-    if (valt == VAL_BF16) return adj_by_vpl<float, VAL_BF16>(A, M, sh, spmm, w_hash, y2, s);
+    if (valt == VAL_F64) return adj_by_vpl<float, VAL_F64>(A, M, sh, spmm, w_hash, y2, sym, s);
+    if (valt == VAL_F32) return adj_by_vpl<float, VAL_F32>(A, M, sh, spmm, w_hash, y2, sym, s);
+    if (valt == VAL_BF16) return adj_by_vpl<float, VAL_BF16>(A, M, sh, spmm, w_hash, y2, sym, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t* perm, int* missing,
+                                  hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_index_kernel, dim3(grid_for(d, 256)), dim3(256), 0, s, row_ptr, col, d, perm, missing);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,
+                                int out_f64, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = grid_for(n, 256);
+  if (a_f64 && out_f64)
+    hipLaunchKernelGGL((permute_scale_kernel<double, double>), dim3(g), dim3(256), 0, s, (const double*)a, perm, n,
+                       scale, (double*)out);
+  else if (a_f64)
+    hipLaunchKernelGGL((permute_scale_kernel<double, float>), dim3(g), dim3(256), 0, s, (const double*)a, perm, n,
+                       scale, (float*)out);
+  else if (out_f64)
+    hipLaunchKernelGGL((permute_scale_kernel<float, double>), dim3(g), dim3(256), 0, s, (const float*)a, perm, n,
+                       scale, (double*)out);
+  else
+    hipLaunchKernelGGL((permute_scale_kernel<float, float>), dim3(g), dim3(256), 0, s, (const float*)a, perm, n,
+                       scale, (float*)out);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_moments(const double* part, int64_t ntiles, int M, int k_lo, int k_hi, int64_t kstride,
