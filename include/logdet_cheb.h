@@ -86,6 +86,7 @@ typedef struct {
     int32_t vec_f64;          /* recurrence vectors in FP64 (1) or FP32 (0) */
     int32_t ckpt_stride;      /* gradient: checkpoint every s steps; 0 = ceil(sqrt(n)) */
     int32_t tile;             /* kernel shape: 0 = autotuned, > 0 = rows per workgroup */
+    int32_t probe_tile;       /* kernel shape: 0 = autotuned, > 0 = probes per pass over the matrix */
     int32_t timing;           /* 1 = time recurrence-step kernels with HIP events on `stream` */
     double *moments_out;      /* host, nullable: M x (n+1) moments mu[j][k] = v_j^T T_k(At) v_j */
     double *probe_out;        /* host, nullable: M per-probe estimates s_j = sum_k c_k mu[j][k] */

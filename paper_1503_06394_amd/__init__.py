@@ -54,7 +54,8 @@ class _Result(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t), ("vec_f64", ctypes.c_int32),
-        ("ckpt_stride", ctypes.c_int32), ("tile", ctypes.c_int32), ("timing", ctypes.c_int32),
+        ("ckpt_stride", ctypes.c_int32), ("tile", ctypes.c_int32), ("probe_tile", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
         ("moments_out", ctypes.c_void_p), ("probe_out", ctypes.c_void_p),
     ]
 
@@ -143,10 +144,12 @@ class DeviceCSR:
                     _DTYPE[self.values.dtype], 0, float(self.diag_shift))
 
 
-def _opts(vec_f64=None, tile=0, timing=False, workspace=None, ckpt_stride=0, moments=None, probes=None):
+def _opts(vec_f64=None, tile=0, timing=False, workspace=None, ckpt_stride=0, moments=None, probes=None,
+          probe_tile=0):
     o = _Opts()
     o.vec_f64 = 0 if vec_f64 is None else (1 if vec_f64 else 2)
     o.tile = int(tile)
+    o.probe_tile = int(probe_tile)
     o.timing = 1 if timing else 0
     o.ckpt_stride = int(ckpt_stride)
     if workspace is not None:
@@ -167,13 +170,14 @@ def _result(r: _Result, rc: int) -> dict:
 
 
 def ld_logdet_cheb(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, *, vec_f64=None, tile=0,
-                   timing=False, workspace=None, want_moments=False, want_probes=False, stream=None) -> dict:
+                   probe_tile=0, timing=False, workspace=None, want_moments=False, want_probes=False,
+                   stream=None) -> dict:
     """Algorithm 1 in [a, b] form: estimate of log det(B + diag_shift I)."""
     import numpy as np
 
     mom = np.zeros((M, n + 1)) if want_moments else None
     pv = np.zeros(M) if want_probes else None
-    o = _opts(vec_f64, tile, timing, workspace, moments=mom, probes=pv)
+    o = _opts(vec_f64, tile, timing, workspace, moments=mom, probes=pv, probe_tile=probe_tile)
     r = _Result()
     cb = B.c()
     rc = _check(lib().ld_logdet_cheb(ctypes.byref(cb), float(a), float(b), int(n), int(M), int(seed) & (2**64 - 1),

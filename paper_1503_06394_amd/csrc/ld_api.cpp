@@ -156,13 +156,19 @@ double lemma_bound(double a, double b, int n, int64_t d) {
 // kernel shape planning and autotuning
 // ------------------------------------------------------------------------------------
 
-Shape base_shape(int vec_f64, int M) {
+// Lane layout for M probes: VPL consecutive probes per lane (a 16-byte vector where M
+// allows), LPR = 2^lpr_log2 lanes per row.  probe_tile > 0 narrows the group so that one
+// pass over the matrix covers only that many probes; the launch then walks the probe tiles
+// one after another (blockIdx.y), which keeps the live slice of W_k small enough to stay in
+// the Infinity Cache.
+Shape base_shape(int vec_f64, int M, int probe_tile = 0) {
   Shape sh{};
   if (!vec_f64)
     sh.vpl = (M % 4 == 0) ? 4 : ((M % 2 == 0) ? 2 : 1);
   else
     sh.vpl = (M % 2 == 0) ? 2 : 1;
-  int lanes = (M + sh.vpl - 1) / sh.vpl;
+  const int want = probe_tile > 0 ? std::min(probe_tile, M) : M;
+  int lanes = (want + sh.vpl - 1) / sh.vpl;
   int lg = 0;
   while ((1 << lg) < lanes && lg < 6) ++lg;
   sh.lpr_log2 = lg;
@@ -171,17 +177,52 @@ Shape base_shape(int vec_f64, int M) {
   return sh;
 }
 
+// Probe-tile layouts the autotuner tries: the full block and up to two narrower ones
+// (at least 16 probes and 4 lanes per row).
+std::vector<Shape> shape_candidates(int vec_f64, int M) {
+  std::vector<Shape> out;
+  const Shape full = base_shape(vec_f64, M);
+  out.push_back(full);
+  for (int drop = 1; drop <= 2; ++drop) {
+    const int lg = full.lpr_log2 - drop;
+    if (lg < 2 || ((1 << lg) * full.vpl) < 16) break;
+    out.push_back(base_shape(vec_f64, M, (1 << lg) * full.vpl));
+  }
+  return out;
+}
+
 int rows_per_iter(const Shape& sh) { return 4 * (64 >> sh.lpr_log2); }
 
-Shape with_tile(Shape sh, int64_t d, int tile_override) {
+// Largest tile height whose CSR slice fits the LDS staging buffer on average (with a
+// margin for rows longer than the mean), as a multiple of the rows one pass covers.
+int staged_tile_cap(const Shape& sh, int64_t d, int64_t nnz) {
+  const int rpi = rows_per_iter(sh);
+  const double per_row = d > 0 ? std::max(1.0, (double)nnz / (double)d) : 1.0;
+  int64_t rows = (int64_t)(0.8 * kStageNnz / per_row);
+  rows = std::min<int64_t>(rows, kStageRows);
+  rows = rows / rpi * rpi;
+  return (int)std::max<int64_t>(rows, rpi);
+}
+
+// Tile heights the autotuner tries: the staging cap and two smaller heights.
+std::vector<int> tile_candidates(const Shape& sh, int64_t d, int64_t nnz) {
+  const int rpi = rows_per_iter(sh);
+  const int cap = staged_tile_cap(sh, d, nnz);
+  std::vector<int> c;
+  for (int div : {1, 2, 4}) {
+    const int r = std::max(rpi, cap / div / rpi * rpi);
+    if (std::find(c.begin(), c.end(), r) == c.end()) c.push_back(r);
+  }
+  return c;
+}
+
+Shape with_tile(Shape sh, int64_t d, int64_t nnz, int tile_override) {
   const int rpi = rows_per_iter(sh);
   if (tile_override > 0) {
     sh.tile_rows = (tile_override + rpi - 1) / rpi * rpi;
     return sh;
   }
-  int64_t u = d / ((int64_t)rpi * 8192);
-  u = std::max<int64_t>(1, std::min<int64_t>(u, 64));
-  sh.tile_rows = (int)(rpi * u);
+  sh.tile_rows = staged_tile_cap(sh, d, nnz);
   return sh;
 }
 
@@ -193,7 +234,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;  // -> tile_rows
+std::map<TuneKey, Shape> g_tune;
 
 // LD_GRAD_SYM=0 forces the two-gather adjoint even for symmetric patterns (for testing).
 bool sym_enabled() {
@@ -206,61 +247,61 @@ bool autotune_enabled() {
   return !(e && e[0] == '0');
 }
 
-// Time the general recurrence step (k >= 2 form) for candidate tile heights on the
-// caller's data and return the fastest.  Buffers are scratch; their contents do not
-// matter for timing.
-int autotune_tile(const ld_csr* B, const Shape& base, int vec_f64, int valt, int M, void* bufA, void* bufB,
-                  double* part, hipStream_t s) {
-  const int rpi = rows_per_iter(base);
+// Time the general recurrence step (k >= 2 form) for each candidate probe-tile layout and
+// tile height on the caller's data and return the fastest.  Buffers are scratch; their
+// contents do not matter for timing.
+Shape autotune(const ld_csr* B, const std::vector<Shape>& shapes, int vec_f64, int valt, int M, void* bufA,
+               void* bufB, double* part, hipStream_t s) {
+  Shape best_sh = shapes[0];
+  best_sh.tile_rows = 0;
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return 0;
+  if (hipEventCreate(&e0) != hipSuccess) return best_sh;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
-    return 0;
+    return best_sh;
   }
   float best = 1e30f;
-  int best_rows = 0;
-  for (int u : {1, 2, 4, 8, 16, 32, 64}) {
-    Shape sh = base;
-    sh.tile_rows = rpi * u;
-    const int64_t ntiles = (B->rows + sh.tile_rows - 1) / sh.tile_rows;
-    if (ntiles < 512 && u > 1) break;  // keep the chip full
-    StepLaunch L{};
-    L.nmat = 1;
-    L.ntiles = ntiles;
-    L.tile_rows = sh.tile_rows;
-    L.M = M;
-    L.shape = sh;
-    StepDesc& D = L.d0;
-    D.row_ptr = B->row_ptr;
-    D.col = B->col_idx;
-    D.val = B->values;
-    D.G = bufA;
-    D.P = bufB;
-    D.out = bufB;
-    D.ag = 1.0;
-    D.bd = 0.0;
-    D.cp = -1.0;
-    D.d = B->rows;
-    D.mu_part = part;
-    D.active = 1;
-    float tot = 0.f;
-    bool ok = true;
-    for (int rep = 0; rep < 4 && ok; ++rep) {
-      ok = hipEventRecord(e0, s) == hipSuccess &&
-           launch_step(L, vec_f64, valt, SRC_BUF, SRC_SAME, SRC_BUF, true, s) == hipSuccess &&
-           hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-      float ms = 0.f;
-      if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && rep > 0) tot += ms;
-    }
-    if (ok && tot < best) {
-      best = tot;
-      best_rows = sh.tile_rows;
+  for (const Shape& base : shapes) {
+    for (int rows : tile_candidates(base, B->rows, B->nnz)) {
+      Shape sh = base;
+      sh.tile_rows = rows;
+      StepLaunch L{};
+      L.nmat = 1;
+      L.ntiles = (B->rows + sh.tile_rows - 1) / sh.tile_rows;
+      L.tile_rows = sh.tile_rows;
+      L.M = M;
+      L.shape = sh;
+      StepDesc& D = L.d0;
+      D.row_ptr = B->row_ptr;
+      D.col = B->col_idx;
+      D.val = B->values;
+      D.G = bufA;
+      D.P = bufB;
+      D.out = bufB;
+      D.ag = 1.0;
+      D.bd = 0.0;
+      D.cp = -1.0;
+      D.d = B->rows;
+      D.mu_part = part;
+      D.active = 1;
+      float tot = 0.f;
+      bool ok = true;
+      for (int rep = 0; rep < 4 && ok; ++rep) {
+        ok = hipEventRecord(e0, s) == hipSuccess &&
+             launch_step(L, vec_f64, valt, SRC_BUF, SRC_SAME, SRC_BUF, true, s) == hipSuccess &&
+             hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && rep > 0) tot += ms;
+      }
+      if (ok && tot < best) {
+        best = tot;
+        best_sh = sh;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return best_rows;
+  return best_sh;
 }
 
 // ------------------------------------------------------------------------------------
@@ -354,22 +395,30 @@ struct FwdPlan {
 
 FwdPlan plan_fwd(const ld_csr* B, int vec_f64, int M, const ld_opts* opt) {
   FwdPlan p;
-  p.sh = with_tile(base_shape(vec_f64, M), B->rows, opt ? opt->tile : 0);
+  p.sh = with_tile(base_shape(vec_f64, M, opt ? opt->probe_tile : 0), B->rows, B->nnz, opt ? opt->tile : 0);
   p.ntiles = B->rows > 0 ? (B->rows + p.sh.tile_rows - 1) / p.sh.tile_rows : 0;
   p.vb = vec_f64 ? 8 : 4;
   return p;
 }
 
-size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, int tile_override) {
-  ld_opts o{};
-  o.tile = tile_override;
-  FwdPlan p = plan_fwd(B, vec_f64, M, &o);
-  // worst case over autotuned tile heights: the smallest tile gives the most tiles
-  Shape small = base_shape(vec_f64, M);
-  const int64_t max_tiles = B->rows > 0 ? (B->rows + rows_per_iter(small) - 1) / rows_per_iter(small) : 0;
-  const int64_t tiles = tile_override > 0 ? p.ntiles : max_tiles;
+// Largest number of row tiles any shape the planner or the autotuner may pick produces.
+int64_t max_tiles(const ld_csr* B, int vec_f64, int M, const ld_opts* opt) {
+  if (B->rows <= 0) return 0;
+  if (opt && opt->tile > 0) return plan_fwd(B, vec_f64, M, opt).ntiles;
+  std::vector<Shape> shapes = (opt && opt->probe_tile > 0)
+                                  ? std::vector<Shape>{base_shape(vec_f64, M, opt->probe_tile)}
+                                  : shape_candidates(vec_f64, M);
+  int min_rows = 1 << 30;
+  for (const Shape& sh : shapes)
+    for (int r : tile_candidates(sh, B->rows, B->nnz)) min_rows = std::min(min_rows, r);
+  return (B->rows + min_rows - 1) / min_rows;
+}
+
+size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, const ld_opts* opt) {
+  const size_t vb = vec_f64 ? 8 : 4;
+  const int64_t tiles = max_tiles(B, vec_f64, M, opt);
   Carve c;
-  const size_t vecb = (size_t)B->rows * M * p.vb;
+  const size_t vecb = (size_t)B->rows * M * vb;
   c.take(vecb);  // A
   c.take(vecb);  // B
   if (ns) {
@@ -391,7 +440,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
   const int valt = valt_of(B->dtype);
   const int vec_f64 = vec_f64_of(opt, valt);
   const int64_t d = B->rows;
-  const size_t need = fwd_workspace(B, n, M, vec_f64, ns, opt ? opt->tile : 0);
+  const size_t need = fwd_workspace(B, n, M, vec_f64, ns, opt);
   Workspace ws;
   int rc = get_workspace(opt, need, s, ws);
   if (rc) return rc;
@@ -423,32 +472,28 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
     }
   }
   const bool tune = (!opt || opt->tile == 0) && autotune_enabled() && d >= 65536;
-  double* part_base = nullptr;
-  {
-    // partial buffer is sized for the smallest tile; carve it now
-    Shape small = base_shape(vec_f64, M);
-    const int64_t max_tiles = d > 0 ? (d + rows_per_iter(small) - 1) / rows_per_iter(small) : 0;
-    const int64_t tiles = (opt && opt->tile > 0) ? p.ntiles : max_tiles;
-    part_base = static_cast<double*>(cv.take((size_t)std::max(n, 1) * tiles * M * 8));
-  }
+  double* part_base =
+      static_cast<double*>(cv.take((size_t)std::max(n, 1) * max_tiles(B, vec_f64, M, opt) * M * 8));
   double* mu_dev = static_cast<double*>(cv.take((size_t)M * (n + 1) * 8));
 
   if (tune && !ns) {
-    TuneKey key{vec_f64, valt, M, 0, d, B->nnz};
-    int rows = 0;
+    TuneKey key{vec_f64, valt, M, opt ? opt->probe_tile : 0, d, B->nnz};
+    Shape sh{};
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       auto it = g_tune.find(key);
-      if (it != g_tune.end()) rows = it->second;
+      if (it != g_tune.end()) sh = it->second;
     }
-    if (!rows) {
-      rows = autotune_tile(B, p.sh, vec_f64, valt, M, bufA, bufB, part_base, s);
+    if (!sh.tile_rows) {
+      const std::vector<Shape> shapes = (opt && opt->probe_tile > 0) ? std::vector<Shape>{p.sh}
+                                                                      : shape_candidates(vec_f64, M);
+      sh = autotune(B, shapes, vec_f64, valt, M, bufA, bufB, part_base, s);
       std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune[key] = rows;
+      g_tune[key] = sh;
     }
-    if (rows > 0) {
-      p.sh.tile_rows = rows;
-      p.ntiles = (d + rows - 1) / rows;
+    if (sh.tile_rows > 0) {
+      p.sh = sh;
+      p.ntiles = (d + sh.tile_rows - 1) / sh.tile_rows;
     }
   }
 
@@ -571,7 +616,7 @@ GradPlan plan_grad(int n, int stride) {
 size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, int stride) {
   const size_t vb = vec_f64 ? 8 : 4;
   GradPlan g = plan_grad(n, stride);
-  Shape sh = with_tile(base_shape(vec_f64, M), B->rows, 0);
+  Shape sh = with_tile(base_shape(vec_f64, M), B->rows, B->nnz, 0);
   const int64_t ntiles = B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
   Carve c;
   const size_t vecb = (size_t)B->rows * M * vb;
@@ -755,7 +800,7 @@ size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) 
   o.vec_f64 = vec_f64 ? 1 : 2;
   const int v64 = vec_f64_of(&o, valt);
   if (mode == 2) return grad_workspace(B, n, M, v64, 0);
-  return fwd_workspace(B, n, M, v64, mode == 1, 0);
+  return fwd_workspace(B, n, M, v64, mode == 1, nullptr);
 }
 
 int ld_logdet_cheb(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
@@ -879,7 +924,7 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   const int vec_f64 = vec_f64_of(opt, valt);
   const int64_t d = B->rows;
   const size_t vb = vec_f64 ? 8 : 4;
-  Shape sh = with_tile(base_shape(vec_f64, M), d, 0);
+  Shape sh = with_tile(base_shape(vec_f64, M), d, B->nnz, 0);
   if (sh.probe_tiles != 1)
     return fail(LD_EINVAL, "gradient needs M <= %d probes per call with these vectors", (1 << sh.lpr_log2) * sh.vpl);
   const int64_t ntiles = d > 0 ? (d + sh.tile_rows - 1) / sh.tile_rows : 0;
@@ -1078,7 +1123,12 @@ int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const d
   const int vec_f64 = vec_f64_of(opt, valt);
   Shape sh = base_shape(vec_f64, M);
   const int rpi = rows_per_iter(sh);
-  const int tile = (opt && opt->tile > 0) ? opt->tile : rpi * 16;
+  int64_t tot_d = 0, tot_nnz = 0;
+  for (int i = 0; i < count; ++i) {
+    tot_d += Bs[i].rows;
+    tot_nnz += Bs[i].nnz;
+  }
+  const int tile = (opt && opt->tile > 0) ? opt->tile : staged_tile_cap(sh, tot_d, tot_nnz);
   sh.tile_rows = (tile + rpi - 1) / rpi * rpi;
 
   std::vector<double> key = {(double)count, (double)M, (double)(seed >> 32), (double)(seed & 0xffffffffu),

@@ -60,6 +60,11 @@ struct StepLaunch {
   Shape shape;
 };
 
+// Capacity of the LDS copy of a row tile's CSR slice (rows, nonzeros).  Tiles larger than
+// this still work but read their slice from global memory.
+constexpr int kStageRows = 1024;
+constexpr int kStageNnz = 2048;
+
 // Value type tags
 enum ValT : int { VAL_F64 = 0, VAL_F32 = 1, VAL_BF16 = 2 };
 

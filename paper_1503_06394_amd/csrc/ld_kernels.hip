@@ -151,6 +151,37 @@ constexpr int kUnroll = LD_UNROLL;  // nonzeros whose gathers are in flight toge
 // fused recurrence step
 // ------------------------------------------------------------------------------------
 
+// The CSR slice of a row tile (row offsets, column indices, values) is staged in LDS once
+// per workgroup: after that a row pass waits on a single global round trip, its gathers.
+// Tiles whose slice does not fit (unusually long rows) read the slice from global memory.
+template <int VALT>
+struct TileCsr {
+  typedef typename Val<VALT>::T MV;
+  int rp[kStageRows + 1];
+  int col[kStageNnz];
+  MV val[kStageNnz];
+};
+
+// Loads the tile's slice into LDS if it fits; returns whether it did.  All threads call it.
+template <int VALT>
+__device__ __forceinline__ bool stage_tile(TileCsr<VALT>& T, const int64_t* rp, const int32_t* ci, const void* val,
+                                           int64_t row0, int64_t row_end, int64_t& nz0) {
+  nz0 = rp[row0];
+  const int64_t nz1 = rp[row_end];
+  const int nrows = (int)(row_end - row0);
+  const bool fits = (nz1 - nz0) <= kStageNnz && nrows <= kStageRows;
+  if (fits) {
+    for (int i = threadIdx.x; i <= nrows; i += kBlock) T.rp[i] = (int)(rp[row0 + i] - nz0);
+    const int nnz = (int)(nz1 - nz0);
+    for (int i = threadIdx.x; i < nnz; i += kBlock) {
+      T.col[i] = ci[nz0 + i];
+      T.val[i] = Val<VALT>::get(val, nz0 + i);
+    }
+  }
+  __syncthreads();
+  return fits;
+}
+
 template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, bool MU>
 __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   typedef typename Val<VALT>::T MV;
@@ -169,7 +200,6 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   const int RPW = 64 >> lg;
   const int sub = lane & (LPR - 1);
   const int grp = lane >> lg;
-  const int gbase = lane & ~(LPR - 1);
   const int M = L.M;
   const int tile_probes = LPR * VPL;
   int p0 = (int)blockIdx.y * tile_probes + sub * VPL;
@@ -184,6 +214,10 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   const int64_t* __restrict__ rp = D.row_ptr;
   const int32_t* __restrict__ ci = D.col;
 
+  __shared__ TileCsr<VALT> T;
+  int64_t nz0;
+  const bool staged = stage_tile<VALT>(T, rp, ci, D.val, row0, row_end, nz0);
+
   double mu[VPL];
 #pragma unroll
   for (int i = 0; i < VPL; ++i) mu[i] = 0.0;
@@ -191,19 +225,64 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
     const int64_t row = base + grp;
     const bool has = row < row_end;
-    int64_t s = 0, e = 0;
+    const int lr = (int)(row - row0);
+    int64_t s = 0, e = 0;  // entry range relative to nz0
     if (has) {
-      s = rp[row];
-      e = rp[row + 1];
+      if (staged) {
+        s = T.rp[lr];
+        e = T.rp[lr + 1];
+      } else {
+        s = rp[row] - nz0;
+        e = rp[row + 1] - nz0;
+      }
     }
+    const int64_t off = (has ? row : row0) * (int64_t)M + p0;
+    // streamed operands first, so their latency overlaps the gathers
+    VT pv[VPL];
+    if constexpr (PSRC == SRC_BUF) {
+      if (has) vload_nt<VT, VPL>(P + off, pv);
+    } else if constexpr (PSRC == SRC_HASH) {
+      probe_signs<VT, VPL>(D.seed, row, p0, pv);
+    }
+    VT dv[VPL];
+    if constexpr (DSRC == SRC_BUF) {
+      if (has) vload<VT, VPL>(Dv + off, dv);
+    } else if constexpr (DSRC == SRC_HASH) {
+      probe_signs<VT, VPL>(D.seed, row, p0, dv);
+    }
+
     VT acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
     bool hd = false;
-
-    // Gather kUnroll rows of G (or probe rows) per pass; padding slots (past the row's end)
-    // issue no load and contribute nothing.
-    auto gather_pass = [&](const int* cc, const VT* aa, const bool* ok) {
+    for (int64_t t = s; t < e; t += kUnroll) {
+      int cc[kUnroll];
+      VT aa[kUnroll];
+      bool ok[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        ok[u] = t + u < e;
+        int cu = 0;
+        MV vu = MV(0);
+        if (ok[u]) {
+          if (staged) {
+            cu = T.col[t + u];
+            vu = T.val[t + u];
+          } else {
+            cu = ci[nz0 + t + u];
+            vu = Val<VALT>::get(D.val, nz0 + t + u);
+          }
+        }
+        VT a = ag * (VT)vu;
+        if constexpr (DSRC == SRC_SAME) {
+          if (ok[u] && cu == row) {
+            a += bd;
+            hd = true;
+          }
+        }
+        aa[u] = a;
+        cc[u] = cu;
+      }
       VT gg[kUnroll][VPL];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -221,97 +300,24 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
       for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
-    };
-
-    if (LPR >= 4) {
-      // cooperative: lane `sub` of the group loads entry cb + sub of the row
-      for (int64_t cb = s; cb < e; cb += LPR) {
-        const int64_t t = cb + sub;
-        int cl = 0;
-        MV vl = MV(0);
-        if (t < e) {
-          cl = ci[t];
-          vl = Val<VALT>::get(D.val, t);
-        }
-        const int cnt = (int)min((int64_t)LPR, e - cb);
-        for (int q = 0; q < cnt; q += kUnroll) {
-          int cc[kUnroll];
-          VT aa[kUnroll];
-          bool ok[kUnroll];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            ok[u] = q + u < cnt;
-            const int srcl = gbase + ((q + u) & (LPR - 1));
-            const int cu = __shfl(cl, srcl, 64);
-            const MV vu = __shfl(vl, srcl, 64);
-            VT a = ok[u] ? ag * (VT)vu : VT(0);
-            if constexpr (DSRC == SRC_SAME) {
-              if (ok[u] && cu == row) {
-                a += bd;
-                hd = true;
-              }
-            }
-            aa[u] = a;
-            cc[u] = cu;
-          }
-          gather_pass(cc, aa, ok);
-        }
-      }
-    } else {
-      // narrow groups: every lane reads the row's entries itself
-      for (int64_t t = s; t < e; t += kUnroll) {
-        int cc[kUnroll];
-        VT aa[kUnroll];
-        bool ok[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          ok[u] = t + u < e;
-          const int cu = ok[u] ? ci[t + u] : 0;
-          VT a = ok[u] ? ag * (VT)Val<VALT>::get(D.val, t + u) : VT(0);
-          if constexpr (DSRC == SRC_SAME) {
-            if (ok[u] && cu == row) {
-              a += bd;
-              hd = true;
-            }
-          }
-          aa[u] = a;
-          cc[u] = cu;
-        }
-        gather_pass(cc, aa, ok);
-      }
     }
 
     if (has) {
-      const int64_t off = row * (int64_t)M + p0;
       if constexpr (DSRC == SRC_SAME) {
         if (!hd) {  // pattern without a stored diagonal in this row
-          VT dv[VPL];
+          VT g[VPL];
           if constexpr (GSRC == SRC_BUF)
-            vload<VT, VPL>(G + off, dv);
+            vload<VT, VPL>(G + off, g);
           else
-            probe_signs<VT, VPL>(D.seed, row, p0, dv);
+            probe_signs<VT, VPL>(D.seed, row, p0, g);
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, g[i], acc[i]);
         }
-      } else if constexpr (DSRC == SRC_BUF) {
-        VT dv[VPL];
-        vload<VT, VPL>(Dv + off, dv);
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
-      } else if constexpr (DSRC == SRC_HASH) {
-        VT dv[VPL];
-        probe_signs<VT, VPL>(D.seed, row, p0, dv);
+      } else if constexpr (DSRC != SRC_NONE) {
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
       }
-      if constexpr (PSRC == SRC_BUF) {
-        VT pv[VPL];
-        vload_nt<VT, VPL>(P + off, pv);
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
-      } else if constexpr (PSRC == SRC_HASH) {
-        VT pv[VPL];
-        probe_signs<VT, VPL>(D.seed, row, p0, pv);
+      if constexpr (PSRC != SRC_NONE) {
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
       }
@@ -376,7 +382,6 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
   const int RPW = 64 >> lpr_log2;
   const int sub = lane & (LPR - 1);
   const int grp = lane >> lpr_log2;
-  const int gbase = lane & ~(LPR - 1);
   int p0 = sub * VPL;
   const bool pact = p0 < M;
   if (!pact) p0 = 0;
@@ -390,14 +395,23 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
   const int64_t* __restrict__ rp = A.row_ptr;
   const int32_t* __restrict__ ci = A.col;
 
+  __shared__ TileCsr<VALT> T;
+  int64_t nz0;
+  const bool staged = stage_tile<VALT>(T, rp, ci, A.val, row0, row_end, nz0);
+
   double gdiag = 0.0;
   for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
     const int64_t row = base + grp;
     const bool has = row < row_end;
-    int64_t s = 0, e = 0;
+    int64_t s = 0, e = 0;  // entry range relative to nz0
     if (has) {
-      s = rp[row];
-      e = rp[row + 1];
+      if (staged) {
+        s = T.rp[row - row0];
+        e = T.rp[row - row0 + 1];
+      } else {
+        s = rp[row] - nz0;
+        e = rp[row + 1] - nz0;
+      }
     }
     const int64_t roff = (has ? row : row0) * (int64_t)M + p0;
     VT yown[VPL], wown[VPL];
@@ -414,8 +428,25 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
 
-    // one pass over up to kUnroll nonzeros starting at entry index t0
-    auto pass = [&](int64_t t0, const int* cc, const MV* vv, const bool* ok) {
+    for (int64_t t = s; t < e; t += kUnroll) {
+      int cc[kUnroll];
+      MV vv[kUnroll];
+      bool ok[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        ok[u] = t + u < e;
+        cc[u] = 0;
+        vv[u] = MV(0);
+        if (ok[u]) {
+          if (staged) {
+            cc[u] = T.col[t + u];
+            vv[u] = T.val[t + u];
+          } else {
+            cc[u] = ci[nz0 + t + u];
+            vv[u] = Val<VALT>::get(A.val, nz0 + t + u);
+          }
+        }
+      }
       VT dot[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -447,46 +478,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
         for (int u = 0; u < kUnroll; ++u) dot[u] += __shfl_xor(dot[u], o, 64);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
-        if (ok[u] && sub == (u & (LPR - 1))) Hacc[t0 + u] += gw * dot[u];
-    };
-
-    if (LPR >= 4) {
-      for (int64_t cb = s; cb < e; cb += LPR) {
-        const int64_t t = cb + sub;
-        int cl = 0;
-        MV vl = MV(0);
-        if (t < e) {
-          cl = ci[t];
-          vl = Val<VALT>::get(A.val, t);
-        }
-        const int cnt = (int)min((int64_t)LPR, e - cb);
-        for (int q = 0; q < cnt; q += kUnroll) {
-          int cc[kUnroll];
-          MV vv[kUnroll];
-          bool ok[kUnroll];
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            ok[u] = q + u < cnt;
-            const int srcl = gbase + ((q + u) & (LPR - 1));
-            cc[u] = __shfl(cl, srcl, 64);
-            vv[u] = __shfl(vl, srcl, 64);
-          }
-          pass(cb + q, cc, vv, ok);
-        }
-      }
-    } else {
-      for (int64_t t = s; t < e; t += kUnroll) {
-        int cc[kUnroll];
-        MV vv[kUnroll];
-        bool ok[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          ok[u] = t + u < e;
-          cc[u] = ok[u] ? ci[t + u] : 0;
-          vv[u] = ok[u] ? Val<VALT>::get(A.val, t + u) : MV(0);
-        }
-        pass(t, cc, vv, ok);
-      }
+        if (ok[u] && sub == (u & (LPR - 1))) Hacc[nz0 + t + u] += gw * dot[u];
     }
     if (has) {
       double dd = 0.0;

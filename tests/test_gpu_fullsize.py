@@ -1,0 +1,98 @@
+"""Parity at the full benchmark sizes, in the launch configuration the benchmark uses.
+
+The oracle cannot redo a whole full-size run in test time, so these tests compare outputs it
+can compute one at a time: per-probe estimates s_j for sampled probes (each probe is an
+independent pass of Algorithm 1), a directional derivative of the gradient (by central
+differences of the oracle's estimate along the diagonal shift), and per-matrix estimates
+of sampled members of the batch.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from tests._gpu import FLOOR, dev, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_1503_06394_amd as pkg
+
+    pkg.lib()
+    return pkg
+
+
+def _probe_parity(ld, oracle_lib, B, shift, a, b, n, M, seed, probes, label):
+    D = dev(B, shift=shift)
+    say(f"full size {label}: GPU forward d={B.d} nnz={B.nnz} M={M} n={n}")
+    r = ld.ld_logdet_cheb(D, a, b, n, M, seed, want_probes=True)
+    for j in probes:
+        say(f"full size {label}: oracle probe {j}")
+        o = oracle_lib.logdet(B, a, b, n, 1, seed=seed, ids=np.array([j]), shift=shift)
+        assert rel(r["s"][j], o["s"][0], FLOOR * B.d) <= TOL32, (label, j, r["s"][j], o["s"][0])
+    return r
+
+
+def test_random_1m_fp32_probes(ld, oracle_lib):
+    """d = 1e6 random sparse SPD (Gershgorin bounds), FP32, M = 64 in one block, n = 50."""
+    B = synth.random_sparse_spd(1_000_000, 5, 2, 1.0, "f32")
+    a, b = oracle_lib.gershgorin(B)
+    r = _probe_parity(ld, oracle_lib, B, 0.0, a, b, 50, 64, 2, [0, 37, 63], "random1m")
+    assert r["status"] == 0
+
+
+@pytest.mark.timeout(600)
+def test_grid_4096_bf16_probe(ld, oracle_lib):
+    """4096 x 4096 Dirichlet grid (d = 16.8M), BF16 values with the 0.01 shift in FP64, FP32
+    recurrence, M = 32, n = 100."""
+    B = synth.grid_laplacian_2d(4096, "bf16")
+    r = _probe_parity(ld, oracle_lib, B, 0.01, 0.01, 8.01, 100, 32, 5, [0], "grid4096")
+    assert r["status"] == 0
+
+
+@pytest.mark.timeout(900)
+def test_gmrf_128_fwd_grad(ld, oracle_lib):
+    """3-D GMRF 128^3 (d = 2.1M), tau = 1, kappa = 0.3, FP32, M = 32, n = 60: sampled probes of the
+    forward, and d Gamma / d shift of the gradient call against central differences of the
+    oracle's estimate with the same 32 probes."""
+    B = synth.grid_laplacian_3d(128, "f32")
+    shift, a, b, n, M, seed = 0.09, 0.09, 12.09, 60, 32, 3
+    _probe_parity(ld, oracle_lib, B, shift, a, b, n, M, seed, [0, 31], "gmrf128")
+    say("full size gmrf128: GPU gradient")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a, b, n, M, seed)
+    # every row stores its diagonal: the diagonal entries of the gradient sum to d/dshift
+    rows = B.row_of_entry()
+    diag = g.double().cpu().numpy()[B.col == rows].sum()
+    assert rel(diag, r["grad_shift"]) <= TOL32
+    h = 1e-3
+    say("full size gmrf128: oracle central differences along the shift")
+    fp = oracle_lib.logdet(B, a, b, n, M, seed=seed, shift=shift + h)["gamma"]
+    fm = oracle_lib.logdet(B, a, b, n, M, seed=seed, shift=shift - h)["gamma"]
+    fd = (fp - fm) / (2 * h)
+    assert rel(r["grad_shift"], fd) <= TOL32, (r["grad_shift"], fd)
+
+
+@pytest.mark.timeout(600)
+def test_batch_256_sampled(ld, oracle_lib):
+    """256 random SPD matrices, d log-uniform in [1e3, 2e5], 5-20 stored entries per row, own
+    Gershgorin bounds and degree n in [20, 80], M = 32, one captured graph; sampled members
+    against the oracle."""
+    mats = synth.random_batch(256, mseed0=1000)
+    ab = [oracle_lib.gershgorin(B) for B in mats]
+    ns = [B.meta["n"] for B in mats]
+    D = [dev(B) for B in mats]
+    say(f"full batch: {len(mats)} matrices, total d={sum(B.d for B in mats)}")
+    res = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, 32, 4)
+    order = np.argsort([B.d for B in mats])
+    for i in [int(order[0]), int(order[1]), int(order[128]), int(order[-1])]:
+        say(f"full batch: oracle for member {i} (d={mats[i].d}, n={ns[i]})")
+        o = oracle_lib.logdet(mats[i], ab[i][0], ab[i][1], ns[i], 32, seed=4 + i)
+        assert rel(res[i]["logdet"], o["gamma"], FLOOR * mats[i].d) <= TOL32, i
