@@ -88,13 +88,18 @@ typedef struct {
     int32_t tile;             /* kernel shape: 0 = autotuned, > 0 = rows per workgroup */
     int32_t probe_tile;       /* kernel shape: 0 = autotuned, > 0 = probes per pass over the matrix */
     int32_t timing;           /* 1 = time recurrence-step kernels with HIP events on `stream` */
+    int32_t plain_recurrence; /* 1 = one sparse product per degree (Algorithm 1's loop as written);
+                                 0 = ceil(n/2) products: moments 2k and 2k+1 from the Chebyshev
+                                 product identities T_2k = 2 T_k^2 - T_0, T_2k+1 = 2 T_k+1 T_k - T_1
+                                 (needs a symmetric matrix; same estimate up to rounding) */
     double *moments_out;      /* host, nullable: M x (n+1) moments mu[j][k] = v_j^T T_k(At) v_j */
     double *probe_out;        /* host, nullable: M per-probe estimates s_j = sum_k c_k mu[j][k] */
 } ld_opts;
 
-/* Algorithm 1 in the [a, b] form: estimate log det(B + diag_shift I).
+/* Algorithm 1 in the [a, b] form: estimate log det(B + diag_shift I) for a symmetric B.
  * Requires 0 < a < b finite, n >= 0, 1 <= M <= 4096.  With vec_f64 = 0 the recurrence runs
- * in FP32 and the moments, coefficients and final sum in FP64. */
+ * in FP32 and the moments, coefficients and final sum in FP64.  By default the moments
+ * v^T T_k(At) v come from ceil(n/2) sparse products (see ld_opts.plain_recurrence). */
 int ld_logdet_cheb(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
                    const ld_opts *opt, void *stream, ld_result *out);
 
@@ -107,8 +112,12 @@ int ld_logabsdet_cheb(const ld_csr *C, const ld_csr *Ct, double smin, double sma
                       uint64_t seed, const ld_opts *opt, void *stream, ld_result *out);
 
 /* Gradient of the ld_logdet_cheb estimate (same B, a, b, n, M, seed, with a and b held
- * fixed) with respect to every stored entry of B, scaled by grad_output:
- *     grad_values[t] = grad_output * dGamma/dB_{row(t), col(t)}.
+ * fixed) with respect to every stored entry of B, scaled by grad_output.  B is symmetric, so
+ * for a symmetric pattern each stored entry receives the derivative along symmetric
+ * perturbations,
+ *     grad_values[t] = grad_output * (dGamma/dB_ij + dGamma/dB_ji) / 2,  (i, j) = entry t,
+ * the same for both orientations of a pair; for a pattern without its transpose the plain
+ * recurrence runs and grad_values[t] = grad_output * dGamma/dB_ij.
  * The adjoint recurrence y_k = c_k v + 2 At y_{k+1} - y_{k+2} runs backwards over
  * segments recomputed from checkpoints every ckpt_stride steps.  grad_values is a device
  * array of nnz elements of type grad_dtype (LD_F64 or LD_F32).  out->grad_shift receives

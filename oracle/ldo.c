@@ -328,6 +328,9 @@ int ldo_logabsdet(const ldo_csr *C, double smin, double smax, int n, int m,
 /* ------------------------------------------------------------------------- */
 /* Gradient (not in the paper; reverse mode through Algorithm 1)              */
 /* ------------------------------------------------------------------------- */
+/* The recurrence evaluates v^T p(X) v for any square X, so this is the derivative with
+ * respect to independent entries; at a symmetric X it is itself symmetric, i.e. it is also
+ * the derivative along symmetric perturbations. */
 /*
  * Per probe v the estimate is s = v^T u with u = sum_k c_k w_k, w_0 = v, w_1 = X v and
  * w_k = 2 X w_{k-1} - w_{k-2}.  With y_k = ds/dw_k (X symmetric):

@@ -88,9 +88,10 @@ int ldo_logdet(const ldo_csr *B, double shift, double a, double b, int n, int m,
 int ldo_logabsdet(const ldo_csr *C, double smin, double smax, int n, int m,
                   const ldo_probes *probes, double *gamma, double *s);
 
-/* Gradient of the ldo_logdet estimate with respect to every stored entry of B (and to
- * the diagonal shift), at fixed a, b and probes, by reverse-mode differentiation of
- * Algorithm 1's recurrence.  grad: nnz entries; grad_shift: nullable; gamma: nullable. */
+/* Gradient of the ldo_logdet estimate with respect to every stored entry of B (and to the
+ * diagonal shift), at fixed a, b and probes, by reverse-mode differentiation of Algorithm 1's
+ * recurrence (entries treated as independent; for symmetric B the result is symmetric).
+ * grad: nnz entries; grad_shift: nullable; gamma: nullable. */
 int ldo_logdet_grad(const ldo_csr *B, double shift, double a, double b, int n, int m,
                     const ldo_probes *probes, double *grad, double *grad_shift, double *gamma);
 

@@ -55,7 +55,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t), ("vec_f64", ctypes.c_int32),
         ("ckpt_stride", ctypes.c_int32), ("tile", ctypes.c_int32), ("probe_tile", ctypes.c_int32),
-        ("timing", ctypes.c_int32),
+        ("timing", ctypes.c_int32), ("plain_recurrence", ctypes.c_int32),
         ("moments_out", ctypes.c_void_p), ("probe_out", ctypes.c_void_p),
     ]
 
@@ -145,8 +145,9 @@ class DeviceCSR:
 
 
 def _opts(vec_f64=None, tile=0, timing=False, workspace=None, ckpt_stride=0, moments=None, probes=None,
-          probe_tile=0):
+          probe_tile=0, plain=False):
     o = _Opts()
+    o.plain_recurrence = 1 if plain else 0
     o.vec_f64 = 0 if vec_f64 is None else (1 if vec_f64 else 2)
     o.tile = int(tile)
     o.probe_tile = int(probe_tile)
@@ -171,13 +172,13 @@ def _result(r: _Result, rc: int) -> dict:
 
 def ld_logdet_cheb(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, *, vec_f64=None, tile=0,
                    probe_tile=0, timing=False, workspace=None, want_moments=False, want_probes=False,
-                   stream=None) -> dict:
+                   plain=False, stream=None) -> dict:
     """Algorithm 1 in [a, b] form: estimate of log det(B + diag_shift I)."""
     import numpy as np
 
     mom = np.zeros((M, n + 1)) if want_moments else None
     pv = np.zeros(M) if want_probes else None
-    o = _opts(vec_f64, tile, timing, workspace, moments=mom, probes=pv, probe_tile=probe_tile)
+    o = _opts(vec_f64, tile, timing, workspace, moments=mom, probes=pv, probe_tile=probe_tile, plain=plain)
     r = _Result()
     cb = B.c()
     rc = _check(lib().ld_logdet_cheb(ctypes.byref(cb), float(a), float(b), int(n), int(M), int(seed) & (2**64 - 1),
@@ -191,12 +192,13 @@ def ld_logdet_cheb(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, 
 
 
 def ld_logabsdet_cheb(C: DeviceCSR, Ct: DeviceCSR | None, smin: float, smax: float, n: int, M: int, seed: int, *,
-                      vec_f64=None, tile=0, timing=False, workspace=None, want_probes=False, stream=None) -> dict:
+                      vec_f64=None, tile=0, timing=False, workspace=None, want_probes=False, plain=False,
+                      stream=None) -> dict:
     """Algorithm 2: estimate of log|det C| = (1/2) log det(C^T C)."""
     import numpy as np
 
     pv = np.zeros(M) if want_probes else None
-    o = _opts(vec_f64, tile, timing, workspace, probes=pv)
+    o = _opts(vec_f64, tile, timing, workspace, probes=pv, plain=plain)
     r = _Result()
     cc = C.c()
     ct = Ct.c() if Ct is not None else None
@@ -211,16 +213,18 @@ def ld_logabsdet_cheb(C: DeviceCSR, Ct: DeviceCSR | None, smin: float, smax: flo
 
 def ld_logdet_cheb_grad(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, grad_output: float = 1.0, *,
                         grad_dtype: torch.dtype | None = None, vec_f64=None, ckpt_stride=0, tile=0, timing=False,
-                        workspace=None, stream=None) -> tuple:
+                        workspace=None, plain=False, stream=None) -> tuple:
     """Gradient of the Algorithm 1 estimate w.r.t. the stored entries of B (a, b fixed).
 
-    Returns (result dict with 'logdet' and 'grad_shift', grad tensor of length nnz)."""
+    For a symmetric pattern the value per stored entry is the derivative along symmetric
+    perturbations, (dGamma/dB_ij + dGamma/dB_ji)/2.  Returns (result dict with 'logdet' and
+    'grad_shift', grad tensor of length nnz)."""
     if grad_dtype is None:
         grad_dtype = torch.float64 if B.values.dtype == torch.float64 else torch.float32
     if grad_dtype not in (torch.float64, torch.float32):
         raise LogdetChebError("grad_dtype must be float64 or float32")
     grad = torch.empty(B.nnz, dtype=grad_dtype, device=B.values.device)
-    o = _opts(vec_f64, tile, timing, workspace, ckpt_stride=ckpt_stride)
+    o = _opts(vec_f64, tile, timing, workspace, ckpt_stride=ckpt_stride, plain=plain)
     r = _Result()
     cb = B.c()
     rc = _check(lib().ld_logdet_cheb_grad(ctypes.byref(cb), float(a), float(b), int(n), int(M),
@@ -231,7 +235,7 @@ def ld_logdet_cheb_grad(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: 
 
 
 def ld_logdet_cheb_batched(mats: list, a, b, n, M: int, seed: int, *, vec_f64=None, tile=0, timing=False,
-                           stream=None) -> list:
+                           plain=False, stream=None) -> list:
     """Batched Algorithm 1: matrix i uses [a[i], b[i]], degree n[i] and probe seed seed + i."""
     count = len(mats)
     arr = (_CSR * count)(*[m.c() for m in mats])
@@ -239,7 +243,7 @@ def ld_logdet_cheb_batched(mats: list, a, b, n, M: int, seed: int, *, vec_f64=No
     bv = (ctypes.c_double * count)(*[float(x) for x in b])
     nv = (ctypes.c_int * count)(*[int(x) for x in n])
     res = (_Result * count)()
-    o = _opts(vec_f64, tile, timing)
+    o = _opts(vec_f64, tile, timing, plain=plain)
     rc = _check(lib().ld_logdet_cheb_batched(count, arr, av, bv, nv, int(M), int(seed) & (2**64 - 1),
                                              ctypes.byref(o), _stream_ptr(stream), res), "ld_logdet_cheb_batched")
     return [_result(res[i], rc) for i in range(count)]

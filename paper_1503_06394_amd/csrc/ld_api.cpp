@@ -250,8 +250,8 @@ bool autotune_enabled() {
 // Time the general recurrence step (k >= 2 form) for each candidate probe-tile layout and
 // tile height on the caller's data and return the fastest.  Buffers are scratch; their
 // contents do not matter for timing.
-Shape autotune(const ld_csr* B, const std::vector<Shape>& shapes, int vec_f64, int valt, int M, void* bufA,
-               void* bufB, double* part, hipStream_t s) {
+Shape autotune(const ld_csr* B, const std::vector<Shape>& shapes, int vec_f64, int valt, int M, int mu_mode,
+               void* bufA, void* bufB, double* part, hipStream_t s) {
   Shape best_sh = shapes[0];
   best_sh.tile_rows = 0;
   hipEvent_t e0, e1;
@@ -283,12 +283,13 @@ Shape autotune(const ld_csr* B, const std::vector<Shape>& shapes, int vec_f64, i
       D.cp = -1.0;
       D.d = B->rows;
       D.mu_part = part;
+      D.mu_part2 = part;  // timing only: both partial slots may overlap
       D.active = 1;
       float tot = 0.f;
       bool ok = true;
       for (int rep = 0; rep < 4 && ok; ++rep) {
         ok = hipEventRecord(e0, s) == hipSuccess &&
-             launch_step(L, vec_f64, valt, SRC_BUF, SRC_SAME, SRC_BUF, true, s) == hipSuccess &&
+             launch_step(L, vec_f64, valt, SRC_BUF, SRC_SAME, SRC_BUF, mu_mode, s) == hipSuccess &&
              hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
         float ms = 0.f;
         if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && rep > 0) tot += ms;
@@ -383,6 +384,38 @@ int vec_f64_of(const ld_opts* opt, int valt) {
   return opt->vec_f64 == 1 ? 1 : 0;
 }
 
+// Product identities (default) or one sparse product per degree.
+bool use_pairs(const ld_opts* opt) { return !(opt && opt->plain_recurrence); }
+
+// Sparse products per probe block: n, or ceil(n/2) with the product identities.
+int steps_for(int n, bool pair) { return pair ? (n + 1) / 2 : n; }
+
+// Partial rows written: one per step, or two per step (W_k^T W_{k+1}, W_{k+1}^T W_{k+1}).
+int partial_rows(int n, bool pair) { return pair ? 2 * steps_for(n, pair) : n; }
+
+// Moments mu[j][0..n] (M x (n+1)) from the reduced partial rows red[j][0..nrows).
+// Plain: row k holds v^T W_{k+1}.  Pairs: row 2k holds a_k = W_k^T W_{k+1}, row 2k+1 holds
+// b_k = W_{k+1}^T W_{k+1} (W_0 = v); with T_{2k+2} = 2 T_{k+1}^2 - T_0 and
+// T_{2k+1} = 2 T_{k+1} T_k - T_1 for symmetric At:
+//   mu_1 = a_0,  mu_{2k+2} = 2 b_k - d,  mu_{2k+1} = 2 a_k - mu_1 (k >= 1).
+void assemble_moments(const std::vector<double>& red, int nrows, bool pair, int n, int M, int64_t d,
+                      std::vector<double>& mu) {
+  for (int j = 0; j < M; ++j) {
+    double* m = &mu[(size_t)j * (n + 1)];
+    const double* r = red.data() + (size_t)j * std::max(nrows, 1);
+    m[0] = (double)d;  // v^T v = d for Rademacher probes
+    if (!pair) {
+      for (int k = 1; k <= n; ++k) m[k] = r[k - 1];
+      continue;
+    }
+    if (n >= 1) m[1] = r[0];
+    for (int k = 0; 2 * k + 1 < nrows; ++k) {
+      if (2 * k + 2 <= n) m[2 * k + 2] = 2.0 * r[2 * k + 1] - (double)d;
+      if (k >= 1 && 2 * k + 1 <= n) m[2 * k + 1] = 2.0 * r[2 * k] - m[1];
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Algorithm 1 / Algorithm 2 forward driver
 // ------------------------------------------------------------------------------------
@@ -429,8 +462,10 @@ size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, const 
     c.take((size_t)B->rows * 8);                    // cursor
     c.take(transpose_scratch_bytes(B->rows));
   }
-  c.take((size_t)std::max(n, 1) * tiles * M * 8);  // partials for degrees 1..n
-  c.take((size_t)M * (n + 1) * 8);                 // moments
+  const int rows = std::max(partial_rows(n, use_pairs(opt)), 1);
+  c.take((size_t)rows * tiles * M * 8);  // per-tile partials
+  c.take((size_t)M * rows * 8);          // reduced partials
+  c.take(reduce_scratch_bytes(rows, M));  // reduction stage 1
   return align_up(c.off);
 }
 
@@ -440,6 +475,9 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
   const int valt = valt_of(B->dtype);
   const int vec_f64 = vec_f64_of(opt, valt);
   const int64_t d = B->rows;
+  const bool pair = use_pairs(opt);
+  const int nsteps = steps_for(n, pair);
+  const int nrows = partial_rows(n, pair);
   const size_t need = fwd_workspace(B, n, M, vec_f64, ns, opt);
   Workspace ws;
   int rc = get_workspace(opt, need, s, ws);
@@ -473,11 +511,13 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
   }
   const bool tune = (!opt || opt->tile == 0) && autotune_enabled() && d >= 65536;
   double* part_base =
-      static_cast<double*>(cv.take((size_t)std::max(n, 1) * max_tiles(B, vec_f64, M, opt) * M * 8));
-  double* mu_dev = static_cast<double*>(cv.take((size_t)M * (n + 1) * 8));
+      static_cast<double*>(cv.take((size_t)std::max(nrows, 1) * max_tiles(B, vec_f64, M, opt) * M * 8));
+  double* red_out = static_cast<double*>(cv.take((size_t)M * std::max(nrows, 1) * 8));
+  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(nrows, M)));
+  const int mu_mode = pair ? MU_PAIR : MU_PROBE;
 
   if (tune && !ns) {
-    TuneKey key{vec_f64, valt, M, opt ? opt->probe_tile : 0, d, B->nnz};
+    TuneKey key{vec_f64, valt, M, (opt ? opt->probe_tile : 0) * 4 + mu_mode, d, B->nnz};
     Shape sh{};
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -487,7 +527,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
     if (!sh.tile_rows) {
       const std::vector<Shape> shapes = (opt && opt->probe_tile > 0) ? std::vector<Shape>{p.sh}
                                                                       : shape_candidates(vec_f64, M);
-      sh = autotune(B, shapes, vec_f64, valt, M, bufA, bufB, part_base, s);
+      sh = autotune(B, shapes, vec_f64, valt, M, mu_mode, bufA, bufB, part_base, s);
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune[key] = sh;
     }
@@ -525,11 +565,16 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
     D.active = 1;
     return D;
   };
+  // step k writes partial row k (plain) or rows 2k, 2k+1 (pairs)
+  auto set_parts = [&](StepDesc& D, int k) {
+    D.mu_part = part_base + (int64_t)(pair ? 2 * k : k) * kstride;
+    D.mu_part2 = pair ? part_base + (int64_t)(2 * k + 1) * kstride : nullptr;
+  };
 
   // W_k lives in: k = 0 -> probe hash, odd k -> A, even k >= 2 -> B.
   auto wbuf = [&](int k) -> void* { return k == 0 ? nullptr : ((k & 1) ? bufA : bufB); };
   LD_HIP(tm.mark(T_OTHER));
-  for (int k = 0; k < n && d > 0; ++k) {
+  for (int k = 0; k < nsteps && d > 0; ++k) {
     const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
     const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
     const double h = k == 0 ? 0.5 : 1.0;  // W_1 = At V carries half of 2 At
@@ -541,9 +586,9 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       D.ag = h * alpha;
       D.bd = h * beff;
       D.cp = k == 0 ? 0.0 : -1.0;
-      D.mu_part = part_base + (int64_t)k * kstride;
+      set_parts(D, k);
       L.d0 = D;
-      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, true, s));
+      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu_mode, s));
       LD_HIP(tm.mark(T_STEP));
     } else {
       // T = C W_k
@@ -552,7 +597,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       D1.out = bufT;
       D1.ag = 1.0;
       L.d0 = D1;
-      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_NONE, SRC_NONE, false, s));
+      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_NONE, SRC_NONE, MU_NONE, s));
       LD_HIP(tm.mark(T_STEP));
       // W_{k+1} = alpha C^T T + beta W_k - W_{k-1}   (halved at k = 0)
       StepDesc D2 = base_desc(&Ct);
@@ -563,17 +608,20 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       D2.ag = h * alpha;
       D2.bd = h * beta;
       D2.cp = k == 0 ? 0.0 : -1.0;
-      D2.mu_part = part_base + (int64_t)k * kstride;
+      set_parts(D2, k);
       L.d0 = D2;
-      LD_HIP(launch_step(L, vec_f64, valt, SRC_BUF, k == 0 ? SRC_HASH : SRC_BUF, psrc, true, s));
+      LD_HIP(launch_step(L, vec_f64, valt, SRC_BUF, k == 0 ? SRC_HASH : SRC_BUF, psrc, mu_mode, s));
       LD_HIP(tm.mark(T_STEP));
     }
   }
-  if (n >= 1 && d > 0) LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 1, n, kstride, mu_dev, n + 1, s));
-  std::vector<double> mu((size_t)M * (n + 1), 0.0);
-  if (n >= 1 && d > 0) LD_HIP(hipMemcpyAsync(mu.data(), mu_dev, mu.size() * 8, hipMemcpyDeviceToHost, s));
+  std::vector<double> red((size_t)M * std::max(nrows, 1), 0.0);
+  if (nrows >= 1 && d > 0) {
+    LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 0, nrows - 1, kstride, red_out, nrows, red_tmp, s));
+    LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * nrows * 8, hipMemcpyDeviceToHost, s));
+  }
   LD_HIP(hipStreamSynchronize(s));
-  for (int j = 0; j < M; ++j) mu[(size_t)j * (n + 1)] = (double)d;  // v^T v = d for Rademacher probes
+  std::vector<double> mu((size_t)M * (n + 1), 0.0);
+  assemble_moments(red, nrows, pair, n, M, d, mu);
   combine(mu, c, n, M, d, ns ? 0.5 : 1.0, out, opt);
   out->poly_bound = lemma_bound(a, b, n, d) * (ns ? 0.5 : 1.0);
   out->grad_shift = 0.0;
@@ -589,48 +637,75 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
 
 namespace {
 
+// Checkpoint plan of the gradient.  The forward produces W_1..W_m (m = n plain, ceil(n/2)
+// with the product identities).  The adjoint starts from y_top (top = n plain, m pairs) and
+// steps j = top-1 .. 1; step j needs W_j and, with pairs, W_{j-1} and W_{j+1} for its seed.
+// Steps are grouped in segments of s = ceil(sqrt(top)) consecutive j; segment q (j in
+// [lo, hi]) keeps the pair (W_{lo-1}, W_lo) from the forward pass and recomputes
+// W_{lo+1}..W_hi; W_{hi+1} is the next segment's checkpoint (or W_top).
 struct GradPlan {
-  int s;                    // checkpoint stride
-  int nseg;                 // segments
-  std::vector<int> slot_of; // W_k -> checkpoint slot (or -1), k = 0..n
+  bool pair;
+  int m, top, s, nseg;
+  std::vector<int> lo, hi;   // per segment
+  std::vector<int> slot_of;  // W_k -> checkpoint slot or -1, k = 0..m
   int nslots;
-  int nseg_buf;             // segment scratch buffers
+  int nseg_buf;              // recomputation scratch blocks (also the forward's rolling pair)
 };
 
-GradPlan plan_grad(int n, int stride) {
+GradPlan plan_grad(int n, bool pair, int stride) {
   GradPlan g;
-  g.s = stride > 0 ? stride : (int)std::ceil(std::sqrt((double)std::max(n, 1)));
-  if (g.s < 2) g.s = 2;
-  g.nseg = n >= 1 ? (n - 1) / g.s + 1 : 0;  // segments cover k = 0..n-1
-  g.slot_of.assign(n + 2, -1);
+  g.pair = pair;
+  g.m = steps_for(n, pair);
+  g.top = pair ? g.m : n;
+  const int nsteps = std::max(g.top - 1, 0);  // adjoint steps j = top-1 .. 1
+  g.s = stride > 0 ? stride : (int)std::ceil(std::sqrt((double)std::max(nsteps, 1)));
+  if (g.s < 1) g.s = 1;
+  g.nseg = nsteps > 0 ? (nsteps - 1) / g.s + 1 : 0;
+  g.slot_of.assign(g.m + 2, -1);
   g.nslots = 0;
+  auto keep = [&](int k) {
+    if (k >= 1 && k <= g.m && g.slot_of[k] < 0) g.slot_of[k] = g.nslots++;
+  };
   for (int q = 0; q < g.nseg; ++q) {
-    const int k0 = q * g.s;
-    if (k0 >= 1 && k0 <= n - 1) g.slot_of[k0] = g.nslots++;
-    if (k0 + 1 <= n - 1) g.slot_of[k0 + 1] = g.nslots++;
+    g.lo.push_back(1 + q * g.s);
+    g.hi.push_back(std::min(1 + (q + 1) * g.s - 1, g.top - 1));
+    keep(g.lo[q] - 1);
+    keep(g.lo[q]);
   }
-  g.nseg_buf = std::max(g.s - 2, 2);
+  if (pair) {  // the seed of y_top and the last step's W_{hi+1}
+    keep(g.top - 1);
+    keep(g.top);
+  }
+  g.nseg_buf = std::max(g.s - 1, 2);
   return g;
 }
 
-size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, int stride) {
+size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, bool pair) {
   const size_t vb = vec_f64 ? 8 : 4;
-  GradPlan g = plan_grad(n, stride);
+  const GradPlan g = plan_grad(n, pair, opt ? opt->ckpt_stride : 0);
   Shape sh = with_tile(base_shape(vec_f64, M), B->rows, B->nnz, 0);
   const int64_t ntiles = B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
+  const int rows = std::max(partial_rows(n, g.pair), 1);
   Carve c;
   const size_t vecb = (size_t)B->rows * M * vb;
   for (int i = 0; i < g.nslots + g.nseg_buf + 2; ++i) c.take(vecb);
-  c.take((size_t)B->nnz * vb);                    // gradient accumulators
-  c.take((size_t)B->nnz * 8);                     // transposed-entry index
-  c.take(256);                                    // missing-transpose flag
+  c.take((size_t)B->nnz * vb);                       // gradient accumulators
+  c.take((size_t)B->nnz * 8);                        // transposed-entry index
+  c.take(256);                                       // missing-transpose flag
   c.take((size_t)std::max<int64_t>(ntiles, 1) * 8);  // diagonal partials
-  c.take(8);                                      // diagonal total
-  c.take((size_t)std::max(n, 1) * ntiles * M * 8);
-  c.take((size_t)M * (n + 1) * 8);
+  c.take(8);                                         // diagonal total
+  c.take((size_t)rows * ntiles * M * 8);             // per-tile moment partials
+  c.take((size_t)M * rows * 8);                      // reduced partials
+  c.take(reduce_scratch_bytes(rows, M));
   return align_up(c.off);
 }
 
+// A non-symmetric pattern falls back to the plain recurrence, so size for both plans.
+size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
+  size_t w = grad_workspace_for(B, n, M, vec_f64, opt, false);
+  if (use_pairs(opt)) w = std::max(w, grad_workspace_for(B, n, M, vec_f64, opt, true));
+  return w;
+}
 
 }  // namespace
 
@@ -646,7 +721,8 @@ struct BatchEntry {
   hipGraph_t graph = nullptr;
   void* mem = nullptr;
   double* mu_dev = nullptr;
-  int kmax = 0;
+  int kmax = 0;  // partial rows of the longest member
+  bool pair = true;
   std::vector<std::vector<double>> coeffs;
   ~BatchEntry() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -665,11 +741,18 @@ double bits_of(const void* p) {
 }
 
 int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M, uint64_t seed,
-                int vec_f64, int valt, const Shape& sh, BatchEntry& E) {
+                int vec_f64, int valt, bool pair, const Shape& sh, BatchEntry& E) {
   const size_t vb = vec_f64 ? 8 : 4;
-  int kmax = 0;
-  for (int i = 0; i < count; ++i) kmax = std::max(kmax, n[i]);
-  E.kmax = kmax;
+  // kmax: steps of the longest member; rmax: partial rows of the longest member
+  int kmax = 0, rmax = 0;
+  std::vector<int> rows_i(count);
+  for (int i = 0; i < count; ++i) {
+    kmax = std::max(kmax, steps_for(n[i], pair));
+    rows_i[i] = partial_rows(n[i], pair);
+    rmax = std::max(rmax, rows_i[i]);
+  }
+  E.kmax = rmax;
+  E.pair = pair;
   std::vector<int64_t> tile_begin(count + 1, 0);
   for (int i = 0; i < count; ++i) tile_begin[i + 1] = tile_begin[i] + (Bs[i].rows + sh.tile_rows - 1) / sh.tile_rows;
   const int64_t ntiles = tile_begin[count];
@@ -691,10 +774,10 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
     offB[i] = c.off - (size_t)Bs[i].rows * M * vb;
   }
   const int64_t kstride = ntiles * M;
-  c.take((size_t)std::max(kmax, 1) * kstride * 8);
-  const size_t off_part = c.off - (size_t)std::max(kmax, 1) * kstride * 8;
-  c.take((size_t)count * M * (kmax + 1) * 8);
-  const size_t off_mu = c.off - (size_t)count * M * (kmax + 1) * 8;
+  c.take((size_t)std::max(rmax, 1) * kstride * 8);
+  const size_t off_part = c.off - (size_t)std::max(rmax, 1) * kstride * 8;
+  c.take((size_t)count * M * (rmax + 1) * 8);
+  const size_t off_mu = c.off - (size_t)count * M * (rmax + 1) * 8;
   c.take((size_t)std::max(kmax, 1) * count * sizeof(StepDesc));
   const size_t off_desc = c.off - (size_t)std::max(kmax, 1) * count * sizeof(StepDesc);
   c.take((size_t)ntiles * 4);
@@ -736,7 +819,7 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
       D.val = Bs[i].values;
       D.seed = seed + (uint64_t)i;
       D.d = Bs[i].rows;
-      D.active = k < n[i] ? 1 : 0;
+      D.active = k < steps_for(n[i], pair) ? 1 : 0;
       const double h = k == 0 ? 0.5 : 1.0;
       D.G = wbuf(k);
       D.P = k >= 2 ? wbuf(k - 1) : nullptr;
@@ -744,7 +827,8 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
       D.ag = h * alpha;
       D.bd = h * beff;
       D.cp = k == 0 ? 0.0 : -1.0;
-      D.mu_part = part + (int64_t)k * kstride + tile_begin[i] * M;
+      D.mu_part = part + (int64_t)(pair ? 2 * k : k) * kstride + tile_begin[i] * M;
+      D.mu_part2 = pair ? part + (int64_t)(2 * k + 1) * kstride + tile_begin[i] * M : nullptr;
       D.tile0 = tile_begin[i];
     }
   }
@@ -752,7 +836,7 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
   LD_HIP(hipMemcpy(d_tm, tile_mat.data(), tile_mat.size() * 4, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(d_tr, tile_row0.data(), tile_row0.size() * 8, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(d_tb, tile_begin.data(), tile_begin.size() * 8, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(d_n, n, (size_t)count * 4, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(d_n, rows_i.data(), (size_t)count * 4, hipMemcpyHostToDevice));
 
   // capture every step and the reduction on a private stream
   hipStream_t cs;
@@ -770,9 +854,9 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
     L.shape = sh;
     const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
     const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
-    err = launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, true, cs);
+    err = launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, pair ? MU_PAIR : MU_PROBE, cs);
   }
-  if (err == hipSuccess) err = launch_reduce_batched(part, d_tb, d_n, count, M, kmax, kstride, E.mu_dev, cs);
+  if (err == hipSuccess) err = launch_reduce_batched(part, d_tb, d_n, count, M, rmax, kstride, E.mu_dev, cs);
   hipError_t e2 = hipStreamEndCapture(cs, &E.graph);
   (void)hipStreamDestroy(cs);
   if (err != hipSuccess) return fail_hip(err, "batched step capture");
@@ -799,7 +883,7 @@ size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) 
   ld_opts o{};
   o.vec_f64 = vec_f64 ? 1 : 2;
   const int v64 = vec_f64_of(&o, valt);
-  if (mode == 2) return grad_workspace(B, n, M, v64, 0);
+  if (mode == 2) return grad_workspace(B, n, M, v64, nullptr);
   return fwd_workspace(B, n, M, v64, mode == 1, nullptr);
 }
 
@@ -928,13 +1012,27 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   if (sh.probe_tiles != 1)
     return fail(LD_EINVAL, "gradient needs M <= %d probes per call with these vectors", (1 << sh.lpr_log2) * sh.vpl);
   const int64_t ntiles = d > 0 ? (d + sh.tile_rows - 1) / sh.tile_rows : 0;
-  const GradPlan g = plan_grad(n, opt ? opt->ckpt_stride : 0);
-  const size_t need = grad_workspace(B, n, M, vec_f64, opt ? opt->ckpt_stride : 0);
+  const size_t need = grad_workspace(B, n, M, vec_f64, opt);
   Workspace ws;
   rc = get_workspace(opt, need, s, ws);
   if (rc) return rc;
   Carve cv;
   cv.base = static_cast<char*>(ws.ptr);
+  int64_t* perm = static_cast<int64_t*>(cv.take((size_t)B->nnz * 8));
+  int* missing = static_cast<int*>(cv.take(256));
+  // The pattern's symmetry decides the form: the product identities (and the symmetrised
+  // gradient) need B = B^T; a pattern without its transpose runs the plain recurrence.
+  LD_HIP(launch_fill_zero(missing, 256, s));
+  LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, B->nnz, perm, missing, s));
+  int miss = 1;
+  if (B->nnz > 0) {
+    LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
+    LD_HIP(hipStreamSynchronize(s));
+  }
+  const bool sym_pattern = miss == 0;
+  const GradPlan g = plan_grad(n, use_pairs(opt) && sym_pattern, opt ? opt->ckpt_stride : 0);
+  const bool pair = g.pair;
+  const int nrows = partial_rows(n, pair);
   const size_t vecb = (size_t)d * M * vb;
   std::vector<void*> slots(g.nslots), seg(g.nseg_buf);
   for (auto& p : slots) p = cv.take(vecb);
@@ -942,25 +1040,37 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   void* Ya = cv.take(vecb);
   void* Yb = cv.take(vecb);
   void* Gacc = cv.take((size_t)B->nnz * vb);
-  int64_t* perm = static_cast<int64_t*>(cv.take((size_t)B->nnz * 8));
-  int* missing = static_cast<int*>(cv.take(256));
   double* gdiag_part = static_cast<double*>(cv.take((size_t)std::max<int64_t>(ntiles, 1) * 8));
   double* gdiag_tot = static_cast<double*>(cv.take(8));
-  double* part = static_cast<double*>(cv.take((size_t)std::max(n, 1) * ntiles * M * 8));
-  double* mu_dev = static_cast<double*>(cv.take((size_t)M * (n + 1) * 8));
+  const int rows_alloc = std::max(nrows, 1);
+  double* part = static_cast<double*>(cv.take((size_t)rows_alloc * ntiles * M * 8));
+  double* red_out = static_cast<double*>(cv.take((size_t)M * rows_alloc * 8));
+  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(rows_alloc, M)));
   const int64_t kstride = ntiles * M;
 
   const std::vector<double> c = cheb_coeffs(a, b, n);
   const double alpha = 4.0 / (b - a);
   const double beta = -2.0 * (a + b) / (b - a);
   const double beff = beta + alpha * B->diag_shift;
+  // Seed coefficients with the product identities (see assemble_moments): the estimate is
+  // const + sum_k al[k] W_k^T W_{k+1} + sum_k be[k] W_{k+1}^T W_{k+1}, k = 0..m-1.
+  std::vector<double> al(g.m + 1, 0.0), be(g.m + 1, 0.0);
+  if (pair) {
+    for (int k = 0; k < g.m; ++k) {
+      if (2 * k + 2 <= n) be[k] = 2.0 * c[2 * k + 2];
+      if (k >= 1 && 2 * k + 1 <= n) al[k] = 2.0 * c[2 * k + 1];
+    }
+    if (n >= 1) {
+      al[0] = c[1];
+      for (int k = 1; k < g.m; ++k)
+        if (2 * k + 1 <= n) al[0] -= c[2 * k + 1];
+    }
+  }
 
   StepTimer tm;
   tm.on = opt && opt->timing;
   tm.s = s;
   LD_HIP(launch_fill_zero(Gacc, (size_t)B->nnz * vb, s));
-  LD_HIP(launch_fill_zero(missing, 256, s));
-  LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, perm, missing, s));
   LD_HIP(launch_fill_zero(gdiag_part, (size_t)std::max<int64_t>(ntiles, 1) * 8, s));
   LD_HIP(tm.mark(T_OTHER));
 
@@ -970,8 +1080,8 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   L.tile_rows = sh.tile_rows;
   L.M = M;
   L.shape = sh;
-  auto step = [&](int gsrc, int psrc, bool mu, const void* G, const void* P, void* o, double h, double cp,
-                  double* mp) -> hipError_t {
+  auto step = [&](int gsrc, int psrc, int mu, const void* G, const void* P, void* o, double h, double cp,
+                  int k) -> hipError_t {
     StepDesc D{};
     D.row_ptr = B->row_ptr;
     D.col = B->col_idx;
@@ -985,16 +1095,19 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
     D.ag = h * alpha;
     D.bd = h * beff;
     D.cp = cp;
-    D.mu_part = mp;
+    if (mu != MU_NONE) {
+      D.mu_part = part + (int64_t)(pair ? 2 * k : k) * kstride;
+      D.mu_part2 = pair ? part + (int64_t)(2 * k + 1) * kstride : nullptr;
+    }
     L.d0 = D;
     return launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu, s);
   };
 
   // forward recurrence with checkpoints: W_k lives in bufW[k] (nullptr = probe hash)
-  std::vector<void*> bufW(n + 2, nullptr);
+  std::vector<void*> bufW(g.m + 2, nullptr);
   void* R0 = seg[0];
   void* R1 = seg[1];
-  for (int k = 0; k < n && d > 0; ++k) {
+  for (int k = 0; k < g.m && d > 0; ++k) {
     void* o;
     if (g.slot_of[k + 1] >= 0) {
       o = slots[g.slot_of[k + 1]];
@@ -1007,27 +1120,30 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
     }
     const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
     const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
-    LD_HIP(step(gsrc, psrc, true, bufW[k], k >= 2 ? bufW[k - 1] : nullptr, o, k == 0 ? 0.5 : 1.0,
-                k == 0 ? 0.0 : -1.0, part + (int64_t)k * kstride));
+    LD_HIP(step(gsrc, psrc, pair ? MU_PAIR : MU_PROBE, bufW[k], k >= 2 ? bufW[k - 1] : nullptr, o,
+                k == 0 ? 0.5 : 1.0, k == 0 ? 0.0 : -1.0, k));
     LD_HIP(tm.mark(T_STEP));
     bufW[k + 1] = o;
   }
-  if (n >= 1 && d > 0) LD_HIP(launch_reduce_moments(part, ntiles, M, 1, n, kstride, mu_dev, n + 1, s));
+  if (nrows >= 1 && d > 0)
+    LD_HIP(launch_reduce_moments(part, ntiles, M, 0, nrows - 1, kstride, red_out, nrows, red_tmp, s));
 
-  // backward: y_n = c_n V; y_k = c_k V + 2 At y_{k+1} - y_{k+2}; SDDMM with w_k.
-  // A symmetric pattern lets each row accumulate its transposed entries from the rows of
-  // y_{k+1} that the SpMM gathers anyway (one gather per nonzero instead of two).
-  int miss = 1;
-  if (B->nnz > 0) {
-    LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
-    LD_HIP(hipStreamSynchronize(s));
-  }
-  const bool sym = (miss == 0) && sym_enabled();
+  // backward.  A symmetric pattern lets each row accumulate its transposed entries from the
+  // rows of y_{j+1} that the SpMM gathers anyway (one gather per nonzero instead of two).
+  const bool sym = sym_pattern && sym_enabled();
+  auto ckpt = [&](int k) -> void* { return k == 0 ? nullptr : slots[g.slot_of[k]]; };
   if (n >= 1 && d > 0) {
-    LD_HIP(launch_fill_probe(Ya, vec_f64, c[n], seed, d, M, s));
+    // y_top: c_n V (plain) or al[top-1] W_{top-1} + 2 be[top-1] W_top (pairs; W_0 = V)
+    if (!pair) {
+      LD_HIP(launch_seed(Ya, vec_f64, nullptr, nullptr, nullptr, c[n], 0.0, 0.0, 0.0, seed, d, M, s));
+    } else {
+      const int t = g.top;
+      LD_HIP(launch_seed(Ya, vec_f64, ckpt(t), t - 1 >= 1 ? ckpt(t - 1) : nullptr, nullptr,
+                         t - 1 == 0 ? al[t - 1] : 0.0, 2.0 * be[t - 1], al[t - 1], 0.0, seed, d, M, s));
+    }
     LD_HIP(tm.mark(T_OTHER));
-    void* y1 = Ya;       // y_{k+1}
-    void* y2 = nullptr;  // y_{k+2}
+    void* y1 = Ya;       // y_{j+1}
+    void* y2 = nullptr;  // y_{j+2}
     AdjDesc A{};
     A.row_ptr = B->row_ptr;
     A.col = B->col_idx;
@@ -1040,48 +1156,61 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
     A.bd = beff;
     A.cp = -1.0;
     for (int q = g.nseg - 1; q >= 0; --q) {
-      const int k_lo = q * g.s;
-      const int k_hi = std::min((q + 1) * g.s, n) - 1;
-      std::vector<void*> segW(k_hi - k_lo + 1, nullptr);
-      segW[0] = k_lo == 0 ? nullptr : slots[g.slot_of[k_lo]];
-      if (k_hi >= k_lo + 1) segW[1] = slots[g.slot_of[k_lo + 1]];
-      for (int i = 2; i <= k_hi - k_lo; ++i) {
-        const bool p_hash = (k_lo + i - 2) == 0;
-        LD_HIP(step(SRC_BUF, p_hash ? SRC_HASH : SRC_BUF, false, segW[i - 1], p_hash ? nullptr : segW[i - 2],
-                    seg[i - 2], 1.0, -1.0, nullptr));
+      const int lo = g.lo[q], hi = g.hi[q];
+      // segW[i] = W_{lo-1+i}, i = 0 .. hi-lo+1 (+1 with pairs: W_{hi+1})
+      std::vector<void*> segW(hi - lo + 3, nullptr);
+      segW[0] = ckpt(lo - 1);
+      segW[1] = ckpt(lo);
+      for (int i = 2; i <= hi - lo + 1; ++i) {
+        const int k = lo - 1 + i;  // recompute W_k = 2 At W_{k-1} - W_{k-2}
+        const bool p_hash = (k - 2) == 0;
+        LD_HIP(step(SRC_BUF, p_hash ? SRC_HASH : SRC_BUF, MU_NONE, segW[i - 1], p_hash ? nullptr : segW[i - 2],
+                    seg[i - 2], 1.0, -1.0, 0));
         LD_HIP(tm.mark(T_STEP));
         segW[i] = seg[i - 2];
       }
-      for (int k = k_hi; k >= std::max(k_lo, 1); --k) {
+      if (pair) segW[hi - lo + 2] = ckpt(hi + 1);
+      for (int j = hi; j >= lo; --j) {
         void* o = y2 ? y2 : (y1 == Ya ? Yb : Ya);
         A.Y1 = y1;
         A.Y2 = y2;
         A.out = o;
-        A.W = segW[k - k_lo];
-        A.cv = c[k];
+        A.W = segW[j - lo + 1];
         A.gw = 2.0;
+        if (!pair) {
+          A.cv = c[j];
+          A.cw = A.cwm = A.cwp = 0.0;
+          A.Wm = A.Wp = nullptr;
+        } else {
+          A.cw = 2.0 * be[j - 1];
+          A.cv = j - 1 == 0 ? al[j - 1] : 0.0;  // W_0 = V
+          A.Wm = j - 1 == 0 ? nullptr : segW[j - lo];
+          A.cwm = al[j - 1];
+          A.Wp = segW[j - lo + 2];
+          A.cwp = al[j];
+        }
         LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, true, false, y2 != nullptr, sym, s));
         LD_HIP(tm.mark(T_ADJ));
         y2 = y1;
         y1 = o;
       }
-      if (k_lo == 0) {
-        // the y_1 w_0^T term, w_0 = v
-        A.Y1 = y1;
-        A.Y2 = nullptr;
-        A.out = nullptr;
-        A.W = nullptr;
-        A.cv = 0.0;
-        A.gw = 1.0;
-        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, false, true, false, sym, s));
-        LD_HIP(tm.mark(T_ADJ));
-      }
     }
+    // the y_1 w_0^T term, w_0 = v
+    A.Y1 = y1;
+    A.Y2 = nullptr;
+    A.out = nullptr;
+    A.W = nullptr;
+    A.Wm = A.Wp = nullptr;
+    A.cv = A.cw = A.cwm = A.cwp = 0.0;
+    A.gw = 1.0;
+    LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, false, true, false, sym, s));
+    LD_HIP(tm.mark(T_ADJ));
   }
   const double scale = grad_output * (2.0 / (b - a)) / M;
   if (B->nnz > 0) {
-    if (sym)
-      LD_HIP(launch_permute_scale(Gacc, vec_f64, perm, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
+    // symmetric pattern: the derivative along symmetric perturbations, (G_ij + G_ji)/2
+    if (sym_pattern)
+      LD_HIP(launch_sym_scale(Gacc, vec_f64, perm, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
     else
       LD_HIP(launch_scale_grad(Gacc, vec_f64, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
   }
@@ -1090,11 +1219,12 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
     LD_HIP(launch_sum_doubles(gdiag_part, ntiles, gdiag_tot, s));
     LD_HIP(hipMemcpyAsync(&gd, gdiag_tot, 8, hipMemcpyDeviceToHost, s));
   }
-  std::vector<double> mu((size_t)M * (n + 1), 0.0);
-  if (n >= 1 && d > 0) LD_HIP(hipMemcpyAsync(mu.data(), mu_dev, mu.size() * 8, hipMemcpyDeviceToHost, s));
+  std::vector<double> red((size_t)M * rows_alloc, 0.0);
+  if (nrows >= 1 && d > 0) LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * nrows * 8, hipMemcpyDeviceToHost, s));
   LD_HIP(tm.mark(T_OTHER));
   LD_HIP(hipStreamSynchronize(s));
-  for (int j = 0; j < M; ++j) mu[(size_t)j * (n + 1)] = (double)d;
+  std::vector<double> mu((size_t)M * (n + 1), 0.0);
+  assemble_moments(red, nrows, pair, n, M, d, mu);
   ld_result r{};
   combine(mu, c, n, M, d, 1.0, &r, opt);
   r.poly_bound = lemma_bound(a, b, n, d);
@@ -1131,8 +1261,9 @@ int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const d
   const int tile = (opt && opt->tile > 0) ? opt->tile : staged_tile_cap(sh, tot_d, tot_nnz);
   sh.tile_rows = (tile + rpi - 1) / rpi * rpi;
 
+  const bool pair = use_pairs(opt);
   std::vector<double> key = {(double)count, (double)M, (double)(seed >> 32), (double)(seed & 0xffffffffu),
-                             (double)vec_f64, (double)sh.tile_rows};
+                             (double)vec_f64, (double)sh.tile_rows, pair ? 1.0 : 0.0};
   for (int i = 0; i < count; ++i) {
     const double v[] = {bits_of(Bs[i].row_ptr), bits_of(Bs[i].col_idx), bits_of(Bs[i].values), (double)Bs[i].rows,
                         (double)Bs[i].nnz, (double)Bs[i].dtype, Bs[i].diag_shift, a[i], b[i], (double)n[i]};
@@ -1143,7 +1274,7 @@ int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const d
   BatchEntry* E;
   if (it == g_batch.end()) {
     auto ent = std::make_unique<BatchEntry>();
-    int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, sh, *ent);
+    int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, pair, sh, *ent);
     if (rc) return rc;
     E = ent.get();
     g_batch[key] = std::move(ent);
@@ -1162,11 +1293,12 @@ int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const d
   LD_HIP(hipStreamSynchronize(s));
   int status = LD_OK;
   for (int i = 0; i < count; ++i) {
+    const int rows = partial_rows(n[i], pair);
+    std::vector<double> red((size_t)M * std::max(rows, 1), 0.0);
+    for (int j = 0; j < M; ++j)
+      for (int r = 0; r < rows; ++r) red[(size_t)j * rows + r] = mu_all[((size_t)i * M + j) * (kmax + 1) + r + 1];
     std::vector<double> mu((size_t)M * (n[i] + 1));
-    for (int j = 0; j < M; ++j) {
-      mu[(size_t)j * (n[i] + 1)] = (double)Bs[i].rows;
-      for (int k = 1; k <= n[i]; ++k) mu[(size_t)j * (n[i] + 1) + k] = mu_all[((size_t)i * M + j) * (kmax + 1) + k];
-    }
+    assemble_moments(red, rows, pair, n[i], M, Bs[i].rows, mu);
     ld_result r{};
     combine(mu, E->coeffs[i], n[i], M, Bs[i].rows, 1.0, &r, nullptr);
     r.poly_bound = lemma_bound(a[i], b[i], n[i], Bs[i].rows);

@@ -33,7 +33,8 @@ struct StepDesc {
   double ag, bd, cp, cv;
   uint64_t seed;
   int64_t d;
-  double* mu_part;  // [tiles of this matrix][M] doubles for this degree, or nullptr
+  double* mu_part;   // [tiles of this matrix][M] doubles for this step, or nullptr
+  double* mu_part2;  // second inner product (MU_PAIR), same layout
   int64_t tile0;    // global index of this matrix's first tile
   int32_t active;   // 0: skip this matrix at this step
   int32_t pad_;
@@ -68,15 +69,24 @@ constexpr int kStageNnz = 2048;
 // Value type tags
 enum ValT : int { VAL_F64 = 0, VAL_F32 = 1, VAL_BF16 = 2 };
 
+// Moment epilogue of a step that produces W_{k+1} from W_k:
+enum Mu : int {
+  MU_NONE = 0,   // none
+  MU_PROBE = 1,  // mu_part  <- per-tile sums of v_j^T W_{k+1}          (moment k+1)
+  MU_PAIR = 2,   // mu_part  <- per-tile sums of W_k^T W_{k+1},  mu_part2 <- W_{k+1}^T W_{k+1}
+};
+
 // Launch one fused step.  gsrc/dsrc/psrc select the operand sources (uniform across
-// matrices), mu selects the probe-moment epilogue.  Returns a hipError_t.
-hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, bool mu,
+// matrices), mu the moment epilogue.  Returns a hipError_t.
+hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu,
                        hipStream_t s);
 
 // Adjoint step (gradient): for row r with y1 = Y_{k+1}:
 //   if spmm: out[r,:] = cv * V[r,:] + ag * sum_t val[t] y1[col[t],:] + bd * y1[r,:] + cp * Y2[r,:]
 //   G[t] += gw * sum_p y1[r,p] * W[col[t],p]    (SDDMM on the pattern of the matrix)
 //   gdiag_part[tile] += gw * sum_p y1[r,p] * W[r,p]
+//   with spmm the new vector also takes the seed  cw * W[r,:] + cwm * Wm[r,:] + cwp * Wp[r,:]
+//   (Wm, Wp nullable): the direct derivative of the estimate with respect to w_k.
 struct AdjDesc {
   const int64_t* row_ptr;
   const int32_t* col;
@@ -85,30 +95,39 @@ struct AdjDesc {
   const void* Y2;  // y_{k+2} (or nullptr)
   void* out;       // y_k (may alias Y2), or nullptr when spmm is off
   const void* W;   // w_k (nullptr => probe hash, k = 0)
+  const void* Wm;  // w_{k-1} for the seed, or nullptr
+  const void* Wp;  // w_{k+1} for the seed, or nullptr
   void* Gacc;      // nnz accumulators (float for FP32 vectors, double for FP64)
   double* gdiag_part;  // [tiles] doubles
-  double ag, bd, cp, cv, gw;
+  double ag, bd, cp, cv, gw, cw, cwm, cwp;
   uint64_t seed;
   int64_t d;
 };
+
+// out[r,:] = cv * V[r,:] + cw * W[r,:] + cwm * Wm[r,:] + cwp * Wp[r,:] (W, Wm, Wp nullable):
+// the adjoint's starting vector.
+hipError_t launch_seed(void* out, int vec_f64, const void* W, const void* Wm, const void* Wp, double cv, double cw,
+                       double cwm, double cwp, uint64_t seed, int64_t d, int M, hipStream_t s);
 
 // sym: the pattern is symmetric and A.Gacc accumulates the transposed entries (see the kernel).
 hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64, int valt, bool spmm,
                           bool w_hash, bool y2, bool sym, hipStream_t s);
 
 // perm[t] = index of the stored entry (col[t], row(t)); *missing |= 1 if some is absent.
-hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t* perm,
+hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz, int64_t* perm,
                                   int* missing, hipStream_t s);
 
-// out[t] = scale * a[perm[t]]
-hipError_t launch_permute_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,
-                                int out_f64, hipStream_t s);
+// out[t] = scale * (a[t] + a[perm[t]]) / 2
+hipError_t launch_sym_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,
+                            int out_f64, hipStream_t s);
 
 // Deterministic reduction of per-tile partials:
 // mu[j * ldmu + k] = sum_{t < ntiles} part[k][t][j] for k in [k_lo, k_hi].
 // part is laid out as part + (k - k_lo) * kstride + t * M + j.
+// tmp: reduce_scratch_bytes(k_hi - k_lo + 1, M) bytes of device scratch.
 hipError_t launch_reduce_moments(const double* part, int64_t ntiles, int M, int k_lo, int k_hi, int64_t kstride,
-                                 double* mu, int ldmu, hipStream_t s);
+                                 double* mu, int ldmu, double* tmp, hipStream_t s);
+size_t reduce_scratch_bytes(int nk, int M);
 
 // Batched reduction: for matrix i, tiles [tile_begin[i], tile_begin[i+1]) of degree k (k <= n[i])
 // into mu[i][j][k].  part[(k-1) * kstride + tile * M + j].
@@ -132,8 +151,6 @@ hipError_t launch_scale_grad(const void* Gacc, int acc_f64, int64_t nnz, double 
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-// out[r, j] = c * v_j[r] (the adjoint's starting vector y_n = c_n V)
-hipError_t launch_fill_probe(void* out, int vec_f64, double c, uint64_t seed, int64_t d, int M, hipStream_t s);
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -19,6 +19,7 @@
 //  * One workgroup per row tile; workgroup ids are remapped so that each of the eight
 //    XCDs walks a contiguous range of tiles in order, which keeps the W_k rows that
 //    banded patterns reuse (neighbours at +-N, +-N^2) inside that XCD's L2.
+#include <algorithm>
 #include <type_traits>
 
 #include "ld_internal.h"
@@ -182,7 +183,7 @@ __device__ __forceinline__ bool stage_tile(TileCsr<VALT>& T, const int64_t* rp, 
   return fits;
 }
 
-template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, bool MU>
+template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, int MU>
 __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   typedef typename Val<VALT>::T MV;
   const int64_t tile = xcd_tile(L.ntiles);
@@ -218,9 +219,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   int64_t nz0;
   const bool staged = stage_tile<VALT>(T, rp, ci, D.val, row0, row_end, nz0);
 
-  double mu[VPL];
+  // MU_PROBE: mu = v^T W_{k+1}.  MU_PAIR: mu = W_k^T W_{k+1} and mu2 = W_{k+1}^T W_{k+1}, the two
+  // inner products the Chebyshev product identities turn into moments 2k+1 and 2k+2.
+  double mu[VPL], mu2[VPL];
 #pragma unroll
-  for (int i = 0; i < VPL; ++i) mu[i] = 0.0;
+  for (int i = 0; i < VPL; ++i) mu[i] = mu2[i] = 0.0;
 
   for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
     const int64_t row = base + grp;
@@ -252,8 +255,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
     }
 
     VT acc[VPL];
+    VT wk[VPL];  // own row of the gathered operand (MU_PAIR with the diagonal folded in)
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
+    for (int i = 0; i < VPL; ++i) acc[i] = wk[i] = VT(0);
     bool hd = false;
     for (int64_t t = s; t < e; t += kUnroll) {
       int cc[kUnroll];
@@ -300,6 +304,13 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
       for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
+      if constexpr (MU == MU_PAIR && DSRC == SRC_SAME) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (ok[u] && cc[u] == row)
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) wk[i] = gg[u][i];
+      }
     }
 
     if (has) {
@@ -311,9 +322,14 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
           else
             probe_signs<VT, VPL>(D.seed, row, p0, g);
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, g[i], acc[i]);
+          for (int i = 0; i < VPL; ++i) {
+            acc[i] = fma(bd, g[i], acc[i]);
+            wk[i] = g[i];
+          }
         }
       } else if constexpr (DSRC != SRC_NONE) {
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) wk[i] = dv[i];
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
       }
@@ -323,7 +339,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
       }
       if (pact) {
         vstore_nt<VT, VPL>(out + off, acc);
-        if constexpr (MU) {
+        if constexpr (MU == MU_PROBE) {
           const uint64_t w = probe_word(D.seed, (uint64_t)row, (uint32_t)(p0 >> 6));
           const uint32_t bits = (uint32_t)(w >> (p0 & 63));
 #pragma unroll
@@ -331,28 +347,48 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
             const double x = (double)acc[i];
             mu[i] += ((bits >> i) & 1u) ? -x : x;
           }
+        } else if constexpr (MU == MU_PAIR) {
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) {
+            const double x = (double)acc[i];
+            mu[i] = fma(x, (double)wk[i], mu[i]);
+            mu2[i] = fma(x, x, mu2[i]);
+          }
         }
       }
     }
   }
 
-  if constexpr (MU) {
-    __shared__ double smu[kWaves][256];
+  if constexpr (MU != MU_NONE) {
+    // fixed-order reduction: wave butterfly, then waves summed in order through LDS that
+    // the tile's CSR slice no longer needs
+    constexpr int NQ = MU == MU_PAIR ? 2 : 1;
     for (int o = LPR; o < 64; o <<= 1)
 #pragma unroll
-      for (int i = 0; i < VPL; ++i) mu[i] += __shfl_xor(mu[i], o, 64);
+      for (int i = 0; i < VPL; ++i) {
+        mu[i] += __shfl_xor(mu[i], o, 64);
+        if constexpr (NQ == 2) mu2[i] += __shfl_xor(mu2[i], o, 64);
+      }
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(&T);  // [NQ][kWaves][256]
+    static_assert(sizeof(TileCsr<VAL_BF16>) >= 2 * kWaves * 256 * sizeof(double), "LDS reuse too small");
     if (grp == 0)
 #pragma unroll
-      for (int i = 0; i < VPL; ++i) smu[wave][sub * VPL + i] = mu[i];
+      for (int i = 0; i < VPL; ++i) {
+        red[wave * 256 + sub * VPL + i] = mu[i];
+        if constexpr (NQ == 2) red[(kWaves + wave) * 256 + sub * VPL + i] = mu2[i];
+      }
     __syncthreads();
-    double* dst = D.mu_part + (tile - D.tile0) * (int64_t)M;
-    for (int j = threadIdx.x; j < tile_probes; j += kBlock) {
-      const int pj = (int)blockIdx.y * tile_probes + j;
-      if (pj < M) {
-        double sum = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+      double* dst = (q == 0 ? D.mu_part : D.mu_part2) + (tile - D.tile0) * (int64_t)M;
+      for (int j = threadIdx.x; j < tile_probes; j += kBlock) {
+        const int pj = (int)blockIdx.y * tile_probes + j;
+        if (pj < M) {
+          double sum = 0.0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) sum += smu[w][j];
-        dst[pj] = sum;
+          for (int w = 0; w < kWaves; ++w) sum += red[(q * kWaves + w) * 256 + j];
+          dst[pj] = sum;
+        }
       }
     }
   }
@@ -488,10 +524,26 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
       if constexpr (SPMM) {
         VT vv[VPL];
         probe_signs<VT, VPL>(A.seed, row, p0, vv);
+        const VT cw = (VT)A.cw;
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
           VT o = fma(bd, yown[i], acc[i]);
+          o = fma(cw, wown[i], o);
           acc[i] = fma(cv, vv[i], o);
+        }
+        if (A.Wm) {
+          VT x[VPL];
+          vload_nt<VT, VPL>(static_cast<const VT*>(A.Wm) + roff, x);
+          const VT c = (VT)A.cwm;
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(c, x[i], acc[i]);
+        }
+        if (A.Wp) {
+          VT x[VPL];
+          vload_nt<VT, VPL>(static_cast<const VT*>(A.Wp) + roff, x);
+          const VT c = (VT)A.cwp;
+#pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(c, x[i], acc[i]);
         }
         if constexpr (Y2) {
           VT y2v[VPL];
@@ -516,51 +568,87 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
 }
 
 // perm[t] = index of the entry (col[t], row(t)); flag set when some transposed entry is missing.
+// One thread per stored entry: its row by binary search over row_ptr, then a scan of row col[t].
 __global__ void __launch_bounds__(256) transpose_index_kernel(const int64_t* row_ptr, const int32_t* col, int64_t d,
-                                                              int64_t* perm, int* missing) {
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
-    for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t) {
-      const int64_t j = col[t];
-      int64_t found = -1;
-      for (int64_t u = row_ptr[j]; u < row_ptr[j + 1]; ++u)
-        if (col[u] == r) {
-          found = u;
-          break;
-        }
-      perm[t] = found;
-      if (found < 0) atomicOr(missing, 1);
+                                                              int64_t nnz, int64_t* perm, int* missing) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * 256) {
+    int64_t lo = 0, hi = d;  // row_ptr[lo] <= t < row_ptr[hi]
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (row_ptr[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
     }
+    const int64_t r = lo;
+    const int64_t j = col[t];
+    int64_t found = -1;
+    for (int64_t u = row_ptr[j]; u < row_ptr[j + 1]; ++u)
+      if (col[u] == r) {
+        found = u;
+        break;
+      }
+    perm[t] = found;
+    if (found < 0) atomicOr(missing, 1);
   }
 }
 
+// out[t] = scale * (a[t] + a[perm[t]]) / 2: the derivative along symmetric perturbations from
+// per-entry accumulators (either orientation, since the mean is symmetric in the pair).
 template <typename TA, typename TO>
-__global__ void __launch_bounds__(256) permute_scale_kernel(const TA* a, const int64_t* perm, int64_t n, double scale,
-                                                            TO* out) {
+__global__ void __launch_bounds__(256) sym_scale_kernel(const TA* a, const int64_t* perm, int64_t n, double scale,
+                                                        TO* out) {
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256)
-    out[t] = (TO)((double)a[perm[t]] * scale);
+    out[t] = (TO)(0.5 * ((double)a[t] + (double)a[perm[t]]) * scale);
 }
 
 // ------------------------------------------------------------------------------------
 // reductions and utilities
 // ------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(1024) reduce_moments_kernel(const double* part, int64_t ntiles, int M, int k_lo,
-                                                              int64_t kstride, double* mu, int ldmu) {
-  const int k = k_lo + blockIdx.x;
+// Stage 1 of the moment reduction: block (k, probe group, chunk) sums tiles
+// [chunk * per, (chunk + 1) * per) with 16 slices x 4 independent accumulators per probe,
+// combined in a fixed order.  Stage 2 adds the chunks in order.  Deterministic.
+constexpr int kRedChunks = 16;
+
+__global__ void __launch_bounds__(1024) reduce_moments_stage1(const double* part, int64_t ntiles, int M,
+                                                              int64_t kstride, double* tmp) {
+  const int kk = blockIdx.x;
   const int j = blockIdx.y * 64 + (threadIdx.x & 63);
-  const int q = threadIdx.x >> 6;  // 16 slices over tiles
-  double s = 0.0;
+  const int q = threadIdx.x >> 6;  // 16 slices
+  const int64_t per = (ntiles + kRedChunks - 1) / kRedChunks;
+  const int64_t t0 = (int64_t)blockIdx.z * per;
+  const int64_t t1 = min(ntiles, t0 + per);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (j < M) {
-    const double* p = part + (int64_t)blockIdx.x * kstride + j;
-    for (int64_t t = q; t < ntiles; t += 16) s += p[t * M];
+    const double* p = part + (int64_t)kk * kstride + j;
+    int64_t t = t0 + q;
+    for (; t + 48 < t1; t += 64) {
+      a0 += p[t * M];
+      a1 += p[(t + 16) * M];
+      a2 += p[(t + 32) * M];
+      a3 += p[(t + 48) * M];
+    }
+    for (; t < t1; t += 16) a0 += p[t * M];
   }
   __shared__ double sh[16][64];
-  sh[q][threadIdx.x & 63] = s;
+  sh[q][threadIdx.x & 63] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (q == 0 && j < M) {
     double sum = 0.0;
     for (int r = 0; r < 16; ++r) sum += sh[r][threadIdx.x & 63];
-    mu[(int64_t)j * ldmu + k] = sum;
+    tmp[((int64_t)kk * kRedChunks + blockIdx.z) * M + j] = sum;
+  }
+}
+
+__global__ void __launch_bounds__(256) reduce_moments_stage2(const double* tmp, int M, int k_lo, int nk, double* mu,
+                                                             int ldmu) {
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < (int64_t)nk * M; x += (int64_t)gridDim.x * 256) {
+    const int kk = (int)(x / M);
+    const int j = (int)(x - (int64_t)kk * M);
+    double sum = 0.0;
+    for (int c = 0; c < kRedChunks; ++c) sum += tmp[((int64_t)kk * kRedChunks + c) * M + j];
+    mu[(int64_t)j * ldmu + k_lo + kk] = sum;
   }
 }
 
@@ -758,13 +846,19 @@ __global__ void __launch_bounds__(256) scale_kernel(const TA* a, int64_t n, doub
 }
 
 template <typename VT>
-__global__ void __launch_bounds__(256) fill_probe_kernel(VT* out, double c, uint64_t seed, int64_t d, int M) {
+__global__ void __launch_bounds__(256) seed_kernel(VT* out, const VT* W, const VT* Wm, const VT* Wp, double cv,
+                                                   double cw, double cwm, double cwp, uint64_t seed, int64_t d,
+                                                   int M) {
   const int64_t total = d * (int64_t)M;
   for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
     const int64_t r = x / M;
     const int j = (int)(x - r * M);
     const uint64_t w = probe_word(seed, (uint64_t)r, (uint32_t)(j >> 6));
-    out[x] = (VT)(((w >> (j & 63)) & 1u) ? -c : c);
+    VT o = (VT)(((w >> (j & 63)) & 1u) ? -cv : cv);
+    if (W) o = fma((VT)cw, W[x], o);
+    if (Wm) o = fma((VT)cwm, Wm[x], o);
+    if (Wp) o = fma((VT)cwp, Wp[x], o);
+    out[x] = o;
   }
 }
 
@@ -796,7 +890,7 @@ static unsigned grid_for(int64_t work, int per_block, unsigned cap = 65536u) {
   return (unsigned)g;
 }
 
-template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, bool MU>
+template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, int MU>
 static hipError_t go_step(const StepLaunch& L, hipStream_t s) {
   const int64_t per = (L.ntiles + 7) / 8;
   dim3 grid((unsigned)(per * 8), (unsigned)L.shape.probe_tiles);
@@ -805,28 +899,34 @@ static hipError_t go_step(const StepLaunch& L, hipStream_t s) {
 }
 
 template <typename VT, int VALT, int VPL>
-static hipError_t step_by_src(const StepLaunch& L, int g, int d, int p, bool mu, hipStream_t s) {
+static hipError_t step_by_src(const StepLaunch& L, int g, int d, int p, int mu, hipStream_t s) {
 #define LD_CASE(G_, D_, P_, MU_) \
   if (g == G_ && d == D_ && p == P_ && mu == MU_) return go_step<VT, VALT, VPL, G_, D_, P_, MU_>(L, s);
-  // Algorithm 1 forward: k = 0, k = 1, k >= 2 (also used for recomputation without moments)
-  LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, true)
-  LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, true)
-  LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, true)
-  LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, false)
-  LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, false)
-  LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, false)
+  // Algorithm 1 forward: k = 0, k = 1, k >= 2 (MU_NONE: recomputation; MU_PAIR: product identities)
+  LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, MU_PROBE)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, MU_PROBE)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, MU_PROBE)
+  LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, MU_PAIR)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, MU_PAIR)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, MU_PAIR)
+  LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, MU_NONE)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, MU_NONE)
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, MU_NONE)
   // Algorithm 2: T = C X, then W_{k+1} = alpha C^T T + beta W_k - W_{k-1}
-  LD_CASE(SRC_HASH, SRC_NONE, SRC_NONE, false)
-  LD_CASE(SRC_BUF, SRC_NONE, SRC_NONE, false)
-  LD_CASE(SRC_BUF, SRC_HASH, SRC_NONE, true)
-  LD_CASE(SRC_BUF, SRC_BUF, SRC_HASH, true)
-  LD_CASE(SRC_BUF, SRC_BUF, SRC_BUF, true)
+  LD_CASE(SRC_HASH, SRC_NONE, SRC_NONE, MU_NONE)
+  LD_CASE(SRC_BUF, SRC_NONE, SRC_NONE, MU_NONE)
+  LD_CASE(SRC_BUF, SRC_HASH, SRC_NONE, MU_PROBE)
+  LD_CASE(SRC_BUF, SRC_BUF, SRC_HASH, MU_PROBE)
+  LD_CASE(SRC_BUF, SRC_BUF, SRC_BUF, MU_PROBE)
+  LD_CASE(SRC_BUF, SRC_HASH, SRC_NONE, MU_PAIR)
+  LD_CASE(SRC_BUF, SRC_BUF, SRC_HASH, MU_PAIR)
+  LD_CASE(SRC_BUF, SRC_BUF, SRC_BUF, MU_PAIR)
 #undef LD_CASE
   return hipErrorInvalidValue;
 }
 
 template <typename VT, int VALT>
-static hipError_t step_by_vpl(const StepLaunch& L, int g, int d, int p, bool mu, hipStream_t s) {
+static hipError_t step_by_vpl(const StepLaunch& L, int g, int d, int p, int mu, hipStream_t s) {
   switch (L.shape.vpl) {
     case 1: return step_by_src<VT, VALT, 1>(L, g, d, p, mu, s);
     case 2: return step_by_src<VT, VALT, 2>(L, g, d, p, mu, s);
@@ -837,7 +937,7 @@ static hipError_t step_by_vpl(const StepLaunch& L, int g, int d, int p, bool mu,
   }
 }
 
-hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, bool mu,
+hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu,
                        hipStream_t s) {
   if (L.ntiles <= 0) return hipSuccess;
   if (vec_f64) {
@@ -902,37 +1002,43 @@ hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64,
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t* perm, int* missing,
-                                  hipStream_t s) {
-  if (d <= 0) return hipSuccess;
-  hipLaunchKernelGGL(transpose_index_kernel, dim3(grid_for(d, 256)), dim3(256), 0, s, row_ptr, col, d, perm, missing);
+hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz, int64_t* perm,
+                                  int* missing, hipStream_t s) {
+  if (d <= 0 || nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_index_kernel, dim3(grid_for(nnz, 256, 1u << 20)), dim3(256), 0, s, row_ptr, col, d,
+                     nnz, perm, missing);
   return hipGetLastError();
 }
 
-hipError_t launch_permute_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,
-                                int out_f64, hipStream_t s) {
+hipError_t launch_sym_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,
+                            int out_f64, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned g = grid_for(n, 256);
   if (a_f64 && out_f64)
-    hipLaunchKernelGGL((permute_scale_kernel<double, double>), dim3(g), dim3(256), 0, s, (const double*)a, perm, n,
-                       scale, (double*)out);
+    hipLaunchKernelGGL((sym_scale_kernel<double, double>), dim3(g), dim3(256), 0, s, (const double*)a, perm, n, scale,
+                       (double*)out);
   else if (a_f64)
-    hipLaunchKernelGGL((permute_scale_kernel<double, float>), dim3(g), dim3(256), 0, s, (const double*)a, perm, n,
-                       scale, (float*)out);
+    hipLaunchKernelGGL((sym_scale_kernel<double, float>), dim3(g), dim3(256), 0, s, (const double*)a, perm, n, scale,
+                       (float*)out);
   else if (out_f64)
-    hipLaunchKernelGGL((permute_scale_kernel<float, double>), dim3(g), dim3(256), 0, s, (const float*)a, perm, n,
-                       scale, (double*)out);
+    hipLaunchKernelGGL((sym_scale_kernel<float, double>), dim3(g), dim3(256), 0, s, (const float*)a, perm, n, scale,
+                       (double*)out);
   else
-    hipLaunchKernelGGL((permute_scale_kernel<float, float>), dim3(g), dim3(256), 0, s, (const float*)a, perm, n,
-                       scale, (float*)out);
+    hipLaunchKernelGGL((sym_scale_kernel<float, float>), dim3(g), dim3(256), 0, s, (const float*)a, perm, n, scale,
+                       (float*)out);
   return hipGetLastError();
 }
 
+size_t reduce_scratch_bytes(int nk, int M) { return (size_t)std::max(nk, 1) * kRedChunks * M * sizeof(double); }
+
 hipError_t launch_reduce_moments(const double* part, int64_t ntiles, int M, int k_lo, int k_hi, int64_t kstride,
-                                 double* mu, int ldmu, hipStream_t s) {
+                                 double* mu, int ldmu, double* tmp, hipStream_t s) {
   if (k_hi < k_lo) return hipSuccess;
-  dim3 grid((unsigned)(k_hi - k_lo + 1), (unsigned)((M + 63) / 64));
-  hipLaunchKernelGGL(reduce_moments_kernel, grid, dim3(1024), 0, s, part, ntiles, M, k_lo, kstride, mu, ldmu);
+  const int nk = k_hi - k_lo + 1;
+  dim3 grid((unsigned)nk, (unsigned)((M + 63) / 64), (unsigned)kRedChunks);
+  hipLaunchKernelGGL(reduce_moments_stage1, grid, dim3(1024), 0, s, part, ntiles, M, kstride, tmp);
+  hipLaunchKernelGGL(reduce_moments_stage2, dim3(grid_for((int64_t)nk * M, 256)), dim3(256), 0, s, tmp, M, k_lo, nk,
+                     mu, ldmu);
   return hipGetLastError();
 }
 
@@ -1036,13 +1142,18 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_fill_probe(void* out, int vec_f64, double c, uint64_t seed, int64_t d, int M, hipStream_t s) {
+hipError_t launch_seed(void* out, int vec_f64, const void* W, const void* Wm, const void* Wp, double cv, double cw,
+                       double cwm, double cwp, uint64_t seed, int64_t d, int M, hipStream_t s) {
   if (d <= 0) return hipSuccess;
   const unsigned g = grid_for(d * (int64_t)M, 256, 1u << 20);
   if (vec_f64)
-    hipLaunchKernelGGL(fill_probe_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(out), c, seed, d, M);
+    hipLaunchKernelGGL(seed_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(out),
+                       static_cast<const double*>(W), static_cast<const double*>(Wm), static_cast<const double*>(Wp),
+                       cv, cw, cwm, cwp, seed, d, M);
   else
-    hipLaunchKernelGGL(fill_probe_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(out), c, seed, d, M);
+    hipLaunchKernelGGL(seed_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(out),
+                       static_cast<const float*>(W), static_cast<const float*>(Wm), static_cast<const float*>(Wp), cv,
+                       cw, cwm, cwp, seed, d, M);
   return hipGetLastError();
 }
 

@@ -27,8 +27,9 @@ def _batch(count, storage, d_max=6000, seed0=300):
     return mats
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-4), ("f64", 1e-10), ("bf16", 1e-4)])
-def test_batched_parity(ld, oracle_lib, storage, tol):
+@pytest.mark.parametrize("storage,tol,plain", [("f32", 1e-4, False), ("f64", 1e-10, False), ("bf16", 1e-4, False),
+                                               ("f32", 1e-4, True), ("f64", 1e-10, True)])
+def test_batched_parity(ld, oracle_lib, storage, tol, plain):
     mats = _batch(14, storage)
     bounds = [oracle_lib.gershgorin(B) for B in mats]
     a = [x[0] for x in bounds]
@@ -36,15 +37,15 @@ def test_batched_parity(ld, oracle_lib, storage, tol):
     ns = [B.meta["n"] for B in mats]
     M, seed = 32, 77
     D = [dev(B) for B in mats]
-    say(f"batched {storage} count={len(mats)}")
-    res = ld.ld_logdet_cheb_batched(D, a, b, ns, M, seed)
+    say(f"batched {storage} count={len(mats)} plain={plain}")
+    res = ld.ld_logdet_cheb_batched(D, a, b, ns, M, seed, plain=plain)
     for i, B in enumerate(mats):
         o = oracle_lib.logdet(B, a[i], b[i], ns[i], M, seed=seed + i)
         assert rel(res[i]["logdet"], o["gamma"], FLOOR * B.d) <= tol, (i, res[i]["logdet"], o["gamma"])
         assert rel(res[i]["std_err"], o["std_err"]) <= max(1e-3, 100 * tol)
     # second call hits the cached graph and reproduces the result bit for bit
     say("batched replay")
-    res2 = ld.ld_logdet_cheb_batched(D, a, b, ns, M, seed)
+    res2 = ld.ld_logdet_cheb_batched(D, a, b, ns, M, seed, plain=plain)
     assert [r["logdet"] for r in res2] == [r["logdet"] for r in res]
 
 

@@ -70,11 +70,14 @@ def test_gershgorin_matches_oracle(ld, oracle_lib, storage):
     assert a == ea and b == eb
 
 
-def test_cfg0_fp64_parity(ld, oracle_lib):
-    """32x32 Dirichlet grid + 0.1 I, a = 0.1, b = 8.1, M = 50, n = 30, FP64 (rel 1e-10)."""
+@pytest.mark.parametrize("plain", [False, True])
+def test_cfg0_fp64_parity(ld, oracle_lib, plain):
+    """32x32 Dirichlet grid + 0.1 I, a = 0.1, b = 8.1, M = 50, n = 30, FP64 (rel 1e-10); both the
+    product-identity form (ceil(n/2) products) and the plain one-product-per-degree form."""
     B = synth.grid_laplacian_2d(32)
-    say("cfg0 fp64")
-    r = ld.ld_logdet_cheb(dev(B, shift=0.1), 0.1, 8.1, 30, 50, 1, want_moments=True, want_probes=True)
+    say(f"cfg0 fp64 plain={plain}")
+    r = ld.ld_logdet_cheb(dev(B, shift=0.1), 0.1, 8.1, 30, 50, 1, want_moments=True, want_probes=True,
+                          plain=plain)
     o = oracle_lib.logdet(B, 0.1, 8.1, 30, 50, seed=1, shift=0.1, want_moments=True)
     _compare(r, o, TOL64, B.d, "cfg0")
     assert r["status"] == 0 and r["flags"] == 0
@@ -91,14 +94,15 @@ CASES32 = [
 ]
 
 
+@pytest.mark.parametrize("plain", [False, True])
 @pytest.mark.parametrize("case", CASES32, ids=[c[0] for c in CASES32])
-def test_fp32_path_parity(ld, oracle_lib, case):
+def test_fp32_path_parity(ld, oracle_lib, case, plain):
     name, build, shift, a, b, n, M = case
     B = build()
     if a is None:
         a, b = oracle_lib.gershgorin(B, shift)
-    say(f"fp32 parity {name}")
-    r = ld.ld_logdet_cheb(dev(B, shift=shift), a, b, n, M, 11, want_moments=True, want_probes=True)
+    say(f"fp32 parity {name} plain={plain}")
+    r = ld.ld_logdet_cheb(dev(B, shift=shift), a, b, n, M, 11, want_moments=True, want_probes=True, plain=plain)
     o = oracle_lib.logdet(B, a, b, n, M, seed=11, shift=shift, want_moments=True)
     _compare(r, o, TOL32, B.d, name)
 
@@ -115,21 +119,22 @@ def test_fp64_vectors_with_fp32_values(ld, oracle_lib):
 @pytest.mark.parametrize("M", [1, 2, 3, 7, 33, 64, 130, 300])
 @pytest.mark.parametrize("vec64", [True, False])
 def test_probe_counts_and_tiles(ld, oracle_lib, M, vec64):
-    """Probe counts that leave lanes idle, need narrow groups, or span several probe tiles."""
+    """Probe counts that leave lanes idle, need narrow groups, or span several probe tiles; odd degree."""
     B = synth.random_sparse_spd(777, 3, 9, 1.0, "f64" if vec64 else "f32")
     a, b = oracle_lib.gershgorin(B)
     say(f"M={M} vec64={vec64}")
-    r = ld.ld_logdet_cheb(dev(B), a, b, 12, M, 5, vec_f64=vec64, want_moments=True, want_probes=True)
-    o = oracle_lib.logdet(B, a, b, 12, M, seed=5, want_moments=True)
+    r = ld.ld_logdet_cheb(dev(B), a, b, 13, M, 5, vec_f64=vec64, want_moments=True, want_probes=True)
+    o = oracle_lib.logdet(B, a, b, 13, M, seed=5, want_moments=True)
     _compare(r, o, TOL64 if vec64 else TOL32, B.d, f"M={M}")
 
 
-@pytest.mark.parametrize("n", [0, 1, 2, 3])
-def test_low_degrees(ld, oracle_lib, n):
-    """n = 0 (Gamma = d log((a+b)/2)) and the first steps of the recurrence."""
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5])
+def test_low_degrees(ld, oracle_lib, n, plain):
+    """n = 0 (Gamma = d log((a+b)/2)) and the first steps of the recurrence, odd and even n."""
     B = synth.grid_laplacian_2d(9)
-    say(f"n={n}")
-    r = ld.ld_logdet_cheb(dev(B, shift=0.2), 0.2, 8.2, n, 6, 4, want_moments=True, want_probes=True)
+    say(f"n={n} plain={plain}")
+    r = ld.ld_logdet_cheb(dev(B, shift=0.2), 0.2, 8.2, n, 6, 4, want_moments=True, want_probes=True, plain=plain)
     o = oracle_lib.logdet(B, 0.2, 8.2, n, 6, seed=4, shift=0.2, want_moments=True)
     _compare(r, o, TOL64, B.d, f"n={n}")
     if n == 0:
@@ -211,7 +216,7 @@ def test_caller_workspace_and_timing(ld, oracle_lib):
     r = ld.ld_logdet_cheb(D, 0.3, 8.3, n, M, 3, workspace=ws, timing=True)
     o = oracle_lib.logdet(B, 0.3, 8.3, n, M, seed=3, shift=0.3)
     assert rel(r["logdet"], o["gamma"]) <= TOL32
-    assert r["kernel_launches"] == n and r["kernel_ms"] > 0
+    assert r["kernel_launches"] == (n + 1) // 2 and r["kernel_ms"] > 0  # product identities: ceil(n/2) steps
     small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
     with pytest.raises(ld.LogdetChebError):
         ld.ld_logdet_cheb(D, 0.3, 8.3, n, M, 3, workspace=small)

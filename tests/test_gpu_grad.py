@@ -27,14 +27,18 @@ def _nw(g, ref):
     return float(np.max(np.abs(g - ref)) / max(np.max(np.abs(ref)), 1e-300))
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 7, 30])
-@pytest.mark.parametrize("stride", [0, 2, 3, 5, 100])
-def test_grad_fp64_parity(ld, oracle_lib, n, stride):
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 30])
+@pytest.mark.parametrize("stride", [0, 1, 2, 3, 5, 100])
+def test_grad_fp64_parity(ld, oracle_lib, n, stride, plain):
+    """Gradient along symmetric perturbations, per stored entry, against the oracle's reverse mode:
+    both the product-identity form and the plain recurrence, every checkpoint stride."""
     B = synth.random_sparse_spd(2000, 4, 17, 1.0, "f64")
     a, b = oracle_lib.gershgorin(B)
     M, seed, shift, go = 16, 9, 0.25, 1.7
-    say(f"grad fp64 n={n} stride={stride}")
-    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a + shift, b + shift, n, M, seed, go, ckpt_stride=stride)
+    say(f"grad fp64 n={n} stride={stride} plain={plain}")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a + shift, b + shift, n, M, seed, go, ckpt_stride=stride,
+                                  plain=plain)
     o = oracle_lib.logdet_grad(B, a + shift, b + shift, n, M, seed=seed, shift=shift)
     assert _nw(g.cpu().numpy(), go * o["grad"]) <= 1e-10
     assert rel(r["grad_shift"], go * o["grad_shift"]) <= 1e-10
@@ -57,15 +61,16 @@ def test_grad_rows_without_diagonal(ld, oracle_lib):
     assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-10
 
 
+@pytest.mark.parametrize("plain", [False, True])
 @pytest.mark.parametrize("M", [1, 3, 32, 64])
-def test_grad_fp32_gmrf_parity(ld, oracle_lib, M):
+def test_grad_fp32_gmrf_parity(ld, oracle_lib, M, plain):
     """3-D GMRF precision Q = tau (kappa^2 I + L) in FP32 with the kappa^2 shift kept in FP64."""
     N, tau, kappa, n = 10, 1.0, 0.3, 60
     L = synth.grid_laplacian_3d(N, "f32")
     shift = tau * kappa ** 2
     a, b = tau * kappa ** 2, tau * (kappa ** 2 + 12.0)
-    say(f"grad fp32 gmrf M={M}")
-    r, g = ld.ld_logdet_cheb_grad(dev(L, shift=shift), a, b, n, M, 3)
+    say(f"grad fp32 gmrf M={M} plain={plain}")
+    r, g = ld.ld_logdet_cheb_grad(dev(L, shift=shift), a, b, n, M, 3, plain=plain)
     o = oracle_lib.logdet_grad(L, a, b, n, M, seed=3, shift=shift)
     assert _nw(g.cpu().numpy(), o["grad"]) <= 1e-4
     assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-4

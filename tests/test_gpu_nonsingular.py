@@ -43,15 +43,15 @@ def _bounds(C):
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-4), ("bf16", 1e-4)])
-@pytest.mark.parametrize("given_t", [False, True])
-def test_alg2_parity(ld, oracle_lib, storage, tol, given_t):
+@pytest.mark.parametrize("given_t,plain", [(False, False), (True, False), (False, True)])
+def test_alg2_parity(ld, oracle_lib, storage, tol, given_t, plain):
     C = synth.random_nonsingular(1200, 8, 6, 3.0, storage)
     smin, smax = _bounds(C)
     n, M = 60, 32
     D = dev(C)
     Ct = ld.ld_transpose(D) if given_t else None
-    say(f"alg2 {storage} given_t={given_t}")
-    r = ld.ld_logabsdet_cheb(D, Ct, smin, smax, n, M, 6, want_probes=True)
+    say(f"alg2 {storage} given_t={given_t} plain={plain}")
+    r = ld.ld_logabsdet_cheb(D, Ct, smin, smax, n, M, 6, want_probes=True, plain=plain)
     o = oracle_lib.logabsdet(C, smin, smax, n, M, seed=6)
     assert rel(r["logdet"], o["gamma"], FLOOR * C.d) <= tol, (r["logdet"], o["gamma"])
     assert np.max(np.abs(r["s"] - o["s"])) <= tol * np.max(np.abs(o["s"]))

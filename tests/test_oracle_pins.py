@@ -383,9 +383,16 @@ def test_alg2_on_spd_matches_alg1_in_expectation(oracle_lib):
 # Gradient (reverse mode of Algorithm 1)
 # --------------------------------------------------------------------------------------
 
+def _transpose_index(B):
+    pos = {(int(r), int(c)): t for t, (r, c) in enumerate(zip(B.row_of_entry(), B.col))}
+    return np.array([pos[(int(c), int(r))] for r, c in zip(B.row_of_entry(), B.col)])
+
+
 def test_gradient_vs_central_differences(oracle_lib):
-    """P10: d Gamma/d B_t by central differences of the oracle's own estimate (same probes, a, b
-    fixed); the estimate is a polynomial in the entries so the O(h^2) error is tiny."""
+    """P10: central differences of the oracle's own estimate (same probes, a, b fixed).  Moving a
+    single stored entry by h changes Gamma by g_t h; moving B_ij and B_ji together changes it by
+    (g_ij + g_ji) h = 2 g_ij h, since the gradient of v^T p(B) v is symmetric at symmetric B.  The
+    estimate is a polynomial in the entries, so the O(h^2) error is tiny."""
     B = synth.random_sparse_spd(24, k_off=3, mseed=21, storage="f64")
     a, b = oracle_lib.gershgorin(B)
     a, b = 0.9 * a, 1.1 * b
@@ -393,14 +400,22 @@ def test_gradient_vs_central_differences(oracle_lib):
     g = oracle_lib.logdet_grad(B, a, b, n, m, seed=seed, shift=shift)
     base = oracle_lib.logdet(B, a, b, n, m, seed=seed, shift=shift)["gamma"]
     assert abs(g["gamma"] - base) < 1e-12 * abs(base)
+    tr = _transpose_index(B)
     h = 1e-5
     for t in range(0, B.nnz, 7):
-        vp = B.val.copy(); vp[t] += h
-        vm = B.val.copy(); vm[t] -= h
-        fp = oracle_lib.logdet(synth.CSR(B.d, B.row_ptr, B.col, vp), a, b, n, m, seed=seed, shift=shift)["gamma"]
-        fm = oracle_lib.logdet(synth.CSR(B.d, B.row_ptr, B.col, vm), a, b, n, m, seed=seed, shift=shift)["gamma"]
-        fd = (fp - fm) / (2 * h)
-        assert abs(fd - g["grad"][t]) <= 1e-7 * max(1.0, abs(fd)), t
+        for mirrored in (False, True):
+            vp = B.val.copy(); vp[t] += h
+            vm = B.val.copy(); vm[t] -= h
+            if mirrored and tr[t] != t:
+                vp[tr[t]] += h
+                vm[tr[t]] -= h
+            fp = oracle_lib.logdet(synth.CSR(B.d, B.row_ptr, B.col, vp), a, b, n, m, seed=seed, shift=shift)["gamma"]
+            fm = oracle_lib.logdet(synth.CSR(B.d, B.row_ptr, B.col, vm), a, b, n, m, seed=seed, shift=shift)["gamma"]
+            fd = (fp - fm) / (2 * h)
+            expect = g["grad"][t] * (2.0 if (mirrored and tr[t] != t) else 1.0)
+            assert abs(fd - expect) <= 1e-7 * max(1.0, abs(fd)), (t, mirrored)
+    # the gradient is symmetric: mirrored entries carry the same value
+    np.testing.assert_allclose(g["grad"], g["grad"][tr], rtol=1e-13, atol=0)
     fp = oracle_lib.logdet(B, a, b, n, m, seed=seed, shift=shift + h)["gamma"]
     fm = oracle_lib.logdet(B, a, b, n, m, seed=seed, shift=shift - h)["gamma"]
     assert abs((fp - fm) / (2 * h) - g["grad_shift"]) <= 1e-7 * max(1.0, abs(g["grad_shift"]))
