@@ -79,10 +79,12 @@ def step_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int) -> int:
     return nnz * (val_bytes + 4) + (d + 1) * 8 + 3 * d * M * vec_bytes
 
 
-def adjoint_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int) -> int:
-    """Compulsory bytes of one adjoint step: the CSR matrix, y_{k+1} and w_k read once each, y_{k+2}
-    read, y_k written, and the nnz gradient accumulators read and written."""
-    return nnz * (val_bytes + 4) + (d + 1) * 8 + 4 * d * M * vec_bytes + 2 * nnz * acc_bytes
+def adjoint_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int, pair: bool) -> int:
+    """Compulsory bytes of one adjoint step: the CSR matrix, y_{j+1} and w_j read once each, y_{j+2}
+    read, y_j written, the nnz gradient accumulators read and written, and with the product
+    identities the seed's w_{j-1} and w_{j+1}."""
+    vectors = 6 if pair else 4
+    return nnz * (val_bytes + 4) + (d + 1) * 8 + vectors * d * M * vec_bytes + 2 * nnz * acc_bytes
 
 
 def traffic_from_profiles(kernel_tag: str, workload_name: str):
@@ -244,7 +246,7 @@ def main() -> None:
 
     # dominant kernel: the larger of the summed step and adjoint kernel times
     sb = step_bytes(d, nnz, M, val_bytes, vec_bytes)
-    ab_ = adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes)
+    ab_ = adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes, True)
     if adj_ms > step_ms and adj_n > 0:
         tag, avg_ms, bytes_ = "adjoint", adj_ms / adj_n, ab_
     else:
@@ -341,7 +343,9 @@ def bench_batch(args, W, copy_gbps) -> None:
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     gms /= args.steps
     vec_bytes = 4
-    alg = sum(ns[i] * (mats[i].nnz * 8 + (mats[i].d + 1) * 8 + 3 * mats[i].d * M * vec_bytes) for i in range(len(mats)))
+    steps = [(x + 1) // 2 for x in ns]  # product identities: ceil(n/2) sparse products per member
+    alg = sum(steps[i] * (mats[i].nnz * 8 + (mats[i].d + 1) * 8 + 3 * mats[i].d * M * vec_bytes)
+              for i in range(len(mats)))
     achieved = alg / (gms / 1e3) / 1e9
     cpu = None
     if not args.no_cpu_baseline:

@@ -84,7 +84,9 @@ typedef struct {
     void *workspace;          /* device scratch or NULL (then the library allocates on `stream`) */
     size_t workspace_bytes;
     int32_t vec_f64;          /* recurrence vectors in FP64 (1) or FP32 (0) */
-    int32_t ckpt_stride;      /* gradient: checkpoint every s steps; 0 = ceil(sqrt(n)) */
+    int32_t ckpt_stride;      /* gradient: checkpoint every s steps; 0 = automatic: keep every
+                                 W_k when that fits (the workspace given, or 40% of free device
+                                 memory), else every ceil(sqrt(steps)) */
     int32_t tile;             /* kernel shape: 0 = autotuned, > 0 = rows per workgroup */
     int32_t probe_tile;       /* kernel shape: 0 = autotuned, > 0 = probes per pass over the matrix */
     int32_t timing;           /* 1 = time recurrence-step kernels with HIP events on `stream` */

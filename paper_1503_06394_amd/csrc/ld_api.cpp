@@ -680,9 +680,9 @@ GradPlan plan_grad(int n, bool pair, int stride) {
   return g;
 }
 
-size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, bool pair) {
+size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, int stride, bool pair) {
   const size_t vb = vec_f64 ? 8 : 4;
-  const GradPlan g = plan_grad(n, pair, opt ? opt->ckpt_stride : 0);
+  const GradPlan g = plan_grad(n, pair, stride);
   Shape sh = with_tile(base_shape(vec_f64, M), B->rows, B->nnz, 0);
   const int64_t ntiles = B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
   const int rows = std::max(partial_rows(n, g.pair), 1);
@@ -701,10 +701,29 @@ size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_o
 }
 
 // A non-symmetric pattern falls back to the plain recurrence, so size for both plans.
-size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
-  size_t w = grad_workspace_for(B, n, M, vec_f64, opt, false);
-  if (use_pairs(opt)) w = std::max(w, grad_workspace_for(B, n, M, vec_f64, opt, true));
+size_t grad_workspace_stride(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, int stride) {
+  size_t w = grad_workspace_for(B, n, M, vec_f64, stride, false);
+  if (use_pairs(opt)) w = std::max(w, grad_workspace_for(B, n, M, vec_f64, stride, true));
   return w;
+}
+
+// Checkpoint stride: the caller's, else 1 (every W_k kept, no recomputation) when that plan
+// fits the memory available -- the caller's workspace, or 40% of the device's free memory --
+// else ceil(sqrt(steps)).
+int choose_stride(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
+  if (opt && opt->ckpt_stride > 0) return opt->ckpt_stride;
+  size_t avail = 0;
+  if (opt && opt->workspace) {
+    avail = opt->workspace_bytes;
+  } else {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) avail = fr / 5 * 2;
+  }
+  return grad_workspace_stride(B, n, M, vec_f64, opt, 1) <= avail ? 1 : 0;
+}
+
+size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
+  return grad_workspace_stride(B, n, M, vec_f64, opt, choose_stride(B, n, M, vec_f64, opt));
 }
 
 }  // namespace
@@ -1012,7 +1031,8 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   if (sh.probe_tiles != 1)
     return fail(LD_EINVAL, "gradient needs M <= %d probes per call with these vectors", (1 << sh.lpr_log2) * sh.vpl);
   const int64_t ntiles = d > 0 ? (d + sh.tile_rows - 1) / sh.tile_rows : 0;
-  const size_t need = grad_workspace(B, n, M, vec_f64, opt);
+  const int stride = choose_stride(B, n, M, vec_f64, opt);
+  const size_t need = grad_workspace_stride(B, n, M, vec_f64, opt, stride);
   Workspace ws;
   rc = get_workspace(opt, need, s, ws);
   if (rc) return rc;
@@ -1030,7 +1050,7 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
     LD_HIP(hipStreamSynchronize(s));
   }
   const bool sym_pattern = miss == 0;
-  const GradPlan g = plan_grad(n, use_pairs(opt) && sym_pattern, opt ? opt->ckpt_stride : 0);
+  const GradPlan g = plan_grad(n, use_pairs(opt) && sym_pattern, stride);
   const bool pair = g.pair;
   const int nrows = partial_rows(n, pair);
   const size_t vecb = (size_t)d * M * vb;

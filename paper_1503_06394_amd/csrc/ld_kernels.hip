@@ -483,6 +483,13 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
           }
         }
       }
+      // accumulator slot this lane will own after the transposing reduction (wide groups),
+      // read before the gathers so its latency overlaps them
+      const bool wide = LPR >= kUnroll;
+      const int myu = wide ? (sub / (LPR / kUnroll)) & (kUnroll - 1) : 0;
+      const bool writer = wide && (sub & (LPR / kUnroll - 1)) == 0 && t + myu < e;
+      VT hold = VT(0);
+      if (writer) hold = Hacc[nz0 + t + myu];
       VT dot[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -509,12 +516,31 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
         for (int i = 0; i < VPL; ++i) dp = SYM ? fma(yg[i], wown[i], dp) : fma(yown[i], wg[i], dp);
         dot[u] = dp;
       }
-      for (int o = 1; o < LPR; o <<= 1)
+      if (wide) {
+        // transposing butterfly: each exchange hands half of the live values to the partner
+        // lane, so after log2(kUnroll) exchanges every lane holds one nonzero's partial;
+        // the remaining exchanges (offsets below LPR/kUnroll) add up the copies.
+        int o = LPR >> 1;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) dot[u] += __shfl_xor(dot[u], o, 64);
+        for (int h = kUnroll; h > 1; h >>= 1, o >>= 1) {
+          const bool up = (sub & o) != 0;
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (ok[u] && sub == (u & (LPR - 1))) Hacc[nz0 + t + u] += gw * dot[u];
+          for (int i = 0; i < h / 2; ++i) {
+            const VT send = up ? dot[i] : dot[i + h / 2];
+            const VT keep = up ? dot[i + h / 2] : dot[i];
+            dot[i] = keep + __shfl_xor(send, o, 64);
+          }
+        }
+        for (; o >= 1; o >>= 1) dot[0] += __shfl_xor(dot[0], o, 64);
+        if (writer) Hacc[nz0 + t + myu] = hold + gw * dot[0];
+      } else {
+        for (int o = 1; o < LPR; o <<= 1)
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) dot[u] += __shfl_xor(dot[u], o, 64);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          if (ok[u] && sub == (u & (LPR - 1))) Hacc[nz0 + t + u] += gw * dot[u];
+      }
     }
     if (has) {
       double dd = 0.0;
@@ -862,8 +888,25 @@ __global__ void __launch_bounds__(256) seed_kernel(VT* out, const VT* W, const V
   }
 }
 
+// Streaming copy: each thread moves four 16-byte vectors per pass (all four loads issued
+// before the stores), non-temporal on both sides.
 __global__ void __launch_bounds__(256) copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n16; t += (int64_t)gridDim.x * 256) dst[t] = src[t];
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4* s = reinterpret_cast<const u32x4*>(src);
+  u32x4* d = reinterpret_cast<u32x4*>(dst);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; t + 3 * stride < n16; t += 4 * stride) {
+    const u32x4 a = __builtin_nontemporal_load(s + t);
+    const u32x4 b = __builtin_nontemporal_load(s + t + stride);
+    const u32x4 c = __builtin_nontemporal_load(s + t + 2 * stride);
+    const u32x4 e = __builtin_nontemporal_load(s + t + 3 * stride);
+    __builtin_nontemporal_store(a, d + t);
+    __builtin_nontemporal_store(b, d + t + stride);
+    __builtin_nontemporal_store(c, d + t + 2 * stride);
+    __builtin_nontemporal_store(e, d + t + 3 * stride);
+  }
+  for (; t < n16; t += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(s + t), d + t);
 }
 
 __global__ void __launch_bounds__(256) copy_tail_kernel(const uint8_t* src, uint8_t* dst, int64_t n) {
@@ -1133,7 +1176,7 @@ hipError_t launch_scale_grad(const void* Gacc, int acc_f64, int64_t nnz, double 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const int64_t n16 = (int64_t)(bytes / 16);
   if (n16 > 0)
-    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16, 256, 1u << 20)), dim3(256), 0, s,
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16, 1024, 1u << 16)), dim3(256), 0, s,
                        static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
   const int64_t tail = (int64_t)(bytes - (size_t)n16 * 16);
   if (tail > 0)
