@@ -204,10 +204,23 @@ int staged_tile_cap(const Shape& sh, int64_t d, int64_t nnz) {
   return (int)std::max<int64_t>(rows, rpi);
 }
 
+// Default tile height: as tall as the LDS slice allows, but short enough that the matrix
+// spreads over at least ~1024 workgroups.
+Shape with_tile(Shape sh, int64_t d, int64_t nnz, int tile_override) {
+  const int rpi = rows_per_iter(sh);
+  if (tile_override > 0) {
+    sh.tile_rows = (tile_override + rpi - 1) / rpi * rpi;
+    return sh;
+  }
+  const int64_t spread = std::max<int64_t>(rpi, d / 1024 / rpi * rpi);
+  sh.tile_rows = (int)std::min<int64_t>(staged_tile_cap(sh, d, nnz), spread);
+  return sh;
+}
+
 // Tile heights the autotuner tries: the staging cap and two smaller heights.
 std::vector<int> tile_candidates(const Shape& sh, int64_t d, int64_t nnz) {
   const int rpi = rows_per_iter(sh);
-  const int cap = staged_tile_cap(sh, d, nnz);
+  const int cap = with_tile(sh, d, nnz, 0).tile_rows;
   std::vector<int> c;
   for (int div : {1, 2, 4}) {
     const int r = std::max(rpi, cap / div / rpi * rpi);
@@ -216,15 +229,6 @@ std::vector<int> tile_candidates(const Shape& sh, int64_t d, int64_t nnz) {
   return c;
 }
 
-Shape with_tile(Shape sh, int64_t d, int64_t nnz, int tile_override) {
-  const int rpi = rows_per_iter(sh);
-  if (tile_override > 0) {
-    sh.tile_rows = (tile_override + rpi - 1) / rpi * rpi;
-    return sh;
-  }
-  sh.tile_rows = staged_tile_cap(sh, d, nnz);
-  return sh;
-}
 
 struct TuneKey {
   int vec, valt, M, mode;

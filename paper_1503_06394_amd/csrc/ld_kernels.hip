@@ -25,7 +25,7 @@
 #include "ld_internal.h"
 
 #ifndef LD_UNROLL
-#define LD_UNROLL 8
+#define LD_UNROLL 4
 #endif
 #ifndef LD_NT
 #define LD_NT 1
@@ -220,10 +220,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   const bool staged = stage_tile<VALT>(T, rp, ci, D.val, row0, row_end, nz0);
 
   // MU_PROBE: mu = v^T W_{k+1}.  MU_PAIR: mu = W_k^T W_{k+1} and mu2 = W_{k+1}^T W_{k+1}, the two
-  // inner products the Chebyshev product identities turn into moments 2k+1 and 2k+2.
-  double mu[VPL], mu2[VPL];
+  // inner products the Chebyshev product identities turn into moments 2k+1 and 2k+2.  A lane
+  // sums over its few rows of the tile in the vector type; everything after that is FP64.
+  VT mu[VPL], mu2[VPL];
 #pragma unroll
-  for (int i = 0; i < VPL; ++i) mu[i] = mu2[i] = 0.0;
+  for (int i = 0; i < VPL; ++i) mu[i] = mu2[i] = VT(0);
 
   for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
     const int64_t row = base + grp;
@@ -343,16 +344,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
           const uint64_t w = probe_word(D.seed, (uint64_t)row, (uint32_t)(p0 >> 6));
           const uint32_t bits = (uint32_t)(w >> (p0 & 63));
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) {
-            const double x = (double)acc[i];
-            mu[i] += ((bits >> i) & 1u) ? -x : x;
-          }
+          for (int i = 0; i < VPL; ++i) mu[i] += ((bits >> i) & 1u) ? -acc[i] : acc[i];
         } else if constexpr (MU == MU_PAIR) {
 #pragma unroll
           for (int i = 0; i < VPL; ++i) {
-            const double x = (double)acc[i];
-            mu[i] = fma(x, (double)wk[i], mu[i]);
-            mu2[i] = fma(x, x, mu2[i]);
+            mu[i] = fma(acc[i], wk[i], mu[i]);
+            mu2[i] = fma(acc[i], acc[i], mu2[i]);
           }
         }
       }
@@ -363,11 +360,17 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
     // fixed-order reduction: wave butterfly, then waves summed in order through LDS that
     // the tile's CSR slice no longer needs
     constexpr int NQ = MU == MU_PAIR ? 2 : 1;
+    double m1[VPL], m2[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      m1[i] = (double)mu[i];
+      m2[i] = (double)mu2[i];
+    }
     for (int o = LPR; o < 64; o <<= 1)
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
-        mu[i] += __shfl_xor(mu[i], o, 64);
-        if constexpr (NQ == 2) mu2[i] += __shfl_xor(mu2[i], o, 64);
+        m1[i] += __shfl_xor(m1[i], o, 64);
+        if constexpr (NQ == 2) m2[i] += __shfl_xor(m2[i], o, 64);
       }
     __syncthreads();
     double* red = reinterpret_cast<double*>(&T);  // [NQ][kWaves][256]
@@ -375,8 +378,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
     if (grp == 0)
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
-        red[wave * 256 + sub * VPL + i] = mu[i];
-        if constexpr (NQ == 2) red[(kWaves + wave) * 256 + sub * VPL + i] = mu2[i];
+        red[wave * 256 + sub * VPL + i] = m1[i];
+        if constexpr (NQ == 2) red[(kWaves + wave) * 256 + sub * VPL + i] = m2[i];
       }
     __syncthreads();
     for (int q = 0; q < NQ; ++q) {
