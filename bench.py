@@ -57,6 +57,12 @@ def workload(name: str):
         kappa = 0.3
         return dict(B=B, shift=kappa ** 2, a=kappa ** 2, b=kappa ** 2 + 12.0, n=60, M=32, seed=3, grad=True,
                     desc="3D GMRF Q=tau(kappa^2 I+L) 128^3, tau=1, kappa=0.3, FP32, M=32, n=60")
+    if name == "nonsingular1m":
+        C = synth.random_nonsingular(1_000_000, per_row=8, mseed=6, diag_add=3.0, storage="f32")
+        return dict(B=C, shift=0.0, a=None, b=None, n=100, M=32, seed=6, grad=False, nonsingular=True,
+                    desc="general sparse d=1e6, 8 N(0,1) entries per row + 3 I, FP32, Algorithm 2 "
+                         "(log|det C| = 1/2 log det C^T C), M=32, n=100, sigma bounds from a 300-step "
+                         "Lanczos estimate on C^T C (smin^2 = 0.5 x lowest Ritz value, smax = 1.05 x sqrt(highest))")
     if name == "batch256":
         mats = synth.random_batch(256, mseed0=1000)
         return dict(B=None, mats=mats, shift=0.0, a=None, b=None, n=None, M=32, seed=4, grad=False,
@@ -75,7 +81,10 @@ def workload(name: str):
 
 def step_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int) -> int:
     """Compulsory bytes of one recurrence step: the CSR matrix once (values, int32 columns, int64
-    row pointers), W_k read once, W_{k-1} read, W_{k+1} written."""
+    row pointers), W_k read once, W_{k-1} read, W_{k+1} written.  Algorithm 2 splits a degree into
+    T = C W_k (C, W_k gathered, T written) and W_{k+1} = alpha C^T T + beta W_k - W_{k-1} (C^T, T
+    gathered, W_k and W_{k-1} read, W_{k+1} written): 2 + 4 vectors over two launches, the same
+    three per launch on average."""
     return nnz * (val_bytes + 4) + (d + 1) * 8 + 3 * d * M * vec_bytes
 
 
@@ -119,14 +128,19 @@ def cpu_baseline(W: dict, a: float, b: float, gpu_probe_values) -> tuple:
     secs, done = 0.0, 0
     while done < M and (secs < 10.0 or done == 0):
         t0 = time.perf_counter()
-        if W["grad"]:
+        if W.get("nonsingular"):
+            oracle.logabsdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]))
+        elif W["grad"]:
             oracle.logdet_grad(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
         else:
             oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
         secs += time.perf_counter() - t0
         done += 1
-    r = oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]), shift=W["shift"])
-    work = done * n * B.nnz
+    if W.get("nonsingular"):
+        r = oracle.logabsdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]))
+    else:
+        r = oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]), shift=W["shift"])
+    work = done * n * B.nnz * (2 if W.get("nonsingular") else 1)
     kind = "fwd+grad" if W["grad"] else "fwd"
     base = {"value": work / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
             "sample": f"{kind} of probes 0..{done - 1} of {M} on the full matrix (degree {n}), single-threaded "
@@ -148,7 +162,7 @@ def main() -> None:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="random1m",
-                    choices=["random1m", "grid32", "gmrf128", "grid4096", "batch256"])
+                    choices=["random1m", "grid32", "gmrf128", "grid4096", "batch256", "nonsingular1m"])
     ap.add_argument("--compare-perprobe", action="store_true",
                     help="also time the plain per-probe FP64 form (one probe per call, FP64 values and vectors)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -191,9 +205,17 @@ def main() -> None:
     do_grad = W["grad"] and not args.fwd_only
     log(f"d={d} nnz={nnz} M={M} n={n} storage={B.storage} grad={do_grad}")
 
-    ws_fwd = torch.empty(ld.ld_workspace_bytes(D, n, M, 0), dtype=torch.uint8, device="cuda:0")
+    ws_fwd = torch.empty(ld.ld_workspace_bytes(D, n, M, 1 if W.get("nonsingular") else 0), dtype=torch.uint8,
+                         device="cuda:0")
     ws_grad = torch.empty(ld.ld_workspace_bytes(D, n, M, 2), dtype=torch.uint8, device="cuda:0") if do_grad else None
     gdt = torch.float64 if vec_f64 else torch.float32
+
+    nonsingular = W.get("nonsingular", False)
+    if nonsingular:
+        # estimated once per matrix, outside the timed region (the same for every evaluation)
+        lo, hi = ld.ld_spectral_estimate(D, iters=300, gram=True, seed=W["seed"])
+        W["a"], W["b"] = (0.5 * lo) ** 0.5, 1.05 * hi ** 0.5
+        log(f"sigma bounds from Lanczos: smin={W['a']:.5g} smax={W['b']:.5g}")
 
     def bounds():
         if W["a"] is not None:
@@ -202,6 +224,8 @@ def main() -> None:
 
     def one_step(timing: bool):
         a, b = bounds()
+        if nonsingular:
+            return ld.ld_logabsdet_cheb(D, None, a, b, n, M, W["seed"], workspace=ws_fwd, timing=timing)
         if do_grad:
             r, g = ld.ld_logdet_cheb_grad(D, a, b, n, M, W["seed"], 1.0, grad_dtype=gdt, workspace=ws_grad,
                                           timing=timing)
@@ -226,7 +250,7 @@ def main() -> None:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    work = M * n * nnz
+    work = M * n * nnz * (2 if nonsingular else 1)  # Algorithm 2 applies C and C^T per degree
     value = work / (ms_per_step / 1e3)
 
     # forward-only throughput on the same inputs (context)
@@ -242,7 +266,10 @@ def main() -> None:
             rf = ld.ld_logdet_cheb(D, a, b, n, M, W["seed"], workspace=ws_fwd)
         torch.cuda.synchronize()
         fwd_ms = (time.perf_counter() - tf0) * 1e3 / kf
-    rp = ld.ld_logdet_cheb(D, a, b, n, M, W["seed"], workspace=ws_fwd, want_probes=True)
+    if nonsingular:
+        rp = ld.ld_logabsdet_cheb(D, None, a, b, n, M, W["seed"], workspace=ws_fwd, want_probes=True)
+    else:
+        rp = ld.ld_logdet_cheb(D, a, b, n, M, W["seed"], workspace=ws_fwd, want_probes=True)
 
     # dominant kernel: the larger of the summed step and adjoint kernel times
     sb = step_bytes(d, nnz, M, val_bytes, vec_bytes)
@@ -280,7 +307,9 @@ def main() -> None:
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if vec_f64 else "f32", "data": "synthetic",
         "config": {"workload": W["desc"], "d": d, "nnz": nnz, "M": M, "n": n, "values": B.storage,
-                   "step": "gershgorin bounds + forward + gradient" if do_grad else "bounds + forward",
+                   "step": ("gershgorin bounds + forward + gradient" if do_grad else
+                            "Algorithm 2 forward (sigma bounds estimated once, before timing)" if nonsingular
+                            else "bounds + forward"),
                    "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "accuracy": accuracy, "kernels": extra,
     }

@@ -141,6 +141,16 @@ int ld_logdet_cheb_batched(int count, const ld_csr *Bs, const double *a, const d
  * a = min_i (B_ii + shift - sum_{j != i} |B_ij|), b = max_i (B_ii + shift + sum_{j != i} |B_ij|). */
 int ld_gershgorin(const ld_csr *B, double *a, double *b, void *stream);
 
+/* Estimates of the extreme eigenvalues of B + diag_shift I (gram = 0, B symmetric) or of
+ * C^T C (gram = 1; Ct nullable, built on the device if NULL) by `iters` steps of the Lanczos
+ * process in FP64 from a Rademacher start vector (probe 0 of `seed`), without
+ * reorthogonalisation.  *lo and *hi receive the extreme Ritz values: *hi <= lambda_max and
+ * *lo >= lambda_min, converging from inside the spectrum, so they are ESTIMATES, not bounds;
+ * callers pad them (Section 3.2 suggests power / inverse power iteration for these bounds).
+ * 2 <= iters <= 2000. */
+int ld_spectral_estimate(const ld_csr *B, const ld_csr *Ct, int gram, int iters, uint64_t seed,
+                         void *stream, double *lo, double *hi);
+
 /* Write the probe block: out[r * M + j] = v_j[r] (int8, +1/-1), r < rows, j < M. */
 int ld_probes(uint64_t seed, int M, int64_t rows, int8_t *out, void *stream);
 

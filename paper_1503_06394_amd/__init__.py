@@ -20,7 +20,7 @@ import torch
 __all__ = [
     "LogdetChebError", "DeviceCSR", "lib", "ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad",
     "ld_logdet_cheb_batched", "ld_gershgorin", "ld_probes", "ld_transpose", "ld_workspace_bytes", "ld_copy",
-    "ld_version", "ld_clear_cache", "LogdetCheb", "logdet_cheb", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
+    "ld_version", "ld_clear_cache", "ld_spectral_estimate", "LogdetCheb", "logdet_cheb", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblogdet_cheb.so")
@@ -82,6 +82,8 @@ def lib():
         L.ld_workspace_bytes.argtypes = [P, I, I, I, I]
         L.ld_workspace_bytes.restype = SZ
         L.ld_copy.argtypes = [P, P, SZ, P, P]
+        L.ld_spectral_estimate.argtypes = [P, P, I, I, U64, P, P, P]
+        L.ld_spectral_estimate.restype = I
         L.ld_clear_cache.argtypes = []
         L.ld_last_error.restype = ctypes.c_char_p
         L.ld_version.restype = ctypes.c_char_p
@@ -257,6 +259,20 @@ def ld_gershgorin(B: DeviceCSR, stream=None) -> tuple:
     _check(lib().ld_gershgorin(ctypes.byref(cb), ctypes.byref(a), ctypes.byref(b), _stream_ptr(stream)),
            "ld_gershgorin")
     return a.value, b.value
+
+
+def ld_spectral_estimate(B: DeviceCSR, iters: int = 200, gram: bool = False, Ct: DeviceCSR | None = None,
+                         seed: int = 0, stream=None) -> tuple:
+    """Extreme Ritz values of B + diag_shift I (or of C^T C with gram=True) after `iters` Lanczos
+    steps in FP64: estimates from inside the spectrum, not bounds."""
+    lo = ctypes.c_double()
+    hi = ctypes.c_double()
+    cb = B.c()
+    ct = Ct.c() if Ct is not None else None
+    _check(lib().ld_spectral_estimate(ctypes.byref(cb), ctypes.byref(ct) if ct is not None else None,
+                                      1 if gram else 0, int(iters), int(seed) & (2**64 - 1), _stream_ptr(stream),
+                                      ctypes.byref(lo), ctypes.byref(hi)), "ld_spectral_estimate")
+    return lo.value, hi.value
 
 
 def ld_probes(seed: int, M: int, rows: int, device="cuda", stream=None) -> torch.Tensor:

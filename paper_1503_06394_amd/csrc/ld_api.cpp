@@ -51,6 +51,7 @@ int fail_hip(hipError_t e, const char* what) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr size_t kDotScratch = 512;  // blocks of the FP64 dot-product partials
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Sequential carve of a device workspace (first pass with base == nullptr sizes it).
@@ -1332,6 +1333,153 @@ int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const d
     if (r.flags) status = LD_WBOUNDS;
   }
   return status;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with diagonal a and
+// squared off-diagonals b2 (b2[0] unused), by the Sturm sequence of its LDL^T pivots.
+static int sturm_below(const std::vector<double>& a, const std::vector<double>& b2, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  for (size_t i = 0; i < a.size(); ++i) {
+    if (i > 0) q = a[i] - x - b2[i] / (q != 0.0 ? q : 1e-300);
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// The idx-th smallest eigenvalue (0-based) of that tridiagonal, by bisection.
+static double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b2, int idx) {
+  double lo = INFINITY, hi = -INFINITY;
+  const size_t k = a.size();
+  for (size_t i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::sqrt(b2[i]) : 0.0) + (i + 1 < k ? std::sqrt(b2[i + 1]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b2, mid) > idx)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+int ld_spectral_estimate(const ld_csr* B, const ld_csr* Ct_in, int gram, int iters, uint64_t seed, void* stream,
+                         double* lo, double* hi) {
+  int rc = check_csr(B, "B");
+  if (rc) return rc;
+  if (!lo || !hi) return fail(LD_EINVAL, "lo or hi is NULL");
+  if (iters < 2 || iters > 2000) return fail(LD_EINVAL, "iters=%d out of range [2, 2000]", iters);
+  if (B->rows < 1) return fail(LD_EINVAL, "empty matrix");
+  if (gram && B->diag_shift != 0.0) return fail(LD_EINVAL, "diag_shift must be 0 with gram = 1");
+  if (Ct_in) {
+    rc = check_csr(Ct_in, "Ct");
+    if (rc) return rc;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t d = B->rows;
+  const int valt = valt_of(B->dtype);
+  Carve c;
+  for (int i = 0; i < 4; ++i) c.take((size_t)d * 8);
+  c.take(kDotScratch * 8);
+  c.take(8);
+  const bool build_t = gram && !Ct_in;
+  if (build_t) {
+    c.take((size_t)(d + 1) * 8);
+    c.take((size_t)B->nnz * 4);
+    c.take((size_t)B->nnz * val_bytes(valt));
+    c.take((size_t)d * 8);
+    c.take(transpose_scratch_bytes(d));
+  }
+  Workspace ws;
+  rc = get_workspace(nullptr, align_up(c.off), s, ws);
+  if (rc) return rc;
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  double* buf[3];
+  for (auto& p : buf) p = static_cast<double*>(cv.take((size_t)d * 8));
+  double* tmp = static_cast<double*>(cv.take((size_t)d * 8));
+  double* part = static_cast<double*>(cv.take(kDotScratch * 8));
+  double* scal = static_cast<double*>(cv.take(8));
+  ld_csr Ct{};
+  if (gram) {
+    if (Ct_in) {
+      Ct = *Ct_in;
+    } else {
+      int64_t* rpt = static_cast<int64_t*>(cv.take((size_t)(d + 1) * 8));
+      int32_t* colt = static_cast<int32_t*>(cv.take((size_t)B->nnz * 4));
+      void* valt_ = cv.take((size_t)B->nnz * val_bytes(valt));
+      int64_t* cursor = static_cast<int64_t*>(cv.take((size_t)d * 8));
+      void* scan = cv.take(transpose_scratch_bytes(d));
+      LD_HIP(launch_transpose(B->row_ptr, B->col_idx, B->values, valt, d, B->nnz, rpt, colt, valt_, cursor, scan,
+                              transpose_scratch_bytes(d), s));
+      Ct = *B;
+      Ct.row_ptr = rpt;
+      Ct.col_idx = colt;
+      Ct.values = valt_;
+    }
+  }
+  // one-probe products in FP64 vectors through the recurrence-step kernel
+  StepLaunch L{};
+  L.nmat = 1;
+  L.M = 1;
+  L.shape = with_tile(base_shape(1, 1), d, B->nnz, 0);
+  L.tile_rows = L.shape.tile_rows;
+  L.ntiles = (d + L.tile_rows - 1) / L.tile_rows;
+  auto product = [&](const ld_csr* X, const double* x, double* y, bool with_shift) -> hipError_t {
+    StepDesc D{};
+    D.row_ptr = X->row_ptr;
+    D.col = X->col_idx;
+    D.val = X->values;
+    D.d = d;
+    D.active = 1;
+    D.G = x;
+    D.out = y;
+    D.ag = 1.0;
+    D.bd = with_shift ? X->diag_shift : 0.0;
+    L.d0 = D;
+    return launch_step(L, 1, valt, SRC_BUF, with_shift ? SRC_SAME : SRC_NONE, SRC_NONE, MU_NONE, s);
+  };
+  auto dot = [&](const double* x, const double* y, double* out) -> int {
+    LD_HIP(launch_dot(x, y, d, part, scal, s));
+    LD_HIP(hipMemcpyAsync(out, scal, 8, hipMemcpyDeviceToHost, s));
+    LD_HIP(hipStreamSynchronize(s));
+    return LD_OK;
+  };
+  double* vprev = buf[0];
+  double* v = buf[1];
+  double* w = buf[2];
+  LD_HIP(launch_fill_zero(vprev, (size_t)d * 8, s));
+  LD_HIP(launch_seed(v, 1, nullptr, nullptr, nullptr, 1.0 / std::sqrt((double)d), 0.0, 0.0, 0.0, seed, d, 1, s));
+  std::vector<double> al, b2{0.0};
+  double beta = 0.0;
+  for (int j = 0; j < iters; ++j) {
+    if (gram) {
+      LD_HIP(product(B, v, tmp, false));
+      LD_HIP(product(&Ct, tmp, w, false));
+    } else {
+      LD_HIP(product(B, v, w, true));
+    }
+    double alpha = 0.0;
+    rc = dot(w, v, &alpha);
+    if (rc) return rc;
+    LD_HIP(launch_lanczos_update(w, v, vprev, alpha, beta, d, s));
+    al.push_back(alpha);
+    double bb = 0.0;
+    rc = dot(w, w, &bb);
+    if (rc) return rc;
+    if (!(bb > 0.0) || !std::isfinite(bb)) break;  // invariant subspace found (or breakdown)
+    beta = std::sqrt(bb);
+    if (j + 1 < iters) b2.push_back(bb);
+    LD_HIP(launch_scale_vec(w, 1.0 / beta, d, vprev, s));  // v_{j+1} into the old v_{j-1} slot
+    std::swap(vprev, v);                                  // v_{j-1} <- v_j, v_j <- v_{j+1}
+  }
+  b2.resize(al.size());
+  *lo = tridiag_eig(al, b2, 0);
+  *hi = tridiag_eig(al, b2, (int)al.size() - 1);
+  return LD_OK;
 }
 
 int ld_clear_cache(void) {

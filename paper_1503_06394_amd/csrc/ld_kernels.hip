@@ -751,6 +751,33 @@ __global__ void __launch_bounds__(256) gershgorin_kernel(const int64_t* row_ptr,
   }
 }
 
+// --- Lanczos helpers (FP64 vectors) ---
+
+__global__ void __launch_bounds__(256) dot_partials_kernel(const double* x, const double* y, int64_t n, double* part) {
+  double s = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) s += x[t] * y[t];
+  __shared__ double sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// w <- w - alpha v - beta u
+__global__ void __launch_bounds__(256) lanczos_update_kernel(double* w, const double* v, const double* u, double alpha,
+                                                             double beta, int64_t n) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256)
+    w[t] = w[t] - alpha * v[t] - beta * u[t];
+}
+
+// y <- c x
+__global__ void __launch_bounds__(256) scale_vec_kernel(const double* x, double c, int64_t n, double* y) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) y[t] = c * x[t];
+}
+
 __global__ void __launch_bounds__(256) probes_kernel(uint64_t seed, int M, int64_t rows, int8_t* out) {
   const int64_t total = rows * (int64_t)M;
   for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
@@ -958,6 +985,8 @@ static hipError_t step_by_src(const StepLaunch& L, int g, int d, int p, int mu, 
   LD_CASE(SRC_HASH, SRC_SAME, SRC_NONE, MU_NONE)
   LD_CASE(SRC_BUF, SRC_SAME, SRC_HASH, MU_NONE)
   LD_CASE(SRC_BUF, SRC_SAME, SRC_BUF, MU_NONE)
+  // plain product (B + shift I) x, for the Lanczos estimate of the spectrum
+  LD_CASE(SRC_BUF, SRC_SAME, SRC_NONE, MU_NONE)
   // Algorithm 2: T = C X, then W_{k+1} = alpha C^T T + beta W_k - W_{k-1}
   LD_CASE(SRC_HASH, SRC_NONE, SRC_NONE, MU_NONE)
   LD_CASE(SRC_BUF, SRC_NONE, SRC_NONE, MU_NONE)
@@ -1111,6 +1140,25 @@ hipError_t launch_gershgorin(const int64_t* row_ptr, const int32_t* col, const v
   else
     hipLaunchKernelGGL(gershgorin_kernel<VAL_BF16>, grid, dim3(256), 0, s, row_ptr, col, val, shift, d, lo_part,
                        hi_part);
+  return hipGetLastError();
+}
+
+constexpr int kDotBlocks = 512;
+
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partials_kernel, dim3(kDotBlocks), dim3(256), 0, s, x, y, n, part);
+  hipLaunchKernelGGL(sum_doubles_kernel, dim3(1), dim3(1024), 0, s, part, (int64_t)kDotBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_update(double* w, const double* v, const double* u, double alpha, double beta, int64_t n,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_update_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, w, v, u, alpha, beta, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_vec(const double* x, double c, int64_t n, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(scale_vec_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, c, n, y);
   return hipGetLastError();
 }
 

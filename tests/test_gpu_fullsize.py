@@ -96,3 +96,20 @@ def test_batch_256_sampled(ld, oracle_lib):
         say(f"full batch: oracle for member {i} (d={mats[i].d}, n={ns[i]})")
         o = oracle_lib.logdet(mats[i], ab[i][0], ab[i][1], ns[i], 32, seed=4 + i)
         assert rel(res[i]["logdet"], o["gamma"], FLOOR * mats[i].d) <= TOL32, i
+
+
+@pytest.mark.timeout(600)
+def test_nonsingular_1m_alg2_probe(ld, oracle_lib):
+    """Algorithm 2 on the general d = 1e6 matrix (8 N(0,1) entries per row plus 3 I, FP32), M = 32,
+    n = 100, bounds from the Lanczos estimate padded as the benchmark pads them; sampled probes."""
+    C = synth.random_nonsingular(1_000_000, 8, 6, 3.0, "f32")
+    D = dev(C)
+    say("full size nonsingular: Lanczos estimate")
+    lo, hi = ld.ld_spectral_estimate(D, iters=300, gram=True, seed=6)
+    smin, smax = (0.5 * lo) ** 0.5, 1.05 * hi ** 0.5
+    say(f"full size nonsingular: GPU Algorithm 2 (smin={smin:.4g}, smax={smax:.4g})")
+    r = ld.ld_logabsdet_cheb(D, None, smin, smax, 100, 32, 6, want_probes=True)
+    for j in (0, 31):
+        say(f"full size nonsingular: oracle probe {j}")
+        o = oracle_lib.logabsdet(C, smin, smax, 100, 1, seed=6, ids=np.array([j]))
+        assert rel(r["s"][j], o["s"][0], FLOOR * C.d) <= TOL32, (j, r["s"][j], o["s"][0])

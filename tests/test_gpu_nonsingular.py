@@ -79,3 +79,29 @@ def test_alg2_rejects_bad_arguments(ld):
     D.diag_shift = 1.0
     with pytest.raises(ld.LogdetChebError):
         ld.ld_logabsdet_cheb(D, None, 0.5, 10.0, 10, 4, 0)
+
+
+def test_spectral_estimate_grid_closed_form(ld):
+    """Lanczos Ritz values of the 32x32 grid + 0.1 I lie inside the closed-form spectrum and
+    converge to its ends."""
+    from tests import _ref
+
+    B = synth.grid_laplacian_2d(32, "f32")
+    lam = _ref.grid2d_eigs(32) + 0.1
+    say("spectral estimate grid")
+    lo, hi = ld.ld_spectral_estimate(dev(B, shift=0.1), iters=300)
+    assert lam.min() * (1 - 1e-9) <= lo <= lam.min() * 1.02
+    assert lam.max() * (1 - 2e-3) <= hi <= lam.max() * (1 + 1e-9)
+
+
+def test_spectral_estimate_gram_vs_svd(ld):
+    """Extreme Ritz values of C^T C against the singular values from a dense SVD."""
+    C = synth.random_nonsingular(1500, 8, 6, 3.0, "f32")
+    sv = np.linalg.svd(synth.dense(C), compute_uv=False)
+    say("spectral estimate gram")
+    lo, hi = ld.ld_spectral_estimate(dev(C), iters=400, gram=True, seed=3)
+    assert sv.min() ** 2 * (1 - 1e-6) <= lo <= 4 * sv.min() ** 2
+    assert sv.max() ** 2 * (1 - 1e-3) <= hi <= sv.max() ** 2 * (1 + 1e-9)
+    # with the transpose given
+    lo2, hi2 = ld.ld_spectral_estimate(dev(C), iters=400, gram=True, seed=3, Ct=ld.ld_transpose(dev(C)))
+    assert abs(lo2 - lo) <= 1e-9 * abs(lo) and abs(hi2 - hi) <= 1e-9 * abs(hi)
