@@ -283,6 +283,8 @@ def main() -> None:
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": f"{tag} kernel",
             "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_}
+    if traffic is not None:
+        roof["traffic_GBps"] = round(traffic / (avg_ms / 1e3) / 1e9, 1)  # counted bytes at the live launch time
     extra = {
         "step_kernel": {"avg_ms": round(step_ms / max(step_n, 1), 5), "launches_per_step": step_n // args.steps,
                         "algorithmic_GBps": round(sb / (step_ms / max(step_n, 1) / 1e3) / 1e9, 1)},
