@@ -83,7 +83,8 @@ typedef struct {
 typedef struct {
     void *workspace;          /* device scratch or NULL (then the library allocates on `stream`) */
     size_t workspace_bytes;
-    int32_t vec_f64;          /* recurrence vectors in FP64 (1) or FP32 (0) */
+    int32_t vec_f64;          /* recurrence vectors: 0 = FP64 for FP64 values, else FP32;
+                                 1 = FP64; 2 = FP32 */
     int32_t ckpt_stride;      /* gradient: checkpoint every s steps; 0 = automatic: keep every
                                  W_k when that fits (the workspace given, or 40% of free device
                                  memory), else every ceil(sqrt(steps)) */
@@ -112,6 +113,18 @@ int ld_logdet_cheb(const ld_csr *B, double a, double b, int n, int M, uint64_t s
  * C's diag_shift must be 0. */
 int ld_logabsdet_cheb(const ld_csr *C, const ld_csr *Ct, double smin, double smax, int n, int M,
                       uint64_t seed, const ld_opts *opt, void *stream, ld_result *out);
+
+/* Taylor-series comparator, for the accuracy comparison of Section 5.1 (not the paper's method).
+ * With the normalisation of Section 3.1, A = I - (B + diag_shift I)/(a + b) has spectrum in
+ * [delta, 1 - delta], delta = a/(a + b), and
+ *     log det(B + diag_shift I) = d log(a + b) - sum_{k>=1} tr(A^k) / k.
+ * The series is truncated after degree n and every trace is estimated with the same M probes as
+ * ld_logdet_cheb: Gamma = d log(a + b) - (1/M) sum_j sum_{k=1..n} v_j^T A^k v_j / k, one sparse
+ * product per degree.  out->poly_bound is the truncation bound d q^(n+1) / ((n+1)(1-q)),
+ * q = b/(a + b); moments_out receives v_j^T A^k v_j (k = 0..n).  Arguments and errors as for
+ * ld_logdet_cheb (plain_recurrence does not apply). */
+int ld_logdet_taylor(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
+                     const ld_opts *opt, void *stream, ld_result *out);
 
 /* Gradient of the ld_logdet_cheb estimate (same B, a, b, n, M, seed, with a and b held
  * fixed) with respect to every stored entry of B, scaled by grad_output.  B is symmetric, so
@@ -151,6 +164,35 @@ int ld_gershgorin(const ld_csr *B, double *a, double *b, void *stream);
 int ld_spectral_estimate(const ld_csr *B, const ld_csr *Ct, int gram, int iters, uint64_t seed,
                          void *stream, double *lo, double *hi);
 
+/* Spanning-tree counting (Section 3.3).  By Kirchhoff's matrix-tree theorem the number of
+ * spanning trees of a graph G is tau(G) = det L(hub), where L(hub) is the Laplacian D - A of G
+ * with the row and column of one vertex removed.  When that vertex is adjacent to every other
+ * vertex, every row of L(hub) has diagonal deg(i) and deg(i) - 1 off-diagonal entries -1, so its
+ * spectrum lies in [1, 2 Delta_max - 1], Delta_max being the largest degree among the other
+ * vertices (the hub's edge included).
+ *
+ * ld_laplacian_minor builds L(hub) from the adjacency pattern `adj` of a simple undirected graph
+ * (device CSR with both orientations of every edge, sorted columns, no self loops; values
+ * ignored).  Output, all device arrays owned by the caller: row_ptr_out (rows entries, i.e. the
+ * rows - 1 rows of the minor plus one), col_out and val_out (adj->nnz - (rows - 1) entries,
+ * columns sorted, values of type val_dtype: LD_F64 or LD_F32, exact integers).  Row r of the
+ * minor is vertex r + (r >= hub); columns above the hub shift down by one.  *max_degree receives
+ * Delta_max.  LD_EINVAL if the hub's degree is not rows - 1, or if some vertex misses the hub,
+ * has a self loop or repeats a neighbour (outputs then undefined, but no write leaves them). */
+int ld_laplacian_minor(const ld_csr *adj, int64_t hub, int64_t *row_ptr_out, int32_t *col_out,
+                       void *val_out, int32_t val_dtype, int64_t *max_degree, void *stream);
+
+/* log tau(G) for a graph whose vertex `hub` is adjacent to every other vertex (Section 3.3):
+ * method 1 runs Algorithm 2 with C = L(hub) and singular values in [1, 2 Delta_max - 1], as the
+ * spanning-tree corollary states; method 0 runs Algorithm 1 on the symmetric positive definite
+ * L(hub) with spectrum in [1, 2 Delta_max - 1].  The minor is built on the device in a
+ * stream-ordered allocation of its own (opt->workspace only serves the estimator); values and
+ * vectors are FP64 when opt->vec_f64 = 1, else FP32.  out->logdet is the estimate of log tau(G).
+ * When Delta_max = 1 the minor is the identity and 0 is returned exactly (probe_out zeroed,
+ * moments_out untouched).  Errors as for ld_laplacian_minor and ld_logdet_cheb. */
+int ld_log_spanning_trees(const ld_csr *adj, int64_t hub, int n, int M, uint64_t seed, int method,
+                          const ld_opts *opt, void *stream, ld_result *out);
+
 /* Write the probe block: out[r * M + j] = v_j[r] (int8, +1/-1), r < rows, j < M. */
 int ld_probes(uint64_t seed, int M, int64_t rows, int8_t *out, void *stream);
 
@@ -158,7 +200,8 @@ int ld_probes(uint64_t seed, int M, int64_t rows, int8_t *out, void *stream);
  * nnz, same dtype); rows of the result have ascending column indices. */
 int ld_transpose(const ld_csr *C, int64_t *row_ptr_t, int32_t *col_t, void *val_t, void *stream);
 
-/* Device bytes the entry point `mode` (0 logdet, 1 logabsdet, 2 grad) needs as workspace. */
+/* Device bytes the entry point `mode` (0 logdet, 1 logabsdet, 2 grad, 3 taylor) needs as
+ * workspace; vec_f64: 1 = FP64 recurrence vectors, 0 = FP32. */
 size_t ld_workspace_bytes(const ld_csr *B, int n, int M, int mode, int vec_f64);
 
 /* Device-to-device streaming copy with the library's own kernel (HBM bandwidth probe);

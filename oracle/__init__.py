@@ -59,10 +59,11 @@ def lib():
         L.ldo_logabsdet.argtypes = [P, D, D, I, I, P, P, P]
         L.ldo_logdet_grad.argtypes = [P, D, D, D, I, I, P, P, P, P]
         L.ldo_gershgorin.argtypes = [P, D, P, P]
+        L.ldo_logdet_taylor.argtypes = [P, D, D, D, I, I, P, P, P]
         L.ldo_lemma_bound.argtypes = [D, I, I64]
         L.ldo_lemma_bound.restype = D
         for f in ("ldo_cheb_coeffs_alg1", "ldo_probe_sign", "ldo_logdet", "ldo_logabsdet",
-                  "ldo_logdet_grad", "ldo_gershgorin"):
+                  "ldo_logdet_grad", "ldo_gershgorin", "ldo_logdet_taylor"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -165,6 +166,21 @@ def logabsdet(C, smin: float, smax: float, n: int, m: int, seed: int = 0, V=None
     return {"gamma": g.value, "s": s, "std_err": float(np.std(s, ddof=1) / math.sqrt(m)) if m > 1 else float("nan")}
 
 
+def logdet_taylor(B, a: float, b: float, n: int, m: int, seed: int = 0, V=None, ids=None,
+                  shift: float = 0.0) -> dict:
+    """Taylor-series comparator of Section 5.1's accuracy comparison: d log(a + b) minus the
+    degree-n truncation of sum_k tr(A^k)/k, A = I - (B + shift I)/(a + b), traces by the probes."""
+    k = _Keep(B)
+    pr, keep = _probes(seed, V, ids, B.d, m)
+    g = ctypes.c_double(0.0)
+    s = np.empty(m)
+    rc = lib().ldo_logdet_taylor(ctypes.byref(k.s), float(shift), float(a), float(b), int(n), int(m),
+                                 ctypes.byref(pr), ctypes.byref(g), _ptr(s))
+    if rc:
+        raise ValueError(f"ldo_logdet_taylor failed ({rc})")
+    return {"gamma": g.value, "s": s, "std_err": float(np.std(s, ddof=1) / math.sqrt(m)) if m > 1 else float("nan")}
+
+
 def logdet_grad(B, a: float, b: float, n: int, m: int, seed: int = 0, V=None, ids=None, shift: float = 0.0) -> dict:
     """Gradient of the ``logdet`` estimate w.r.t. the stored entries of B and the diagonal shift."""
     k = _Keep(B)
@@ -217,3 +233,69 @@ def logdet_batch(mats, a, b, ns, m: int, seed0: int, shift=None) -> list:
     for i, B in enumerate(mats):
         out.append(logdet(B, a[i], b[i], ns[i], m, seed=seed0 + i, shift=0.0 if shift is None else shift[i]))
     return out
+
+
+class SimpleCsr:
+    """Plain CSR container (row_ptr int64, col int32, val float64) for matrices the oracle builds."""
+
+    def __init__(self, d, row_ptr, col, val):
+        self.d = int(d)
+        self.row_ptr = np.asarray(row_ptr, dtype=np.int64)
+        self.col = np.asarray(col, dtype=np.int32)
+        self.val = np.asarray(val, dtype=np.float64)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+
+def laplacian_minor(adj, hub: int) -> tuple:
+    """Kirchhoff's matrix-tree theorem (Section 3.3): the Laplacian L = D - A of the graph with
+    adjacency pattern ``adj`` (both orientations of every edge stored), with the row and column
+    of vertex ``hub`` deleted.  Returns (minor as SimpleCsr with sorted columns, Delta_max), where
+    Delta_max is the largest degree among the vertices other than the hub."""
+    d = int(adj.d)
+    row_ptr = np.asarray(adj.row_ptr, dtype=np.int64)
+    deg = np.diff(row_ptr)
+    entries = {}
+    for r in range(d):
+        if r == hub:
+            continue
+        rr = r - (1 if r > hub else 0)
+        row = {rr: float(deg[r])}
+        for t in range(row_ptr[r], row_ptr[r + 1]):
+            c = int(adj.col[t])
+            if c == hub or c == r:
+                continue
+            cc = c - (1 if c > hub else 0)
+            row[cc] = row.get(cc, 0.0) - 1.0
+        entries[rr] = sorted(row.items())
+    m = d - 1
+    rp = np.zeros(m + 1, dtype=np.int64)
+    cols, vals = [], []
+    for rr in range(m):
+        rp[rr + 1] = rp[rr] + len(entries[rr])
+        for c, v in entries[rr]:
+            cols.append(c)
+            vals.append(v)
+    others = np.delete(deg, hub)
+    return SimpleCsr(m, rp, cols, vals), int(others.max()) if others.size else 0
+
+
+def log_spanning_trees(adj, hub: int, n: int, m: int, seed: int = 0, method: int = 1, V=None, ids=None) -> dict:
+    """Estimate of log tau(G) for a graph whose vertex ``hub`` is adjacent to every other vertex
+    (Section 3.3): the spectrum of L(hub) lies in [1, 2 Delta_max - 1], so method 1 runs
+    Algorithm 2 with C = L(hub) and singular values in that interval (the corollary's inputs),
+    and method 0 runs Algorithm 1 on L(hub) with that interval.  Delta_max = 1 means L(hub) = I,
+    and log tau = 0 exactly."""
+    L, dmax = laplacian_minor(adj, hub)
+    if dmax <= 1:
+        return {"gamma": 0.0, "s": np.zeros(m), "minor": L, "delta_max": dmax}
+    hi = 2.0 * dmax - 1.0
+    if method == 1:
+        r = logabsdet(L, 1.0, hi, n, m, seed=seed, V=V, ids=ids)
+    else:
+        r = logdet(L, 1.0, hi, n, m, seed=seed, V=V, ids=ids)
+    r["minor"] = L
+    r["delta_max"] = dmax
+    return r

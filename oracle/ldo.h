@@ -83,6 +83,13 @@ int ldo_alg1(int64_t d, ldo_matvec_fn matvec, const void *ctx, double delta, int
 int ldo_logdet(const ldo_csr *B, double shift, double a, double b, int n, int m,
                const ldo_probes *probes, double *gamma, double *s, double *mom);
 
+/* Taylor-series comparator for the accuracy comparison of Section 5.1 (not the paper's method):
+ * with A = I - (B + shift I)/(a + b), log det(B + shift I) = d log(a + b) - sum_{k>=1} tr(A^k)/k,
+ * truncated after degree n, each trace estimated with the probes.  s (nullable, m): per-probe
+ * values. */
+int ldo_logdet_taylor(const ldo_csr *B, double shift, double a, double b, int n, int m,
+                      const ldo_probes *probes, double *gamma, double *s);
+
 /* Algorithm 2 (Section 3.2): log|det C| for a non-singular C with singular values in
  * [smin, smax].  s (nullable, m): per-probe values of the final output formula. */
 int ldo_logabsdet(const ldo_csr *C, double smin, double smax, int n, int m,

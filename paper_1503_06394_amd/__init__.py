@@ -20,7 +20,9 @@ import torch
 __all__ = [
     "LogdetChebError", "DeviceCSR", "lib", "ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad",
     "ld_logdet_cheb_batched", "ld_gershgorin", "ld_probes", "ld_transpose", "ld_workspace_bytes", "ld_copy",
-    "ld_version", "ld_clear_cache", "ld_spectral_estimate", "LogdetCheb", "logdet_cheb", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
+    "ld_version", "ld_clear_cache", "ld_spectral_estimate", "ld_laplacian_minor", "ld_log_spanning_trees",
+    "ld_logdet_taylor",
+    "LogdetCheb", "logdet_cheb", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblogdet_cheb.so")
@@ -84,11 +86,15 @@ def lib():
         L.ld_copy.argtypes = [P, P, SZ, P, P]
         L.ld_spectral_estimate.argtypes = [P, P, I, I, U64, P, P, P]
         L.ld_spectral_estimate.restype = I
+        L.ld_laplacian_minor.argtypes = [P, I64, P, P, P, ctypes.c_int32, P, P]
+        L.ld_logdet_taylor.argtypes = [P, D, D, I, I, U64, P, P, P]
+        L.ld_log_spanning_trees.argtypes = [P, I64, I, I, U64, I, P, P, P]
         L.ld_clear_cache.argtypes = []
         L.ld_last_error.restype = ctypes.c_char_p
         L.ld_version.restype = ctypes.c_char_p
         for f in ("ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad", "ld_logdet_cheb_batched",
-                  "ld_gershgorin", "ld_probes", "ld_transpose", "ld_copy", "ld_clear_cache"):
+                  "ld_gershgorin", "ld_probes", "ld_transpose", "ld_copy", "ld_clear_cache", "ld_laplacian_minor",
+                  "ld_log_spanning_trees", "ld_logdet_taylor"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -207,6 +213,68 @@ def ld_logabsdet_cheb(C: DeviceCSR, Ct: DeviceCSR | None, smin: float, smax: flo
     rc = _check(lib().ld_logabsdet_cheb(ctypes.byref(cc), ctypes.byref(ct) if ct is not None else None, float(smin),
                                         float(smax), int(n), int(M), int(seed) & (2**64 - 1), ctypes.byref(o),
                                         _stream_ptr(stream), ctypes.byref(r)), "ld_logabsdet_cheb")
+    out = _result(r, rc)
+    if pv is not None:
+        out["s"] = pv
+    return out
+
+
+def ld_logdet_taylor(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, *, vec_f64=None, tile=0,
+                     timing=False, workspace=None, want_moments=False, want_probes=False, stream=None) -> dict:
+    """Taylor-series comparator (Section 5.1): d log(a+b) - sum_{k<=n} tr(A^k)/k by the probes,
+    A = I - (B + diag_shift I)/(a + b)."""
+    import numpy as np
+
+    mom = np.zeros((M, n + 1)) if want_moments else None
+    pv = np.zeros(M) if want_probes else None
+    o = _opts(vec_f64, tile, timing, workspace, moments=mom, probes=pv)
+    r = _Result()
+    cb = B.c()
+    rc = _check(lib().ld_logdet_taylor(ctypes.byref(cb), float(a), float(b), int(n), int(M), int(seed) & (2**64 - 1),
+                                       ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)), "ld_logdet_taylor")
+    out = _result(r, rc)
+    if mom is not None:
+        out["moments"] = mom
+    if pv is not None:
+        out["s"] = pv
+    return out
+
+
+def ld_laplacian_minor(adj: DeviceCSR, hub: int, dtype: torch.dtype = torch.float32, stream=None) -> tuple:
+    """Laplacian of a graph (adjacency pattern ``adj``) with the hub's row and column removed.
+    Returns (DeviceCSR of the minor, Delta_max)."""
+    if dtype not in (torch.float64, torch.float32):
+        raise LogdetChebError("minor values must be float64 or float32")
+    m = adj.d - 1
+    if m < 1:
+        raise LogdetChebError("a graph needs at least 2 vertices")
+    nnz = adj.nnz - m
+    if nnz < m:
+        raise LogdetChebError("adjacency has too few entries for a hub adjacent to every vertex")
+    dev = adj.row_ptr.device
+    rp = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz, dtype=dtype, device=dev)
+    dmax = ctypes.c_int64(0)
+    ca = adj.c()
+    _check(lib().ld_laplacian_minor(ctypes.byref(ca), int(hub), rp.data_ptr(), col.data_ptr(), val.data_ptr(),
+                                    _DTYPE[dtype], ctypes.byref(dmax), _stream_ptr(stream)), "ld_laplacian_minor")
+    return DeviceCSR(rp, col, val), int(dmax.value)
+
+
+def ld_log_spanning_trees(adj: DeviceCSR, hub: int, n: int, M: int, seed: int, *, method: int = 1, vec_f64=None,
+                          tile=0, timing=False, workspace=None, want_probes=False, plain=False, stream=None) -> dict:
+    """Estimate of log tau(G) for a graph whose vertex ``hub`` is adjacent to every other vertex:
+    method 1 = Algorithm 2 on L(hub) (the spanning-tree corollary), method 0 = Algorithm 1."""
+    import numpy as np
+
+    pv = np.zeros(M) if want_probes else None
+    o = _opts(vec_f64, tile, timing, workspace, probes=pv, plain=plain)
+    r = _Result()
+    ca = adj.c()
+    rc = _check(lib().ld_log_spanning_trees(ctypes.byref(ca), int(hub), int(n), int(M), int(seed) & (2**64 - 1),
+                                            int(method), ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)),
+                "ld_log_spanning_trees")
     out = _result(r, rc)
     if pv is not None:
         out["s"] = pv

@@ -634,6 +634,95 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
   return out->flags ? LD_WBOUNDS : LD_OK;
 }
 
+// ------------------------------------------------------------------------------------
+// Taylor-series comparator: W_k = A W_{k-1}, A = I - (B + shift I)/(a + b), moments v^T A^k v
+// ------------------------------------------------------------------------------------
+
+size_t taylor_workspace(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
+  const size_t vb = vec_f64 ? 8 : 4;
+  const int64_t tiles = max_tiles(B, vec_f64, M, opt);
+  const int rows = std::max(n, 1);
+  Carve c;
+  c.take((size_t)B->rows * M * vb);
+  c.take((size_t)B->rows * M * vb);
+  c.take((size_t)rows * tiles * M * 8);
+  c.take((size_t)M * rows * 8);
+  c.take(reduce_scratch_bytes(rows, M));
+  return align_up(c.off);
+}
+
+int run_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt, hipStream_t s,
+               ld_result* out) {
+  const int valt = valt_of(B->dtype);
+  const int vec_f64 = vec_f64_of(opt, valt);
+  const int64_t d = B->rows;
+  Workspace ws;
+  int rc = get_workspace(opt, taylor_workspace(B, n, M, vec_f64, opt), s, ws);
+  if (rc) return rc;
+  FwdPlan p = plan_fwd(B, vec_f64, M, opt);
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  const size_t vecb = (size_t)d * M * p.vb;
+  void* buf[2] = {cv.take(vecb), cv.take(vecb)};
+  const int rows = std::max(n, 1);
+  double* part_base = static_cast<double*>(cv.take((size_t)rows * max_tiles(B, vec_f64, M, opt) * M * 8));
+  double* red_out = static_cast<double*>(cv.take((size_t)M * rows * 8));
+  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(rows, M)));
+  const int64_t kstride = p.ntiles * M;
+  const double scale = a + b;  // B/(a + b) has spectrum in [delta, 1 - delta] (Section 3.1)
+
+  StepTimer tm;
+  tm.on = opt && opt->timing;
+  tm.s = s;
+  StepLaunch L{};
+  L.nmat = 1;
+  L.ntiles = p.ntiles;
+  L.tile_rows = p.sh.tile_rows;
+  L.M = M;
+  L.shape = p.sh;
+  LD_HIP(tm.mark(T_OTHER));
+  for (int k = 0; k < n && d > 0; ++k) {  // W_{k+1} = A W_k with W_0 = V from the probe hash
+    StepDesc D{};
+    D.row_ptr = B->row_ptr;
+    D.col = B->col_idx;
+    D.val = B->values;
+    D.seed = seed;
+    D.d = d;
+    D.active = 1;
+    D.G = k == 0 ? nullptr : buf[(k - 1) & 1];
+    D.out = buf[k & 1];
+    D.ag = -1.0 / scale;
+    D.bd = 1.0 - B->diag_shift / scale;
+    D.cp = 0.0;  // the probe-hash third operand costs no memory traffic and is scaled away
+    D.mu_part = part_base + (int64_t)k * kstride;
+    L.d0 = D;
+    LD_HIP(launch_step(L, vec_f64, valt, k == 0 ? SRC_HASH : SRC_BUF, SRC_SAME, k == 0 ? SRC_NONE : SRC_HASH,
+                       MU_PROBE, s));
+    LD_HIP(tm.mark(T_STEP));
+  }
+  std::vector<double> red((size_t)M * rows, 0.0);
+  if (n >= 1 && d > 0) {
+    LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 0, n - 1, kstride, red_out, n, red_tmp, s));
+    LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * n * 8, hipMemcpyDeviceToHost, s));
+  }
+  LD_HIP(hipStreamSynchronize(s));
+  // log det B = d log(a + b) - sum_k tr(A^k)/k: coefficients log(a + b) on mu_0 = v^T v = d and -1/k
+  std::vector<double> mu((size_t)M * (n + 1), 0.0), c(n + 1);
+  c[0] = std::log(scale);
+  for (int k = 1; k <= n; ++k) c[k] = -1.0 / k;
+  for (int j = 0; j < M; ++j) {
+    mu[(size_t)j * (n + 1)] = (double)d;
+    for (int k = 1; k <= n; ++k) mu[(size_t)j * (n + 1) + k] = red[(size_t)j * rows + (k - 1)];
+  }
+  combine(mu, c, n, M, d, 1.0, out, opt);
+  // truncation: |sum_{k>n} tr(A^k)/k| <= d q^{n+1} / ((n+1)(1-q)), q = 1 - delta = b/(a+b)
+  const double q = b / scale;
+  out->poly_bound = (double)d * std::pow(q, n + 1) / ((n + 1) * (1.0 - q));
+  out->grad_shift = 0.0;
+  tm.report(out);
+  return out->flags ? LD_WBOUNDS : LD_OK;
+}
+
 }  // namespace
 
 // ======================================================================================
@@ -908,6 +997,7 @@ size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) 
   o.vec_f64 = vec_f64 ? 1 : 2;
   const int v64 = vec_f64_of(&o, valt);
   if (mode == 2) return grad_workspace(B, n, M, v64, nullptr);
+  if (mode == 3) return taylor_workspace(B, n, M, v64, nullptr);
   return fwd_workspace(B, n, M, v64, mode == 1, nullptr);
 }
 
@@ -920,6 +1010,20 @@ int ld_logdet_cheb(const ld_csr* B, double a, double b, int n, int M, uint64_t s
   if (!out) return fail(LD_EINVAL, "out is NULL");
   ld_result r{};
   rc = run_forward(B, nullptr, false, a, b, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
+  if (rc < 0) return rc;
+  *out = r;
+  return rc;
+}
+
+int ld_logdet_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
+                     void* stream, ld_result* out) {
+  int rc = check_csr(B, "B");
+  if (rc) return rc;
+  rc = check_common(a, b, n, M);
+  if (rc) return rc;
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  ld_result r{};
+  rc = run_taylor(B, a, b, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
   if (rc < 0) return rc;
   *out = r;
   return rc;
@@ -943,6 +1047,94 @@ int ld_logabsdet_cheb(const ld_csr* C, const ld_csr* Ct, double smin, double sma
   if (!out) return fail(LD_EINVAL, "out is NULL");
   ld_result r{};
   rc = run_forward(C, Ct, true, smin * smin, smax * smax, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
+  if (rc < 0) return rc;
+  *out = r;
+  return rc;
+}
+
+int ld_laplacian_minor(const ld_csr* adj, int64_t hub, int64_t* row_ptr_out, int32_t* col_out, void* val_out,
+                       int32_t val_dtype, int64_t* max_degree, void* stream) {
+  int rc = check_csr(adj, "adj");
+  if (rc) return rc;
+  if (adj->rows < 2) return fail(LD_EINVAL, "a graph needs at least 2 vertices; got %lld", (long long)adj->rows);
+  if (hub < 0 || hub >= adj->rows) return fail(LD_EINVAL, "hub %lld outside [0, %lld)", (long long)hub,
+                                               (long long)adj->rows);
+  if (val_dtype != LD_F64 && val_dtype != LD_F32) return fail(LD_EDTYPE, "minor values must be LD_F64 or LD_F32");
+  if (!row_ptr_out || !col_out || !val_out || !max_degree) return fail(LD_EINVAL, "an output pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t hb[2];
+  LD_HIP(hipMemcpyAsync(hb, adj->row_ptr + hub, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  const int64_t deg_hub = hb[1] - hb[0];
+  if (deg_hub != adj->rows - 1)
+    return fail(LD_EINVAL, "vertex %lld has degree %lld, not %lld: it is not adjacent to every other vertex",
+                (long long)hub, (long long)deg_hub, (long long)(adj->rows - 1));
+  const int64_t m = adj->rows - 1;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (m + 255) / 256));
+  Workspace ws;
+  rc = get_workspace(nullptr, (size_t)nb * 16, s, ws);
+  if (rc) return rc;
+  int64_t* mx_part = static_cast<int64_t*>(ws.ptr);
+  int64_t* bad_part = mx_part + nb;
+  LD_HIP(launch_laplacian_minor(adj->row_ptr, adj->col_idx, adj->rows, hub, deg_hub, row_ptr_out, col_out, val_out,
+                                val_dtype == LD_F64 ? VAL_F64 : VAL_F32, mx_part, bad_part, nb, s));
+  std::vector<int64_t> h(2 * (size_t)nb);
+  LD_HIP(hipMemcpyAsync(h.data(), mx_part, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  int64_t mx = 0, bad = 0;
+  for (int i = 0; i < nb; ++i) {
+    mx = std::max(mx, h[i]);
+    bad += h[nb + i];
+  }
+  if (bad)
+    return fail(LD_EINVAL, "%lld vertices miss the hub, carry a self loop or repeat a neighbour", (long long)bad);
+  *max_degree = mx;
+  return LD_OK;
+}
+
+int ld_log_spanning_trees(const ld_csr* adj, int64_t hub, int n, int M, uint64_t seed, int method, const ld_opts* opt,
+                          void* stream, ld_result* out) {
+  if (method != 0 && method != 1) return fail(LD_EINVAL, "method must be 0 (Algorithm 1) or 1 (Algorithm 2)");
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  int rc = check_csr(adj, "adj");
+  if (rc) return rc;
+  rc = check_common(1.0, 2.0, n, M);
+  if (rc) return rc;
+  if (adj->rows < 2) return fail(LD_EINVAL, "a graph needs at least 2 vertices; got %lld", (long long)adj->rows);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t m = adj->rows - 1;
+  const int64_t nnz_out = adj->nnz - m;  // valid once the hub's degree is checked to be m
+  if (nnz_out < m) return fail(LD_EINVAL, "adjacency has too few entries for a hub of degree %lld", (long long)m);
+  const bool f64 = opt && opt->vec_f64 == 1;
+  Carve c;
+  c.take((size_t)(m + 1) * 8);
+  c.take((size_t)nnz_out * 4);
+  c.take((size_t)nnz_out * (f64 ? 8 : 4));
+  Workspace ws;
+  rc = get_workspace(nullptr, align_up(c.off), s, ws);
+  if (rc) return rc;
+  c = Carve{static_cast<char*>(ws.ptr)};
+  int64_t* rp = static_cast<int64_t*>(c.take((size_t)(m + 1) * 8));
+  int32_t* col = static_cast<int32_t*>(c.take((size_t)nnz_out * 4));
+  void* val = c.take((size_t)nnz_out * (f64 ? 8 : 4));
+  int64_t dmax = 0;
+  rc = ld_laplacian_minor(adj, hub, rp, col, val, f64 ? LD_F64 : LD_F32, &dmax, stream);
+  if (rc) return rc;
+  ld_result r{};
+  r.n = n;
+  r.M = M;
+  if (dmax <= 1) {  // every other vertex hangs off the hub alone: L(hub) = I and the tree is unique
+    if (opt && opt->probe_out)
+      for (int j = 0; j < M; ++j) opt->probe_out[j] = 0.0;
+    *out = r;
+    return LD_OK;
+  }
+  ld_csr L{m, m, nnz_out, rp, col, val, f64 ? LD_F64 : LD_F32, 0, 0.0};
+  const double hi = 2.0 * (double)dmax - 1.0;  // spectrum of L(hub) lies in [1, 2 Delta_max - 1]
+  if (method == 0)
+    rc = run_forward(&L, nullptr, false, 1.0, hi, n, M, seed, opt, s, &r);
+  else
+    rc = run_forward(&L, &L, true, 1.0, hi * hi, n, M, seed, opt, s, &r);  // C = L(hub) is its own transpose
   if (rc < 0) return rc;
   *out = r;
   return rc;

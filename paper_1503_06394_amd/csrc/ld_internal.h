@@ -139,6 +139,13 @@ hipError_t launch_sum_doubles(const double* x, int64_t n, double* out, hipStream
 hipError_t launch_gershgorin(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, double shift,
                              int64_t d, double* lo_part, double* hi_part, int nblocks, hipStream_t s);
 
+// Laplacian minor L(hub) of a graph given by its adjacency pattern (see the kernel); valt is
+// VAL_F64 or VAL_F32.  max_part / bad_part: nblocks partial maxima of the degree and counts of rows
+// that miss the hub or carry a self loop.
+hipError_t launch_laplacian_minor(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t hub, int64_t deg_hub,
+                                  int64_t* rp_out, int32_t* col_out, void* val_out, int valt, int64_t* max_part,
+                                  int64_t* bad_part, int nblocks, hipStream_t s);
+
 hipError_t launch_probes(uint64_t seed, int M, int64_t rows, int8_t* out, hipStream_t s);
 
 hipError_t launch_transpose(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, int64_t d,

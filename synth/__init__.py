@@ -28,6 +28,10 @@ __all__ = [
     "random_nonsingular",
     "random_batch",
     "diagonal_matrix",
+    "graph_from_edges",
+    "wheel_graph",
+    "complete_graph",
+    "hub_graph",
     "permute",
     "dense",
 ]
@@ -245,3 +249,50 @@ def dense(B: CSR) -> np.ndarray:
     A = np.zeros((B.d, B.d))
     A[B.row_of_entry(), B.col.astype(np.int64)] = B.val
     return A
+
+
+# ----------------------------------------------------------------------------------------
+# graphs for spanning-tree counting (adjacency patterns, values 1)
+
+
+def graph_from_edges(nv: int, u: np.ndarray, v: np.ndarray, kind: str = "graph") -> CSR:
+    """Adjacency pattern of the simple undirected graph on ``nv`` vertices with edges (u[e], v[e]):
+    both orientations stored, repeated edges merged, self loops dropped, columns sorted, values 1."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    rows = np.concatenate([u[keep], v[keep]])
+    cols = np.concatenate([v[keep], u[keep]])
+    key = np.unique(rows * nv + cols)
+    r, c = key // nv, key % nv
+    row_ptr = np.zeros(nv + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=nv), out=row_ptr[1:])
+    return CSR(nv, row_ptr, c.astype(np.int32), np.ones(key.shape[0]), "f32", {"kind": kind})
+
+
+def wheel_graph(k: int) -> CSR:
+    """Wheel W_k: hub 0 joined to every vertex of the cycle 1..k (k >= 3)."""
+    if k < 3:
+        raise ValueError("a wheel needs a cycle of at least 3 vertices")
+    ring = np.arange(1, k + 1, dtype=np.int64)
+    u = np.concatenate([np.zeros(k, dtype=np.int64), ring])
+    v = np.concatenate([ring, np.roll(ring, -1)])
+    return graph_from_edges(k + 1, u, v, "wheel")
+
+
+def complete_graph(nv: int) -> CSR:
+    """Complete graph K_nv."""
+    iu, ju = np.triu_indices(nv, 1)
+    return graph_from_edges(nv, iu, ju, "complete")
+
+
+def hub_graph(nv: int, k_off: int = 5, mseed: int = 7) -> CSR:
+    """Vertex 0 joined to every other vertex, plus ``k_off`` distinct uniform random neighbours
+    drawn for each of the vertices 1..nv-1 among the others (edges mirrored and merged), so that
+    non-hub degrees are about 2 k_off + 1.  The class of graphs of the spanning-tree section."""
+    rng = np.random.default_rng(mseed)
+    m = nv - 1
+    draws = _distinct_offdiag_draws(rng, m, k_off) + 1  # among vertices 1..nv-1
+    u = np.concatenate([np.zeros(m, dtype=np.int64), np.repeat(np.arange(1, nv, dtype=np.int64), k_off)])
+    v = np.concatenate([np.arange(1, nv, dtype=np.int64), draws.reshape(-1)])
+    return graph_from_edges(nv, u, v, "hub")

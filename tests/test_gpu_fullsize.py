@@ -113,3 +113,17 @@ def test_nonsingular_1m_alg2_probe(ld, oracle_lib):
         say(f"full size nonsingular: oracle probe {j}")
         o = oracle_lib.logabsdet(C, smin, smax, 100, 1, seed=6, ids=np.array([j]))
         assert rel(r["s"][j], o["s"][0], FLOOR * C.d) <= TOL32, (j, r["s"][j], o["s"][0])
+
+
+@pytest.mark.timeout(600)
+def test_spanning_trees_1m_probe(ld, oracle_lib):
+    """Spanning-tree counting on a d = 1e6 hub graph (5 random neighbours drawn per vertex plus the
+    hub), Algorithm 2 on L(hub) with sigma in [1, 2 Delta_max - 1], FP32, M = 32, n = 100;
+    sampled probes against the oracle's own minor and Algorithm 2."""
+    G = synth.hub_graph(1_000_000, 5, 7)
+    say("full size spanning trees: GPU minor + Algorithm 2")
+    r = ld.ld_log_spanning_trees(dev(G), 0, 100, 32, 8, method=1, want_probes=True)
+    for j in (0, 17):
+        say(f"full size spanning trees: oracle probe {j}")
+        o = oracle_lib.log_spanning_trees(G, 0, 100, 1, seed=8, method=1, ids=np.array([j]))
+        assert rel(r["s"][j], o["s"][0], FLOOR * G.d) <= TOL32, (j, r["s"][j], o["s"][0])
