@@ -193,6 +193,11 @@ int ld_laplacian_minor(const ld_csr *adj, int64_t hub, int64_t *row_ptr_out, int
 int ld_log_spanning_trees(const ld_csr *adj, int64_t hub, int n, int M, uint64_t seed, int method,
                           const ld_opts *opt, void *stream, ld_result *out);
 
+/* Quadratic form x^T (B + diag_shift I) x in FP64 for a device FP64 vector x of B->rows
+ * entries: the data term of a Gaussian log-likelihood, -x^T J x / 2 (Section 5.2).  One sparse
+ * product into library scratch and a fixed-order FP64 dot; *out is a host double. */
+int ld_quadratic_form(const ld_csr *B, const double *x, void *stream, double *out);
+
 /* Write the probe block: out[r * M + j] = v_j[r] (int8, +1/-1), r < rows, j < M. */
 int ld_probes(uint64_t seed, int M, int64_t rows, int8_t *out, void *stream);
 

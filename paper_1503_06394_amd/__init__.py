@@ -21,7 +21,7 @@ __all__ = [
     "LogdetChebError", "DeviceCSR", "lib", "ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad",
     "ld_logdet_cheb_batched", "ld_gershgorin", "ld_probes", "ld_transpose", "ld_workspace_bytes", "ld_copy",
     "ld_version", "ld_clear_cache", "ld_spectral_estimate", "ld_laplacian_minor", "ld_log_spanning_trees",
-    "ld_logdet_taylor",
+    "ld_logdet_taylor", "ld_quadratic_form",
     "LogdetCheb", "logdet_cheb", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
 ]
 
@@ -88,13 +88,14 @@ def lib():
         L.ld_spectral_estimate.restype = I
         L.ld_laplacian_minor.argtypes = [P, I64, P, P, P, ctypes.c_int32, P, P]
         L.ld_logdet_taylor.argtypes = [P, D, D, I, I, U64, P, P, P]
+        L.ld_quadratic_form.argtypes = [P, P, P, P]
         L.ld_log_spanning_trees.argtypes = [P, I64, I, I, U64, I, P, P, P]
         L.ld_clear_cache.argtypes = []
         L.ld_last_error.restype = ctypes.c_char_p
         L.ld_version.restype = ctypes.c_char_p
         for f in ("ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad", "ld_logdet_cheb_batched",
                   "ld_gershgorin", "ld_probes", "ld_transpose", "ld_copy", "ld_clear_cache", "ld_laplacian_minor",
-                  "ld_log_spanning_trees", "ld_logdet_taylor"):
+                  "ld_log_spanning_trees", "ld_logdet_taylor", "ld_quadratic_form"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -238,6 +239,17 @@ def ld_logdet_taylor(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int
     if pv is not None:
         out["s"] = pv
     return out
+
+
+def ld_quadratic_form(B: DeviceCSR, x: torch.Tensor, stream=None) -> float:
+    """x^T (B + diag_shift I) x in FP64; x is a contiguous float64 device vector of length d."""
+    if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.numel() != B.d:
+        raise LogdetChebError("x must be a contiguous float64 device vector of length d")
+    out = ctypes.c_double(0.0)
+    cb = B.c()
+    _check(lib().ld_quadratic_form(ctypes.byref(cb), x.data_ptr(), _stream_ptr(stream), ctypes.byref(out)),
+           "ld_quadratic_form")
+    return out.value
 
 
 def ld_laplacian_minor(adj: DeviceCSR, hub: int, dtype: torch.dtype = torch.float32, stream=None) -> tuple:

@@ -1558,6 +1558,54 @@ static double tridiag_eig(const std::vector<double>& a, const std::vector<double
   return 0.5 * (lo + hi);
 }
 
+int ld_quadratic_form(const ld_csr* B, const double* x, void* stream, double* out) {
+  int rc = check_csr(B, "B");
+  if (rc) return rc;
+  if (!out || (!x && B->rows > 0)) return fail(LD_EINVAL, "x or out is NULL");
+  const int64_t d = B->rows;
+  if (d == 0) {
+    *out = 0.0;
+    return LD_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Carve c;
+  c.take((size_t)d * 8);
+  c.take(kDotScratch * 8);
+  c.take(8);
+  Workspace ws;
+  rc = get_workspace(nullptr, align_up(c.off), s, ws);
+  if (rc) return rc;
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  double* y = static_cast<double*>(cv.take((size_t)d * 8));
+  double* part = static_cast<double*>(cv.take(kDotScratch * 8));
+  double* res = static_cast<double*>(cv.take(8));
+  StepLaunch L{};
+  L.nmat = 1;
+  L.M = 1;
+  L.shape = with_tile(base_shape(1, 1), d, B->nnz, 0);
+  L.tile_rows = L.shape.tile_rows;
+  L.ntiles = (d + L.tile_rows - 1) / L.tile_rows;
+  StepDesc D{};
+  D.row_ptr = B->row_ptr;
+  D.col = B->col_idx;
+  D.val = B->values;
+  D.d = d;
+  D.active = 1;
+  D.G = x;
+  D.out = y;
+  D.ag = 1.0;
+  D.bd = B->diag_shift;
+  L.d0 = D;
+  LD_HIP(launch_step(L, 1, valt_of(B->dtype), SRC_BUF, SRC_SAME, SRC_NONE, MU_NONE, s));  // y = (B + shift I) x
+  LD_HIP(launch_dot(x, y, d, part, res, s));
+  double h = 0.0;
+  LD_HIP(hipMemcpyAsync(&h, res, 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  *out = h;
+  return LD_OK;
+}
+
 int ld_spectral_estimate(const ld_csr* B, const ld_csr* Ct_in, int gram, int iters, uint64_t seed, void* stream,
                          double* lo, double* hi) {
   int rc = check_csr(B, "B");

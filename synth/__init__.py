@@ -32,6 +32,8 @@ __all__ = [
     "wheel_graph",
     "complete_graph",
     "hub_graph",
+    "gmrf_grid_precision",
+    "gmrf_sample",
     "permute",
     "dense",
 ]
@@ -296,3 +298,39 @@ def hub_graph(nv: int, k_off: int = 5, mseed: int = 7) -> CSR:
     u = np.concatenate([np.zeros(m, dtype=np.int64), np.repeat(np.arange(1, nv, dtype=np.int64), k_off)])
     v = np.concatenate([np.arange(1, nv, dtype=np.int64), draws.reshape(-1)])
     return graph_from_edges(nv, u, v, "hub")
+
+
+# ----------------------------------------------------------------------------------------
+# grid GMRF with partial correlation rho (maximum-likelihood experiment of Section 5.2)
+
+
+def gmrf_grid_precision(N: int, rho: float, storage: str = "f32") -> CSR:
+    """Precision matrix J(rho) of the N x N grid GMRF whose nodes have four neighbours with
+    partial correlation rho: J_ii = 1 and J_ij = -rho for grid neighbours (Dirichlet boundary, so
+    border nodes have fewer neighbours).  Positive definite for |rho| < 1/4."""
+    L = grid_laplacian_2d(N, "f64")
+    diag = L.col.astype(np.int64) == L.row_of_entry()
+    val = np.where(diag, 1.0, -float(rho))
+    return CSR(L.d, L.row_ptr, L.col, round_to(val, storage), storage, {"kind": "gmrf_grid", "N": N, "rho": rho})
+
+
+def gmrf_sample(N: int, rho: float, seed: int = 0, z: np.ndarray | None = None) -> np.ndarray:
+    """One exact draw x ~ N(0, J(rho)^{-1}) of the grid GMRF above (float64, length N*N), with
+    J(rho) taken in exact arithmetic.  The grid's adjacency matrix is diagonalised by the
+    orthonormal type-I discrete sine transform S (S = S^T = S^{-1}, eigenvalues
+    2cos(p pi/(N+1)) + 2cos(q pi/(N+1))), so x = S diag(1 - rho lambda_pq)^{-1/2} S z with z
+    standard normal (drawn from ``seed`` unless given as an (N*N,) or (N*N, k) array)."""
+    from scipy.fft import dstn
+
+    if z is None:
+        z = np.random.default_rng(seed).standard_normal(N * N)
+    z = np.asarray(z, dtype=np.float64)
+    cols = z.reshape(N * N, -1)
+    t = np.pi * np.arange(1, N + 1) / (N + 1)
+    lam = 2.0 * np.cos(t)[:, None] + 2.0 * np.cos(t)[None, :]
+    scale = 1.0 / np.sqrt(1.0 - rho * lam)
+    out = np.empty_like(cols)
+    for k in range(cols.shape[1]):
+        g = dstn(cols[:, k].reshape(N, N), type=1, norm="ortho")
+        out[:, k] = dstn(g * scale, type=1, norm="ortho").reshape(-1)
+    return out.reshape(z.shape)

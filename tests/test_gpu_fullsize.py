@@ -127,3 +127,32 @@ def test_spanning_trees_1m_probe(ld, oracle_lib):
         say(f"full size spanning trees: oracle probe {j}")
         o = oracle_lib.log_spanning_trees(G, 0, 100, 1, seed=8, method=1, ids=np.array([j]))
         assert rel(r["s"][j], o["s"][0], FLOOR * G.d) <= TOL32, (j, r["s"][j], o["s"][0])
+
+
+@pytest.mark.timeout(900)
+def test_gmrf_5000_likelihood(ld, oracle_lib):
+    """The 5000 x 5000 grid GMRF of Section 5.2 (d = 25M): a draw at rho = -0.22, the
+    log-likelihood at three values of rho (FP32, M = 16, n = 40, the same probes), maximal at the
+    hidden value; probe 0 of the log det at rho = -0.22 against the oracle."""
+    import torch
+
+    from paper_1503_06394_amd.gmrf import GMRF
+
+    N = 5000
+    say("full size gmrf5000: pattern and sample")
+    L = synth.grid_laplacian_2d(N, "f32")
+    x = synth.gmrf_sample(N, -0.22, seed=1)
+    D = dev(L)
+    g = GMRF(D.row_ptr, D.col)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    del D
+    say("full size gmrf5000: GPU curve")
+    curve = g.sweep([-0.24, -0.22, -0.20], xt, 40, 16, 2)
+    assert max(curve, key=lambda r: r["loglik"])["rho"] == -0.22
+    J = g.precision(-0.22)
+    r = ld.ld_logdet_cheb(J, 0.12, 1.88, 40, 16, 2, want_probes=True)
+    del J, g, xt
+    say("full size gmrf5000: oracle probe 0")
+    Jh = synth.gmrf_grid_precision(N, -0.22, "f32")
+    o = oracle_lib.logdet(Jh, 0.12, 1.88, 40, 1, seed=2, ids=np.array([0]))
+    assert rel(r["s"][0], o["s"][0], FLOOR * Jh.d) <= TOL32
