@@ -1,0 +1,118 @@
+"""Edge cases of every estimator entry point: the empty matrix, the largest probe block, very high
+degree, and argument errors raised before any kernel runs."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests._gpu import FLOOR, dev, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ld():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_1503_06394_amd as pkg
+
+    pkg.lib()
+    return pkg
+
+
+def _empty(ld, dtype):
+    import torch
+
+    return ld.DeviceCSR(torch.zeros(1, dtype=torch.int64, device="cuda"), torch.zeros(0, dtype=torch.int32, device="cuda"),
+                        torch.zeros(0, dtype=dtype, device="cuda"))
+
+
+@pytest.mark.parametrize("f64", [False, True])
+def test_empty_matrix_has_log_det_zero(ld, f64):
+    import torch
+
+    E = _empty(ld, torch.float64 if f64 else torch.float32)
+    say(f"empty matrix f64={f64}")
+    for r in (ld.ld_logdet_cheb(E, 1.0, 2.0, 10, 4, 1, want_probes=True),
+              ld.ld_logdet_cheb(E, 1.0, 2.0, 10, 4, 1, plain=True),
+              ld.ld_logabsdet_cheb(E, None, 1.0, 2.0, 10, 4, 1),
+              ld.ld_logdet_taylor(E, 1.0, 2.0, 10, 4, 1)):
+        assert r["status"] == 0 and r["logdet"] == 0.0
+    r, g = ld.ld_logdet_cheb_grad(E, 1.0, 2.0, 10, 4, 1)
+    assert r["logdet"] == 0.0 and g.numel() == 0 and r["grad_shift"] == 0.0
+
+
+def test_largest_probe_block(ld, oracle_lib):
+    """M = 4096, the most one call accepts (many probe tiles per pass), FP32; M = 4097 is refused."""
+    B = synth.random_sparse_spd(300, 3, 13, 1.0, "f32")
+    a, b = oracle_lib.gershgorin(B)
+    say("M = 4096")
+    r = ld.ld_logdet_cheb(dev(B), a, b, 12, 4096, 5, want_probes=True)
+    o = oracle_lib.logdet(B, a, b, 12, 4096, seed=5)
+    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-4
+    for j in (0, 63, 64, 2047, 4095):
+        assert rel(r["s"][j], o["s"][j], FLOOR * B.d) <= 1e-4, j
+    with pytest.raises(ld.LogdetChebError):
+        ld.ld_logdet_cheb(dev(B), a, b, 12, 4097, 5)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_high_degree_fp64(ld, oracle_lib, plain):
+    """n = 2000 (the recurrence and the product identities stay within FP64 parity)."""
+    B = synth.random_sparse_spd(400, 3, 17, 1.0, "f64")
+    a, b = oracle_lib.gershgorin(B)
+    say(f"n = 2000 plain={plain}")
+    r = ld.ld_logdet_cheb(dev(B), a, b, 2000, 8, 6, plain=plain)
+    o = oracle_lib.logdet(B, a, b, 2000, 8, seed=6)
+    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10
+
+
+def test_argument_errors_before_any_kernel(ld):
+    B = dev(synth.random_sparse_spd(100, 3, 2, 1.0, "f32"))
+    say("argument errors")
+    bad = [(0.0, 1.0, 10, 4), (2.0, 1.0, 10, 4), (1.0, 1.0, 10, 4), (float("nan"), 2.0, 10, 4),
+           (1.0, float("inf"), 10, 4), (1.0, 2.0, -1, 4), (1.0, 2.0, 100001, 4), (1.0, 2.0, 10, 0)]
+    for a, b, n, M in bad:
+        for f in (ld.ld_logdet_cheb, ld.ld_logdet_taylor):
+            with pytest.raises(ld.LogdetChebError):
+                f(B, a, b, n, M, 1)
+        with pytest.raises(ld.LogdetChebError):
+            ld.ld_logdet_cheb_grad(B, a, b, n, M, 1)
+    with pytest.raises(ld.LogdetChebError):
+        ld.ld_logabsdet_cheb(B, None, 0.0, 1.0, 10, 4, 1)
+    shifted = ld.DeviceCSR(B.row_ptr, B.col, B.values, 0.5)
+    with pytest.raises(ld.LogdetChebError, match="diag_shift"):
+        ld.ld_logabsdet_cheb(shifted, None, 0.5, 1.0, 10, 4, 1)
+
+
+def _graph_laplacian_plus_identity(G):
+    """L + I of a graph: -1 per edge, degree + 1 on the diagonal (rows sorted by column)."""
+    rows = np.repeat(np.arange(G.d), np.diff(G.row_ptr))
+    r = np.concatenate([rows, np.arange(G.d)])
+    c = np.concatenate([G.col.astype(np.int64), np.arange(G.d)])
+    v = np.concatenate([-np.ones(G.nnz), np.diff(G.row_ptr) + 1.0])
+    o = np.lexsort((c, r))
+    row_ptr = np.zeros(G.d + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=G.d), out=row_ptr[1:])
+    return synth.CSR(G.d, row_ptr, c[o].astype(np.int32), v[o], "f64", {})
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_row_longer_than_the_lds_slice(ld, oracle_lib, plain):
+    """A hub row with 4999 stored entries overflows the LDS staging of its tile, which then reads
+    the CSR from global memory: forward and gradient against the oracle (FP64)."""
+    B = _graph_laplacian_plus_identity(synth.hub_graph(5000, 2, 3))
+    assert np.diff(B.row_ptr).max() > 4096
+    a, b = oracle_lib.gershgorin(B)
+    say(f"long row: forward and gradient plain={plain}")
+    r = ld.ld_logdet_cheb(dev(B), a, b, 20, 16, 4, plain=plain)
+    o = oracle_lib.logdet(B, a, b, 20, 16, seed=4)
+    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10
+    rg, g = ld.ld_logdet_cheb_grad(dev(B), a, b, 20, 16, 4, plain=plain)
+    og = oracle_lib.logdet_grad(B, a, b, 20, 16, seed=4)
+    gg = g.cpu().numpy()
+    assert np.max(np.abs(gg - og["grad"])) <= 1e-10 * np.max(np.abs(og["grad"]))
