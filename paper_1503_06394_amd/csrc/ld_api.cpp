@@ -19,6 +19,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/logdet_cheb.h"
@@ -28,16 +29,33 @@ using namespace ld;
 
 namespace {
 
-thread_local std::string g_err;
+thread_local char g_err[512] = "";
 
+// Records the message for ld_last_error (never allocates, never throws) and returns `code`.
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
+}
+
+// Runs an entry point's body so that no C++ exception (host allocation failure in a std::vector,
+// std::map, ...) crosses the C ABI.  Status-returning entry points then return LD_ENOMEM or
+// LD_EINVAL; ld_workspace_bytes returns 0.  The message is left for ld_last_error.
+template <typename R, typename F>
+R guarded(F&& body) noexcept {
+  int code;
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    code = fail(LD_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    code = fail(LD_EINVAL, "internal error: %s", e.what());
+  } catch (...) {
+    code = fail(LD_EINVAL, "internal error");
+  }
+  return std::is_same<R, int>::value ? (R)code : (R)0;
 }
 
 int fail_hip(hipError_t e, const char* what) {
@@ -902,7 +920,8 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
   c.take((size_t)count * 4);
   const size_t off_n = c.off - (size_t)count * 4;
   hipError_t e = hipMalloc(&E.mem, align_up(c.off));
-  if (e != hipSuccess) return fail(LD_ENOMEM, "hipMalloc(%zu) for the batch: %s", align_up(c.off), hipGetErrorString(e));
+  if (e != hipSuccess)
+    return fail(LD_ENOMEM, "hipMalloc(%zu) for the batch: %s", align_up(c.off), hipGetErrorString(e));
   char* base = static_cast<char*>(E.mem);
   for (int i = 0; i < count; ++i) {
     bufA[i] = base + offA[i];
@@ -986,11 +1005,11 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
 
 extern "C" {
 
-const char* ld_last_error(void) { return g_err.c_str(); }
+const char* ld_last_error(void) { return g_err; }
 
 const char* ld_version(void) { return "logdet_cheb 1.0 (gfx950)"; }
 
-size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) {
+static size_t workspace_bytes_impl(const ld_csr* B, int n, int M, int mode, int vec_f64) {
   if (!B || n < 0 || M < 1) return 0;
   const int valt = valt_of(B->dtype);
   ld_opts o{};
@@ -1001,8 +1020,8 @@ size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) 
   return fwd_workspace(B, n, M, v64, mode == 1, nullptr);
 }
 
-int ld_logdet_cheb(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
-                   void* stream, ld_result* out) {
+static int logdet_cheb_impl(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
+                            void* stream, ld_result* out) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
   rc = check_common(a, b, n, M);
@@ -1015,8 +1034,8 @@ int ld_logdet_cheb(const ld_csr* B, double a, double b, int n, int M, uint64_t s
   return rc;
 }
 
-int ld_logdet_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
-                     void* stream, ld_result* out) {
+static int logdet_taylor_impl(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
+                              void* stream, ld_result* out) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
   rc = check_common(a, b, n, M);
@@ -1029,8 +1048,8 @@ int ld_logdet_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t
   return rc;
 }
 
-int ld_logabsdet_cheb(const ld_csr* C, const ld_csr* Ct, double smin, double smax, int n, int M, uint64_t seed,
-                      const ld_opts* opt, void* stream, ld_result* out) {
+static int logabsdet_cheb_impl(const ld_csr* C, const ld_csr* Ct, double smin, double smax, int n, int M, uint64_t seed,
+                               const ld_opts* opt, void* stream, ld_result* out) {
   int rc = check_csr(C, "C");
   if (rc) return rc;
   if (Ct) {
@@ -1052,8 +1071,8 @@ int ld_logabsdet_cheb(const ld_csr* C, const ld_csr* Ct, double smin, double sma
   return rc;
 }
 
-int ld_laplacian_minor(const ld_csr* adj, int64_t hub, int64_t* row_ptr_out, int32_t* col_out, void* val_out,
-                       int32_t val_dtype, int64_t* max_degree, void* stream) {
+static int laplacian_minor_impl(const ld_csr* adj, int64_t hub, int64_t* row_ptr_out, int32_t* col_out, void* val_out,
+                                int32_t val_dtype, int64_t* max_degree, void* stream) {
   int rc = check_csr(adj, "adj");
   if (rc) return rc;
   if (adj->rows < 2) return fail(LD_EINVAL, "a graph needs at least 2 vertices; got %lld", (long long)adj->rows);
@@ -1092,8 +1111,8 @@ int ld_laplacian_minor(const ld_csr* adj, int64_t hub, int64_t* row_ptr_out, int
   return LD_OK;
 }
 
-int ld_log_spanning_trees(const ld_csr* adj, int64_t hub, int n, int M, uint64_t seed, int method, const ld_opts* opt,
-                          void* stream, ld_result* out) {
+static int log_spanning_trees_impl(const ld_csr* adj, int64_t hub, int n, int M, uint64_t seed, int method,
+                                   const ld_opts* opt, void* stream, ld_result* out) {
   if (method != 0 && method != 1) return fail(LD_EINVAL, "method must be 0 (Algorithm 1) or 1 (Algorithm 2)");
   if (!out) return fail(LD_EINVAL, "out is NULL");
   int rc = check_csr(adj, "adj");
@@ -1140,7 +1159,7 @@ int ld_log_spanning_trees(const ld_csr* adj, int64_t hub, int n, int M, uint64_t
   return rc;
 }
 
-int ld_gershgorin(const ld_csr* B, double* a, double* b, void* stream) {
+static int gershgorin_impl(const ld_csr* B, double* a, double* b, void* stream) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
   if (!a || !b) return fail(LD_EINVAL, "a or b is NULL");
@@ -1167,7 +1186,7 @@ int ld_gershgorin(const ld_csr* B, double* a, double* b, void* stream) {
   return LD_OK;
 }
 
-int ld_probes(uint64_t seed, int M, int64_t rows, int8_t* out, void* stream) {
+static int probes_impl(uint64_t seed, int M, int64_t rows, int8_t* out, void* stream) {
   if (M < 1 || rows < 0 || (!out && rows > 0)) return fail(LD_EINVAL, "invalid probe block arguments");
   hipStream_t s = static_cast<hipStream_t>(stream);
   LD_HIP(launch_probes(seed, M, rows, out, s));
@@ -1175,7 +1194,7 @@ int ld_probes(uint64_t seed, int M, int64_t rows, int8_t* out, void* stream) {
   return LD_OK;
 }
 
-int ld_transpose(const ld_csr* C, int64_t* row_ptr_t, int32_t* col_t, void* val_t, void* stream) {
+static int transpose_impl(const ld_csr* C, int64_t* row_ptr_t, int32_t* col_t, void* val_t, void* stream) {
   int rc = check_csr(C, "C");
   if (rc) return rc;
   if (!row_ptr_t || (C->nnz > 0 && (!col_t || !val_t))) return fail(LD_EINVAL, "NULL output buffer");
@@ -1191,7 +1210,7 @@ int ld_transpose(const ld_csr* C, int64_t* row_ptr_t, int32_t* col_t, void* val_
   return LD_OK;
 }
 
-int ld_copy(void* dst, const void* src, size_t bytes, void* stream, double* ms) {
+static int copy_impl(void* dst, const void* src, size_t bytes, void* stream, double* ms) {
   if ((!dst || !src) && bytes) return fail(LD_EINVAL, "NULL pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
@@ -1209,8 +1228,8 @@ int ld_copy(void* dst, const void* src, size_t bytes, void* stream, double* ms) 
   return LD_OK;
 }
 
-int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, double grad_output,
-                        void* grad_values, int grad_dtype, const ld_opts* opt, void* stream, ld_result* out) {
+static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, double grad_output,
+                                 void* grad_values, int grad_dtype, const ld_opts* opt, void* stream, ld_result* out) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
   rc = check_common(a, b, n, M);
@@ -1451,8 +1470,8 @@ int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint6
   return r.flags ? LD_WBOUNDS : LD_OK;
 }
 
-int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M,
-                           uint64_t seed, const ld_opts* opt, void* stream, ld_result* outs) {
+static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M,
+                                    uint64_t seed, const ld_opts* opt, void* stream, ld_result* outs) {
   if (count < 1 || !Bs || !a || !b || !n || !outs) return fail(LD_EINVAL, "invalid batch arguments");
   if (M < 1 || M > 4096) return fail(LD_EINVAL, "probe count M=%d out of range [1, 4096]", M);
   for (int i = 0; i < count; ++i) {
@@ -1558,7 +1577,7 @@ static double tridiag_eig(const std::vector<double>& a, const std::vector<double
   return 0.5 * (lo + hi);
 }
 
-int ld_quadratic_form(const ld_csr* B, const double* x, void* stream, double* out) {
+static int quadratic_form_impl(const ld_csr* B, const double* x, void* stream, double* out) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
   if (!out || (!x && B->rows > 0)) return fail(LD_EINVAL, "x or out is NULL");
@@ -1606,8 +1625,8 @@ int ld_quadratic_form(const ld_csr* B, const double* x, void* stream, double* ou
   return LD_OK;
 }
 
-int ld_spectral_estimate(const ld_csr* B, const ld_csr* Ct_in, int gram, int iters, uint64_t seed, void* stream,
-                         double* lo, double* hi) {
+static int spectral_estimate_impl(const ld_csr* B, const ld_csr* Ct_in, int gram, int iters, uint64_t seed,
+                                  void* stream, double* lo, double* hi) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
   if (!lo || !hi) return fail(LD_EINVAL, "lo or hi is NULL");
@@ -1722,7 +1741,7 @@ int ld_spectral_estimate(const ld_csr* B, const ld_csr* Ct_in, int gram, int ite
   return LD_OK;
 }
 
-int ld_clear_cache(void) {
+static int clear_cache_impl(void) {
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     g_batch.clear();
@@ -1733,3 +1752,79 @@ int ld_clear_cache(void) {
 }
 
 }  // extern "C"
+
+// ======================================================================================
+// C ABI: every entry point runs under `guarded`
+// ======================================================================================
+
+size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) {
+  return guarded<size_t>([&] { return workspace_bytes_impl(B, n, M, mode, vec_f64); });
+}
+
+int ld_logdet_cheb(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
+                   void* stream, ld_result* out) {
+  return guarded<int>([&] { return logdet_cheb_impl(B, a, b, n, M, seed, opt, stream, out); });
+}
+
+int ld_logdet_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
+                     void* stream, ld_result* out) {
+  return guarded<int>([&] { return logdet_taylor_impl(B, a, b, n, M, seed, opt, stream, out); });
+}
+
+int ld_logabsdet_cheb(const ld_csr* C, const ld_csr* Ct, double smin, double smax, int n, int M, uint64_t seed,
+                      const ld_opts* opt, void* stream, ld_result* out) {
+  return guarded<int>([&] { return logabsdet_cheb_impl(C, Ct, smin, smax, n, M, seed, opt, stream, out); });
+}
+
+int ld_laplacian_minor(const ld_csr* adj, int64_t hub, int64_t* row_ptr_out, int32_t* col_out, void* val_out,
+                       int32_t val_dtype, int64_t* max_degree, void* stream) {
+  return guarded<int>([&] {
+    return laplacian_minor_impl(adj, hub, row_ptr_out, col_out, val_out, val_dtype, max_degree, stream);
+  });
+}
+
+int ld_log_spanning_trees(const ld_csr* adj, int64_t hub, int n, int M, uint64_t seed, int method, const ld_opts* opt,
+                          void* stream, ld_result* out) {
+  return guarded<int>([&] { return log_spanning_trees_impl(adj, hub, n, M, seed, method, opt, stream, out); });
+}
+
+int ld_gershgorin(const ld_csr* B, double* a, double* b, void* stream) {
+  return guarded<int>([&] { return gershgorin_impl(B, a, b, stream); });
+}
+
+int ld_probes(uint64_t seed, int M, int64_t rows, int8_t* out, void* stream) {
+  return guarded<int>([&] { return probes_impl(seed, M, rows, out, stream); });
+}
+
+int ld_transpose(const ld_csr* C, int64_t* row_ptr_t, int32_t* col_t, void* val_t, void* stream) {
+  return guarded<int>([&] { return transpose_impl(C, row_ptr_t, col_t, val_t, stream); });
+}
+
+int ld_copy(void* dst, const void* src, size_t bytes, void* stream, double* ms) {
+  return guarded<int>([&] { return copy_impl(dst, src, bytes, stream, ms); });
+}
+
+int ld_logdet_cheb_grad(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, double grad_output,
+                        void* grad_values, int grad_dtype, const ld_opts* opt, void* stream, ld_result* out) {
+  return guarded<int>([&] {
+    return logdet_cheb_grad_impl(B, a, b, n, M, seed, grad_output, grad_values, grad_dtype, opt, stream, out);
+  });
+}
+
+int ld_logdet_cheb_batched(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M,
+                           uint64_t seed, const ld_opts* opt, void* stream, ld_result* outs) {
+  return guarded<int>([&] { return logdet_cheb_batched_impl(count, Bs, a, b, n, M, seed, opt, stream, outs); });
+}
+
+int ld_quadratic_form(const ld_csr* B, const double* x, void* stream, double* out) {
+  return guarded<int>([&] { return quadratic_form_impl(B, x, stream, out); });
+}
+
+int ld_spectral_estimate(const ld_csr* B, const ld_csr* Ct_in, int gram, int iters, uint64_t seed, void* stream,
+                         double* lo, double* hi) {
+  return guarded<int>([&] { return spectral_estimate_impl(B, Ct_in, gram, iters, seed, stream, lo, hi); });
+}
+
+int ld_clear_cache(void) {
+  return guarded<int>([&] { return clear_cache_impl(); });
+}
