@@ -362,9 +362,7 @@ def bench_batch(args, W, copy_gbps) -> None:
 
     mats, M, seed = W["mats"], W["M"], W["seed"]
     D = [ld.DeviceCSR.from_host(B, device="cuda:0") for B in mats]
-    ab = [ld.ld_gershgorin(x) for x in D]
-    a = [x[0] for x in ab]
-    b = [x[1] for x in ab]
+    a, b = ld.ld_gershgorin_batched(D)
     ns = [B.meta["n"] for B in mats]
     work = sum(M * ns[i] * mats[i].nnz for i in range(len(mats)))
     log(f"batch: {len(mats)} matrices, sum d={sum(B.d for B in mats)}, sum nnz={sum(B.nnz for B in mats)}")
@@ -374,8 +372,8 @@ def bench_batch(args, W, copy_gbps) -> None:
     t0 = time.perf_counter()
     gms = 0.0
     for _ in range(args.steps):
-        ab = [ld.ld_gershgorin(x) for x in D]
-        res = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, M, seed, timing=True)
+        ga, gb = ld.ld_gershgorin_batched(D)
+        res = ld.ld_logdet_cheb_batched(D, ga, gb, ns, M, seed, timing=True)
         gms += res[0]["kernel_ms"]
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps

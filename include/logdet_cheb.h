@@ -144,8 +144,9 @@ int ld_logdet_cheb_grad(const ld_csr *B, double a, double b, int n, int M, uint6
 /* Batched Algorithm 1: matrix i (count of them, uneven sizes) uses its own bounds
  * [a[i], b[i]], degree n[i] and probe seed seed + i, all with M probes.  The whole batch
  * runs as one captured HIP graph.  a, b, n, outs are host arrays of `count` entries;
- * Bs is a host array of descriptors pointing at device data.  opt->moments_out and
- * opt->probe_out are ignored. */
+ * Bs is a host array of descriptors pointing at device data.  a and b may both be NULL:
+ * then every member gets its Gershgorin interval (ld_gershgorin_batched).  opt->moments_out
+ * and opt->probe_out are ignored. */
 int ld_logdet_cheb_batched(int count, const ld_csr *Bs, const double *a, const double *b,
                            const int *n, int M, uint64_t seed, const ld_opts *opt, void *stream,
                            ld_result *outs);
@@ -153,6 +154,11 @@ int ld_logdet_cheb_batched(int count, const ld_csr *Bs, const double *a, const d
 /* Gershgorin interval of B + diag_shift I (FP64):
  * a = min_i (B_ii + shift - sum_{j != i} |B_ij|), b = max_i (B_ii + shift + sum_{j != i} |B_ij|). */
 int ld_gershgorin(const ld_csr *B, double *a, double *b, void *stream);
+
+/* Gershgorin intervals of `count` matrices (host array of descriptors of device data, one
+ * dtype, none empty) in one pass: a[i], b[i] (host) as ld_gershgorin would give them, bit for
+ * bit (the bounds of a1 for a batch). */
+int ld_gershgorin_batched(int count, const ld_csr *Bs, double *a, double *b, void *stream);
 
 /* Estimates of the extreme eigenvalues of B + diag_shift I (gram = 0, B symmetric) or of
  * C^T C (gram = 1; Ct nullable, built on the device if NULL) by `iters` steps of the Lanczos

@@ -21,7 +21,7 @@ __all__ = [
     "LogdetChebError", "DeviceCSR", "lib", "ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad",
     "ld_logdet_cheb_batched", "ld_gershgorin", "ld_probes", "ld_transpose", "ld_workspace_bytes", "ld_copy",
     "ld_version", "ld_clear_cache", "ld_spectral_estimate", "ld_laplacian_minor", "ld_log_spanning_trees",
-    "ld_logdet_taylor", "ld_quadratic_form",
+    "ld_logdet_taylor", "ld_quadratic_form", "ld_gershgorin_batched",
     "LogdetCheb", "logdet_cheb", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
 ]
 
@@ -79,6 +79,7 @@ def lib():
         L.ld_logdet_cheb_grad.argtypes = [P, D, D, I, I, U64, D, P, I, P, P, P]
         L.ld_logdet_cheb_batched.argtypes = [I, P, P, P, P, I, U64, P, P, P]
         L.ld_gershgorin.argtypes = [P, P, P, P]
+        L.ld_gershgorin_batched.argtypes = [I, P, P, P, P]
         L.ld_probes.argtypes = [U64, I, I64, P, P]
         L.ld_transpose.argtypes = [P, P, P, P, P]
         L.ld_workspace_bytes.argtypes = [P, I, I, I, I]
@@ -95,7 +96,7 @@ def lib():
         L.ld_version.restype = ctypes.c_char_p
         for f in ("ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad", "ld_logdet_cheb_batched",
                   "ld_gershgorin", "ld_probes", "ld_transpose", "ld_copy", "ld_clear_cache", "ld_laplacian_minor",
-                  "ld_log_spanning_trees", "ld_logdet_taylor", "ld_quadratic_form"):
+                  "ld_log_spanning_trees", "ld_logdet_taylor", "ld_quadratic_form", "ld_gershgorin_batched"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -318,17 +319,30 @@ def ld_logdet_cheb_grad(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: 
 
 def ld_logdet_cheb_batched(mats: list, a, b, n, M: int, seed: int, *, vec_f64=None, tile=0, timing=False,
                            plain=False, stream=None) -> list:
-    """Batched Algorithm 1: matrix i uses [a[i], b[i]], degree n[i] and probe seed seed + i."""
+    """Batched Algorithm 1: matrix i uses [a[i], b[i]], degree n[i] and probe seed seed + i.
+    With a = b = None every member gets its Gershgorin interval, computed in one device pass."""
     count = len(mats)
+    if (a is None) != (b is None):
+        raise LogdetChebError("give both a and b, or neither")
     arr = (_CSR * count)(*[m.c() for m in mats])
-    av = (ctypes.c_double * count)(*[float(x) for x in a])
-    bv = (ctypes.c_double * count)(*[float(x) for x in b])
+    av = (ctypes.c_double * count)(*[float(x) for x in a]) if a is not None else None
+    bv = (ctypes.c_double * count)(*[float(x) for x in b]) if b is not None else None
     nv = (ctypes.c_int * count)(*[int(x) for x in n])
     res = (_Result * count)()
     o = _opts(vec_f64, tile, timing, plain=plain)
     rc = _check(lib().ld_logdet_cheb_batched(count, arr, av, bv, nv, int(M), int(seed) & (2**64 - 1),
                                              ctypes.byref(o), _stream_ptr(stream), res), "ld_logdet_cheb_batched")
     return [_result(res[i], rc) for i in range(count)]
+
+
+def ld_gershgorin_batched(mats: list, stream=None) -> tuple:
+    """Gershgorin intervals of every matrix of a batch in one device pass: (list of a, list of b)."""
+    count = len(mats)
+    arr = (_CSR * count)(*[m.c() for m in mats])
+    av = (ctypes.c_double * count)()
+    bv = (ctypes.c_double * count)()
+    _check(lib().ld_gershgorin_batched(count, arr, av, bv, _stream_ptr(stream)), "ld_gershgorin_batched")
+    return list(av), list(bv)
 
 
 def ld_gershgorin(B: DeviceCSR, stream=None) -> tuple:

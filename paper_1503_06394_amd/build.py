@@ -25,7 +25,7 @@ HIP_FLAGS = [
 def build(verbose: bool = False, jobs: int = 4) -> str:
     objs = []
     procs = []
-    for src, lang in (("ld_kernels.hip", "hip"), ("ld_graph.hip", "hip"), ("ld_api.cpp", "hip")):
+    for src, lang in (("ld_kernels.hip", "hip"), ("ld_prep.hip", "hip"), ("ld_api.cpp", "hip")):
         obj = os.path.join(CSRC, src + ".o")
         cmd = [HIPCC, "-x", lang, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:

@@ -1159,6 +1159,55 @@ static int log_spanning_trees_impl(const ld_csr* adj, int64_t hub, int n, int M,
   return rc;
 }
 
+// Rows per work item of the batched Gershgorin pass.
+constexpr int64_t kGershRows = 4096;
+
+static int gershgorin_batched_impl(int count, const ld_csr* Bs, double* a, double* b, void* stream) {
+  if (count < 1 || !Bs || !a || !b) return fail(LD_EINVAL, "invalid batch arguments");
+  for (int i = 0; i < count; ++i) {
+    char name[32];
+    snprintf(name, sizeof(name), "Bs[%d]", i);
+    int rc = check_csr(&Bs[i], name);
+    if (rc) return rc;
+    if (Bs[i].rows < 1) return fail(LD_EINVAL, "Bs[%d] is empty: no spectrum", i);
+    if (Bs[i].dtype != Bs[0].dtype) return fail(LD_EDTYPE, "all batch matrices must share one dtype");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<GershItem> items;
+  std::vector<int> owner;
+  for (int i = 0; i < count; ++i)
+    for (int64_t r = 0; r < Bs[i].rows; r += kGershRows) {
+      items.push_back(GershItem{Bs[i].row_ptr, Bs[i].col_idx, Bs[i].values, Bs[i].diag_shift, r,
+                                std::min(Bs[i].rows, r + kGershRows)});
+      owner.push_back(i);
+    }
+  const int ni = (int)items.size();
+  Carve c;
+  c.take(sizeof(GershItem) * ni);
+  c.take((size_t)ni * 16);
+  Workspace ws;
+  int rc = get_workspace(nullptr, align_up(c.off), s, ws);
+  if (rc) return rc;
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  GershItem* d_items = static_cast<GershItem*>(cv.take(sizeof(GershItem) * ni));
+  double* part = static_cast<double*>(cv.take((size_t)ni * 16));
+  LD_HIP(hipMemcpyAsync(d_items, items.data(), sizeof(GershItem) * ni, hipMemcpyHostToDevice, s));
+  LD_HIP(launch_gershgorin_batched(d_items, ni, valt_of(Bs[0].dtype), part, part + ni, s));
+  std::vector<double> h(2 * (size_t)ni);
+  LD_HIP(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) {
+    a[i] = INFINITY;
+    b[i] = -INFINITY;
+  }
+  for (int k = 0; k < ni; ++k) {
+    a[owner[k]] = std::min(a[owner[k]], h[k]);
+    b[owner[k]] = std::max(b[owner[k]], h[ni + k]);
+  }
+  return LD_OK;
+}
+
 static int gershgorin_impl(const ld_csr* B, double* a, double* b, void* stream) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
@@ -1472,8 +1521,17 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
 
 static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M,
                                     uint64_t seed, const ld_opts* opt, void* stream, ld_result* outs) {
-  if (count < 1 || !Bs || !a || !b || !n || !outs) return fail(LD_EINVAL, "invalid batch arguments");
+  if (count < 1 || !Bs || !n || !outs || (!a) != (!b)) return fail(LD_EINVAL, "invalid batch arguments");
   if (M < 1 || M > 4096) return fail(LD_EINVAL, "probe count M=%d out of range [1, 4096]", M);
+  std::vector<double> ga, gb;
+  if (!a) {  // Gershgorin bounds of every member in one pass
+    ga.resize(count);
+    gb.resize(count);
+    int rc = gershgorin_batched_impl(count, Bs, ga.data(), gb.data(), stream);
+    if (rc) return rc;
+    a = ga.data();
+    b = gb.data();
+  }
   for (int i = 0; i < count; ++i) {
     char name[32];
     snprintf(name, sizeof(name), "Bs[%d]", i);
@@ -1786,6 +1844,10 @@ int ld_laplacian_minor(const ld_csr* adj, int64_t hub, int64_t* row_ptr_out, int
 int ld_log_spanning_trees(const ld_csr* adj, int64_t hub, int n, int M, uint64_t seed, int method, const ld_opts* opt,
                           void* stream, ld_result* out) {
   return guarded<int>([&] { return log_spanning_trees_impl(adj, hub, n, M, seed, method, opt, stream, out); });
+}
+
+int ld_gershgorin_batched(int count, const ld_csr* Bs, double* a, double* b, void* stream) {
+  return guarded<int>([&] { return gershgorin_batched_impl(count, Bs, a, b, stream); });
 }
 
 int ld_gershgorin(const ld_csr* B, double* a, double* b, void* stream) {

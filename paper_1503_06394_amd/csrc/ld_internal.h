@@ -139,6 +139,17 @@ hipError_t launch_sum_doubles(const double* x, int64_t n, double* out, hipStream
 hipError_t launch_gershgorin(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, double shift,
                              int64_t d, double* lo_part, double* hi_part, int nblocks, hipStream_t s);
 
+// One workgroup's share of a batched Gershgorin pass: rows [row0, row1) of one matrix.
+struct GershItem {
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const void* val;
+  double shift;
+  int64_t row0, row1;
+};
+hipError_t launch_gershgorin_batched(const GershItem* items, int nitems, int valt, double* lo_part, double* hi_part,
+                                     hipStream_t s);
+
 // Laplacian minor L(hub) of a graph given by its adjacency pattern (see the kernel); valt is
 // VAL_F64 or VAL_F32.  max_part / bad_part: nblocks partial maxima of the degree and counts of rows
 // that miss the hub or carry a self loop.

@@ -1,8 +1,70 @@
-// Graph kernels for gfx950: the Laplacian minor used to count spanning trees (Section 3.3 of
-// Han, Malioutov & Shin, arXiv 1503.06394).  Built once per graph, outside the estimator's loop.
+// Preparation kernels for gfx950 that run once per matrix, before the estimator's loop (Han,
+// Malioutov & Shin, arXiv 1503.06394): Gershgorin bounds for a whole batch of matrices in one
+// launch, and the Laplacian minor used to count spanning trees (Section 3.3).
 #include "ld_internal.h"
 
 namespace ld {
+
+// Stored value t of a CSR value array of type VALT, widened to double.
+template <int VALT>
+__device__ __forceinline__ double value_at(const void* p, int64_t t) {
+  if constexpr (VALT == VAL_F64) return static_cast<const double*>(p)[t];
+  if constexpr (VALT == VAL_F32) return (double)static_cast<const float*>(p)[t];
+  return (double)__uint_as_float((uint32_t)static_cast<const uint16_t*>(p)[t] << 16);  // BF16
+}
+
+// --- Gershgorin intervals of a batch ---
+//
+// Work item i (one per workgroup) covers rows [row0, row1) of one matrix and writes the minimum
+// of B_rr + shift - sum_{c != r} |B_rc| and the maximum of B_rr + shift + sum_{c != r} |B_rc| over
+// them; the host takes the min / max over a matrix's items.  Same arithmetic per row as the
+// single-matrix kernel, and min / max do not depend on order, so the bounds agree bit for bit.
+template <int VALT>
+__global__ void __launch_bounds__(256) gershgorin_batched_kernel(const GershItem* items, double* lo_part,
+                                                                 double* hi_part) {
+  const GershItem it = items[blockIdx.x];
+  double lo = __builtin_inf(), hi = -__builtin_inf();
+  for (int64_t r = it.row0 + threadIdx.x; r < it.row1; r += 256) {
+    double diag = 0.0, off = 0.0;
+    for (int64_t t = it.row_ptr[r]; t < it.row_ptr[r + 1]; ++t) {
+      const double v = value_at<VALT>(it.val, t);
+      if (it.col[t] == r)
+        diag += v;
+      else
+        off += fabs(v);
+    }
+    diag += it.shift;
+    lo = fmin(lo, diag - off);
+    hi = fmax(hi, diag + off);
+  }
+  __shared__ double sl[256], sh[256];
+  sl[threadIdx.x] = lo;
+  sh[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + w]);
+      sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    lo_part[blockIdx.x] = sl[0];
+    hi_part[blockIdx.x] = sh[0];
+  }
+}
+
+hipError_t launch_gershgorin_batched(const GershItem* items, int nitems, int valt, double* lo_part, double* hi_part,
+                                     hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (valt == VAL_F64)
+    hipLaunchKernelGGL(gershgorin_batched_kernel<VAL_F64>, dim3(nitems), dim3(256), 0, s, items, lo_part, hi_part);
+  else if (valt == VAL_F32)
+    hipLaunchKernelGGL(gershgorin_batched_kernel<VAL_F32>, dim3(nitems), dim3(256), 0, s, items, lo_part, hi_part);
+  else
+    hipLaunchKernelGGL(gershgorin_batched_kernel<VAL_BF16>, dim3(nitems), dim3(256), 0, s, items, lo_part, hi_part);
+  return hipGetLastError();
+}
 
 // --- Laplacian minor for spanning-tree counting (Kirchhoff's matrix-tree theorem) ---
 //

@@ -84,3 +84,28 @@ def test_batched_rejects_mixed_dtypes(ld):
     with pytest.raises(ld.LogdetChebError):
         ld.ld_logdet_cheb_batched([m1, m2], [0.1, 0.1], [10.0, 10.0], [5, 5], 4, 0)
     assert torch.cuda.is_available()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_gershgorin_batched_bit_exact(ld, oracle_lib, storage):
+    """One pass over a batch (members split into several work items, shifts included) gives the
+    single-matrix and the oracle's Gershgorin intervals bit for bit."""
+    mats = _batch(12, storage, d_max=20_000, seed0=410) + [synth.grid_laplacian_2d(90, storage)]
+    shifts = [0.0] * 12 + [0.25]
+    D = [dev(B, shift=s) for B, s in zip(mats, shifts)]
+    say(f"batched gershgorin {storage}")
+    a, b = ld.ld_gershgorin_batched(D)
+    for i, B in enumerate(mats):
+        assert (a[i], b[i]) == ld.ld_gershgorin(D[i])
+        assert (a[i], b[i]) == oracle_lib.gershgorin(B, shifts[i])
+
+
+def test_batched_default_bounds_are_gershgorin(ld, oracle_lib):
+    mats = _batch(6, "f32", seed0=1200)
+    ns = [B.meta["n"] for B in mats]
+    D = [dev(B) for B in mats]
+    say("batched with default bounds")
+    r0 = ld.ld_logdet_cheb_batched(D, None, None, ns, 16, 3)
+    ab = [oracle_lib.gershgorin(B) for B in mats]
+    r1 = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, 16, 3)
+    assert [r["logdet"] for r in r0] == [r["logdet"] for r in r1]
