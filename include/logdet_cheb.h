@@ -216,7 +216,8 @@ int ld_transpose(const ld_csr *C, int64_t *row_ptr_t, int32_t *col_t, void *val_
 size_t ld_workspace_bytes(const ld_csr *B, int n, int M, int mode, int vec_f64);
 
 /* Device-to-device streaming copy with the library's own kernel (HBM bandwidth probe);
- * returns the kernel duration in milliseconds through *ms (nullable). */
+ * returns the kernel duration in milliseconds through *ms (nullable).  dst and src must be
+ * 16-byte aligned (LD_EINVAL otherwise); any byte count is copied exactly. */
 int ld_copy(void *dst, const void *src, size_t bytes, void *stream, double *ms);
 
 /* Release the library's cached batched graphs (with their device memory) and autotuning

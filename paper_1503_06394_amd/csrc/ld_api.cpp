@@ -1261,18 +1261,24 @@ static int transpose_impl(const ld_csr* C, int64_t* row_ptr_t, int32_t* col_t, v
 
 static int copy_impl(void* dst, const void* src, size_t bytes, void* stream, double* ms) {
   if ((!dst || !src) && bytes) return fail(LD_EINVAL, "NULL pointer");
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u)
+    return fail(LD_EINVAL, "ld_copy needs 16-byte aligned pointers");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipEvent_t e0, e1;
-  LD_HIP(hipEventCreate(&e0));
-  LD_HIP(hipEventCreate(&e1));
-  LD_HIP(hipEventRecord(e0, s));
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  LD_HIP(hipEventCreate(&ev.e[0]));
+  LD_HIP(hipEventCreate(&ev.e[1]));
+  LD_HIP(hipEventRecord(ev.e[0], s));
   LD_HIP(launch_copy(dst, src, bytes, s));
-  LD_HIP(hipEventRecord(e1, s));
-  LD_HIP(hipEventSynchronize(e1));
+  LD_HIP(hipEventRecord(ev.e[1], s));
+  LD_HIP(hipEventSynchronize(ev.e[1]));
   float t = 0.f;
-  LD_HIP(hipEventElapsedTime(&t, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  LD_HIP(hipEventElapsedTime(&t, ev.e[0], ev.e[1]));
   if (ms) *ms = t;
   return LD_OK;
 }

@@ -918,25 +918,22 @@ __global__ void __launch_bounds__(256) seed_kernel(VT* out, const VT* W, const V
   }
 }
 
-// Streaming copy: each thread moves four 16-byte vectors per pass (all four loads issued
-// before the stores), non-temporal on both sides.
+// Streaming copy: each workgroup moves 1024 16-byte vectors per pass, four per thread at
+// a 4 KB spacing, all four loads issued before the stores, non-temporal on both sides.
 __global__ void __launch_bounds__(256) copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
   typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
   const u32x4* s = reinterpret_cast<const u32x4*>(src);
   u32x4* d = reinterpret_cast<u32x4*>(dst);
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  for (; t + 3 * stride < n16; t += 4 * stride) {
-    const u32x4 a = __builtin_nontemporal_load(s + t);
-    const u32x4 b = __builtin_nontemporal_load(s + t + stride);
-    const u32x4 c = __builtin_nontemporal_load(s + t + 2 * stride);
-    const u32x4 e = __builtin_nontemporal_load(s + t + 3 * stride);
-    __builtin_nontemporal_store(a, d + t);
-    __builtin_nontemporal_store(b, d + t + stride);
-    __builtin_nontemporal_store(c, d + t + 2 * stride);
-    __builtin_nontemporal_store(e, d + t + 3 * stride);
+  const int64_t stride = (int64_t)gridDim.x * 1024;
+  for (int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x; base < n16; base += stride) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u * 256 < n16) v[u] = __builtin_nontemporal_load(s + base + u * 256);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u * 256 < n16) __builtin_nontemporal_store(v[u], d + base + u * 256);
   }
-  for (; t < n16; t += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(s + t), d + t);
 }
 
 __global__ void __launch_bounds__(256) copy_tail_kernel(const uint8_t* src, uint8_t* dst, int64_t n) {

@@ -116,3 +116,18 @@ def test_row_longer_than_the_lds_slice(ld, oracle_lib, plain):
     og = oracle_lib.logdet_grad(B, a, b, 20, 16, seed=4)
     gg = g.cpu().numpy()
     assert np.max(np.abs(gg - og["grad"])) <= 1e-10 * np.max(np.abs(og["grad"]))
+
+
+@pytest.mark.parametrize("nbytes", [1, 15, 16, 4096 * 16 + 7, (1 << 20) + 3, 64 << 20])
+def test_copy_kernel_is_exact(ld, nbytes):
+    """The streaming copy used as the bandwidth reference copies every byte, tails included."""
+    import torch
+
+    say(f"copy {nbytes} bytes")
+    g = torch.Generator(device="cuda").manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes + 32,), dtype=torch.uint8, device="cuda", generator=g)
+    dst = torch.zeros(nbytes + 32, dtype=torch.uint8, device="cuda")
+    ld.ld_copy(dst[:nbytes], src[:nbytes])
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src[:nbytes])
+    assert int(dst[nbytes:].count_nonzero()) == 0
