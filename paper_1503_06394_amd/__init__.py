@@ -22,7 +22,7 @@ __all__ = [
     "ld_logdet_cheb_batched", "ld_gershgorin", "ld_probes", "ld_transpose", "ld_workspace_bytes", "ld_copy",
     "ld_version", "ld_clear_cache", "ld_spectral_estimate", "ld_laplacian_minor", "ld_log_spanning_trees",
     "ld_logdet_taylor", "ld_quadratic_form", "ld_gershgorin_batched",
-    "LogdetCheb", "logdet_cheb", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
+    "LogdetCheb", "logdet_cheb", "logdet", "as_device_csr", "LD_F64", "LD_F32", "LD_BF16", "LD_WBOUNDS",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblogdet_cheb.so")
@@ -425,6 +425,7 @@ class LogdetCheb(torch.autograd.Function):
         r = ld_logdet_cheb(B, a, b, n, M, seed)
         ctx.save_for_backward(values, row_ptr, col)
         ctx.cfg = (float(shift), a, b, n, M, seed)
+        ctx.std_err = r["std_err"]  # read back through the output's grad_fn by ``logdet``
         return torch.tensor(r["logdet"], dtype=torch.float64, device=values.device)
 
     @staticmethod
@@ -436,6 +437,41 @@ class LogdetCheb(torch.autograd.Function):
         r, grad = ld_logdet_cheb_grad(B, a, b, n, M, seed, float(g.item()), grad_dtype=gdt)
         gshift = torch.tensor(r["grad_shift"], dtype=torch.float64, device=values.device)
         return grad.to(values.dtype), gshift, None, None, None, None, None, None, None
+
+
+def as_device_csr(B, diag_shift: float = 0.0) -> DeviceCSR:
+    """A DeviceCSR as it is, or a square torch sparse CSR tensor on the GPU viewed as one (row
+    pointers as int64 and columns as int32, copied only if their dtype differs)."""
+    if isinstance(B, DeviceCSR):
+        return B
+    if torch.is_tensor(B) and B.layout == torch.sparse_csr:
+        if B.dim() != 2 or B.shape[0] != B.shape[1]:
+            raise LogdetChebError("the sparse CSR tensor must be square")
+        return DeviceCSR(B.crow_indices().to(torch.int64).contiguous(), B.col_indices().to(torch.int32).contiguous(),
+                         B.values().contiguous(), float(diag_shift))
+    raise LogdetChebError("expected a DeviceCSR or a torch sparse CSR tensor")
+
+
+def logdet(B, n: int, M: int, seed: int = 0, a: float | None = None, b: float | None = None,
+           shift: float = 0.0) -> tuple:
+    """Algorithm 1 on a DeviceCSR or a square torch sparse CSR tensor (plus shift * I): returns
+    (estimate as a float64 0-d tensor, standard error).  When the stored values require grad the
+    estimate carries the gradient with respect to them (the library's adjoint, a and b held
+    fixed); the bounds default to the Gershgorin interval."""
+    D = as_device_csr(B, shift)
+    if a is None or b is None:
+        ga, gb = ld_gershgorin(D)
+        a = ga if a is None else a
+        b = gb if b is None else b
+        if not a > 0:
+            raise LogdetChebError(f"Gershgorin lower bound {a} is not positive; pass a > 0 explicitly")
+    vals = B.values() if torch.is_tensor(B) else D.values
+    if vals.requires_grad:
+        st = torch.tensor(float(shift), dtype=torch.float64, device=vals.device)
+        out = LogdetCheb.apply(vals, st, D.row_ptr, D.col, float(a), float(b), int(n), int(M), int(seed))
+        return out, out.grad_fn.std_err
+    r = ld_logdet_cheb(D, a, b, n, M, seed)
+    return torch.tensor(r["logdet"], dtype=torch.float64, device=vals.device), r["std_err"]
 
 
 def logdet_cheb(B: DeviceCSR, n: int, M: int, seed: int = 0, a: float | None = None, b: float | None = None,

@@ -854,6 +854,7 @@ struct BatchEntry {
   double* mu_dev = nullptr;
   int kmax = 0;  // partial rows of the longest member
   bool pair = true;
+  uint64_t last_use = 0;
   std::vector<std::vector<double>> coeffs;
   ~BatchEntry() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -863,6 +864,8 @@ struct BatchEntry {
 };
 std::mutex g_batch_mu;
 std::map<std::vector<double>, std::unique_ptr<BatchEntry>> g_batch;
+uint64_t g_batch_clock = 0;               // use counter for least-recently-used eviction
+constexpr size_t kBatchCacheEntries = 8;  // captured graphs (with their device memory) kept
 
 double bits_of(const void* p) {
   uint64_t u = (uint64_t)(uintptr_t)p;
@@ -1573,6 +1576,12 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
   auto it = g_batch.find(key);
   BatchEntry* E;
   if (it == g_batch.end()) {
+    if (g_batch.size() >= kBatchCacheEntries) {  // every graph has finished: each call synchronises
+      auto lru = g_batch.begin();
+      for (auto jt = g_batch.begin(); jt != g_batch.end(); ++jt)
+        if (jt->second->last_use < lru->second->last_use) lru = jt;
+      g_batch.erase(lru);
+    }
     auto ent = std::make_unique<BatchEntry>();
     int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, pair, sh, *ent);
     if (rc) return rc;
@@ -1581,6 +1590,7 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
   } else {
     E = it->second.get();
   }
+  E->last_use = ++g_batch_clock;
   StepTimer tm;
   tm.on = opt && opt->timing;
   tm.s = s;

@@ -109,3 +109,22 @@ def test_batched_default_bounds_are_gershgorin(ld, oracle_lib):
     ab = [oracle_lib.gershgorin(B) for B in mats]
     r1 = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, 16, 3)
     assert [r["logdet"] for r in r0] == [r["logdet"] for r in r1]
+
+
+def test_graph_cache_evicts_least_recently_used(ld, oracle_lib):
+    """Eleven bound sets pass through the cache of eight captured graphs; every result, also of a
+    set whose graph was evicted and is captured again, matches the oracle."""
+    mats = _batch(3, "f64", seed0=77)
+    ns = [B.meta["n"] for B in mats]
+    D = [dev(B) for B in mats]
+    ab = [oracle_lib.gershgorin(B) for B in mats]
+    ld.ld_clear_cache()
+    for k in list(range(11)) + [0]:
+        a = [x[0] * (1.0 - 0.01 * k) for x in ab]
+        b = [x[1] * (1.0 + 0.01 * k) for x in ab]
+        say(f"batched cache round {k}")
+        res = ld.ld_logdet_cheb_batched(D, a, b, ns, 4, 2)
+        for i, B in enumerate(mats):
+            o = oracle_lib.logdet(B, a[i], b[i], ns[i], 4, seed=2 + i)
+            assert rel(res[i]["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10
+    ld.ld_clear_cache()
