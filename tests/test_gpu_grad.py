@@ -2,6 +2,8 @@
 mode, plus the torch.autograd wrapper and the GMRF chain rule through (tau, kappa)."""
 from __future__ import annotations
 
+import warnings
+
 import numpy as np
 import pytest
 
@@ -95,8 +97,8 @@ def test_autograd_function_and_gmrf_chain_rule(ld, oracle_lib):
     Lv = torch.tensor(L.val, dtype=torch.float64, device="cuda")
     rp = torch.tensor(L.row_ptr, device="cuda")
     col = torch.tensor(L.col, device="cuda")
-    a = float(tau * kappa ** 2)
-    b = float(tau * (kappa ** 2 + 12.0))
+    a = float((tau * kappa ** 2).detach())
+    b = float((tau * (kappa ** 2 + 12.0)).detach())
     say("autograd gmrf")
     vals = tau * Lv
     shift = tau * kappa ** 2
@@ -148,7 +150,9 @@ def test_torch_sparse_csr_front_end(ld, oracle_lib):
     crow = torch.tensor(B.row_ptr, device="cuda")
     col = torch.tensor(B.col.astype(np.int64), device="cuda")
     vals = torch.tensor(B.val, device="cuda", requires_grad=True)
-    T = torch.sparse_csr_tensor(crow, col, vals, size=(B.d, B.d))
+    with warnings.catch_warnings():  # torch marks sparse CSR support as beta
+        warnings.simplefilter("ignore", UserWarning)
+        T = torch.sparse_csr_tensor(crow, col, vals, size=(B.d, B.d))
     say("torch sparse CSR front end")
     est, se = ld.logdet(T, 20, 16, seed=6)
     o = oracle_lib.logdet(B, a, b, 20, 16, seed=6)
