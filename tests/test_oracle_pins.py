@@ -324,6 +324,28 @@ def test_theorem1_guarantee(oracle_lib):
         assert abs(exact - g) <= eps * abs(exact)
 
 
+def test_theorem2_guarantee(oracle_lib):
+    """Theorem 2 as an inequality: C with singular values in [1, sqrt 2] (kappa = sqrt 2), m and n at
+    the theorem's requirement for eps = 0.2, zeta = 0.2; |log|det C| - Gamma| <= eps d in every one of
+    3 runs (probability >= 1 - zeta each)."""
+    rng = np.random.default_rng(8)
+    d = 20
+    U, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    V, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    sv = rng.uniform(1.0, math.sqrt(2.0), size=d)
+    Cd = (U * sv) @ V.T
+    rows, cols = np.nonzero(np.ones((d, d)))
+    C = synth.CSR(d, np.arange(0, d * d + 1, d, dtype=np.int64), cols.astype(np.int32), Cd[rows, cols])
+    eps, zeta = 0.2, 0.2
+    m_req, n_req = oracle_lib.thm2_params(eps, math.sqrt(2.0), zeta)
+    m, n = int(math.ceil(m_req)), int(math.ceil(n_req))
+    exact = float(np.log(sv).sum())
+    assert abs(exact - np.linalg.slogdet(Cd)[1]) < 1e-12
+    for seed in range(3):
+        g = oracle_lib.logabsdet(C, 1.0, math.sqrt(2.0), n, m, seed=seed)["gamma"]
+        assert abs(exact - g) <= eps * d
+
+
 def test_theorem1_degree_example():
     """Section 3.1 quotes n = 14 for delta = 0.1, eps = 0.01; the printed formula gives 25.95,
     i.e. n = 26 (a discrepancy in the paper, recorded rather than enforced)."""

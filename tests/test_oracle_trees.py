@@ -106,3 +106,17 @@ def test_tree_estimate_statistical(oracle_lib):
     L = r["minor"]
     exact = np.linalg.slogdet(_dense(L))[1]
     assert abs(r["gamma"] - exact) < 5 * r["std_err"] + 1e-6 * exact
+
+
+def test_spanning_tree_corollary_guarantee(oracle_lib):
+    """The spanning-tree corollary as an inequality: for the wheel W_20 (Delta_max = Delta_avg = 3),
+    eps = 0.5 < 2/(Delta_avg - 1) and zeta = 0.2, Algorithm 2 with m and n at the corollary's
+    requirement (Theorem 2's M and N at eps (Delta_avg - 1)/4 and kappa = 2 Delta_max - 1) lands within
+    eps log tau of log tau in every one of 3 runs."""
+    eps, zeta = 0.5, 0.2
+    m_req, n_req = oracle_lib.thm2_params(eps * (3 - 1) / 4, 2 * 3 - 1, zeta)
+    m, n = int(math.ceil(m_req)), int(math.ceil(n_req))
+    log_tau = math.log(_lucas(40) - 2)
+    for seed in range(3):
+        r = oracle_lib.log_spanning_trees(synth.wheel_graph(20), 0, n, m, seed=seed, method=1)
+        assert abs(r["gamma"] - log_tau) <= eps * log_tau
