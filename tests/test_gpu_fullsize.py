@@ -156,3 +156,54 @@ def test_gmrf_5000_likelihood(ld, oracle_lib):
     Jh = synth.gmrf_grid_precision(N, -0.22, "f32")
     o = oracle_lib.logdet(Jh, 0.12, 1.88, 40, 1, seed=2, ids=np.array([0]))
     assert rel(r["s"][0], o["s"][0], FLOOR * Jh.d) <= TOL32
+
+
+@pytest.mark.timeout(900)
+def test_random_1m_gradient_bench_configuration(ld, oracle_lib):
+    """The benchmark's fwd+grad call (d = 1e6 random SPD, FP32, M = 64, n = 50, Gershgorin bounds,
+    FP32 gradient) against the oracle's gradient averaged over the same 64 probes, computed in CPU
+    worker processes: 20000 sampled entries (normwise, 1e-4) and d Gamma / d shift (1e-4)."""
+    import os
+
+    import torch
+
+    from tests._oracle_pool import mean_gradient
+
+    spec = ("random_sparse_spd", 1_000_000, 5, 2, 1.0, "f32")
+    B = synth.random_sparse_spd(*spec[1:])
+    D = dev(B)
+    a, b = ld.ld_gershgorin(D)
+    say("full size random1m gradient: GPU")
+    r, g = ld.ld_logdet_cheb_grad(D, a, b, 50, 64, 2, 1.0, grad_dtype=torch.float32)
+    idx = np.sort(np.random.default_rng(9).choice(B.nnz, 20_000, replace=False))
+    gg = g.double().cpu().numpy()[idx]
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    say(f"full size random1m gradient: oracle, 64 probes over {workers} worker processes")
+    og, ogs = mean_gradient(spec, a, b, 50, 64, 2, idx, workers)
+    assert np.max(np.abs(gg - og)) <= TOL32 * np.max(np.abs(og))
+    assert rel(r["grad_shift"], ogs) <= TOL32
+
+
+@pytest.mark.timeout(900)
+def test_gmrf_128_gradient_bench_configuration(ld, oracle_lib):
+    """The benchmark's gmrf128 fwd+grad call (128^3 GMRF, FP32, M = 32, n = 60, shift 0.09) against the
+    oracle's gradient averaged over the same 32 probes in CPU worker processes: 20000 sampled
+    entries (normwise, 1e-4) and d Gamma / d shift (1e-4)."""
+    import os
+
+    import torch
+
+    from tests._oracle_pool import mean_gradient
+
+    spec = ("grid_laplacian_3d", 128, "f32")
+    B = synth.grid_laplacian_3d(128, "f32")
+    shift, a, b, n, M, seed = 0.09, 0.09, 12.09, 60, 32, 3
+    say("full size gmrf128 gradient: GPU")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a, b, n, M, seed, 1.0, grad_dtype=torch.float32)
+    idx = np.sort(np.random.default_rng(10).choice(B.nnz, 20_000, replace=False))
+    gg = g.double().cpu().numpy()[idx]
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    say(f"full size gmrf128 gradient: oracle, {M} probes over {workers} worker processes")
+    og, ogs = mean_gradient(spec, a, b, n, M, seed, idx, workers, shift=shift)
+    assert np.max(np.abs(gg - og)) <= TOL32 * np.max(np.abs(og))
+    assert rel(r["grad_shift"], ogs) <= TOL32
