@@ -973,6 +973,7 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
   LD_HIP(hipMemcpy(d_tb, tile_begin.data(), tile_begin.size() * 8, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(d_n, rows_i.data(), (size_t)count * 4, hipMemcpyHostToDevice));
 
+  if (rmax == 0) return LD_OK;  // every member has degree 0: nothing to run, no graph
   // capture every step and the reduction on a private stream
   hipStream_t cs;
   LD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1595,11 +1596,11 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
   tm.on = opt && opt->timing;
   tm.s = s;
   LD_HIP(tm.mark(T_OTHER));
-  LD_HIP(hipGraphLaunch(E->exec, s));
+  if (E->exec) LD_HIP(hipGraphLaunch(E->exec, s));
   LD_HIP(tm.mark(T_STEP));
   const int kmax = E->kmax;
   std::vector<double> mu_all((size_t)count * M * (kmax + 1));
-  LD_HIP(hipMemcpyAsync(mu_all.data(), E->mu_dev, mu_all.size() * 8, hipMemcpyDeviceToHost, s));
+  if (kmax > 0) LD_HIP(hipMemcpyAsync(mu_all.data(), E->mu_dev, mu_all.size() * 8, hipMemcpyDeviceToHost, s));
   LD_HIP(hipStreamSynchronize(s));
   int status = LD_OK;
   for (int i = 0; i < count; ++i) {

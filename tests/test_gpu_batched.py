@@ -128,3 +128,29 @@ def test_graph_cache_evicts_least_recently_used(ld, oracle_lib):
             o = oracle_lib.logdet(B, a[i], b[i], ns[i], 4, seed=2 + i)
             assert rel(res[i]["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10
     ld.ld_clear_cache()
+
+
+@pytest.mark.parametrize("M", [1, 100, 300])
+def test_batched_probe_counts(ld, oracle_lib, M):
+    """Probe blocks of one lane, of one wide tile and of several probe tiles per pass (M = 300)."""
+    mats = _batch(4, "f32", d_max=3000, seed0=640)
+    ab = [oracle_lib.gershgorin(B) for B in mats]
+    ns = [B.meta["n"] for B in mats]
+    D = [dev(B) for B in mats]
+    say(f"batched M={M}")
+    res = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, M, 9)
+    for i, B in enumerate(mats):
+        o = oracle_lib.logdet(B, ab[i][0], ab[i][1], ns[i], M, seed=9 + i)
+        assert rel(res[i]["logdet"], o["gamma"], FLOOR * B.d) <= 1e-4, i
+
+
+@pytest.mark.parametrize("ns", [[0], [0, 1, 2, 5], [1, 1], [7]])
+def test_batched_low_degrees_and_single_member(ld, oracle_lib, ns):
+    mats = [synth.random_sparse_spd(200 + 37 * i, 3, 50 + i, 1.0, "f64") for i in range(len(ns))]
+    ab = [oracle_lib.gershgorin(B) for B in mats]
+    D = [dev(B) for B in mats]
+    say(f"batched degrees {ns}")
+    res = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, 8, 5)
+    for i, B in enumerate(mats):
+        o = oracle_lib.logdet(B, ab[i][0], ab[i][1], ns[i], 8, seed=5 + i)
+        assert rel(res[i]["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10, (i, ns[i])
