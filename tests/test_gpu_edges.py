@@ -131,3 +131,15 @@ def test_copy_kernel_is_exact(ld, nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst[:nbytes], src[:nbytes])
     assert int(dst[nbytes:].count_nonzero()) == 0
+
+
+def test_degree_zero_gradient_is_zero(ld, oracle_lib):
+    """At n = 0 the estimate d log((a+b)/2) does not depend on B: zero gradient, zero d/dshift."""
+    B = synth.random_sparse_spd(500, 3, 23, 1.0, "f64")
+    a, b = oracle_lib.gershgorin(B)
+    say("gradient at n = 0")
+    r, g = ld.ld_logdet_cheb_grad(dev(B), a, b, 0, 8, 1)
+    assert r["logdet"] == pytest.approx(B.d * math.log((a + b) / 2), rel=1e-15)
+    assert float(g.abs().max()) == 0.0 and r["grad_shift"] == 0.0
+    o = oracle_lib.logdet_grad(B, a, b, 0, 8, seed=1)
+    assert np.all(o["grad"] == 0.0) and o["grad_shift"] == 0.0
