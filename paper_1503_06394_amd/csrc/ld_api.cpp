@@ -1562,7 +1562,8 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
     tot_d += Bs[i].rows;
     tot_nnz += Bs[i].nnz;
   }
-  const int tile = (opt && opt->tile > 0) ? opt->tile : staged_tile_cap(sh, tot_d, tot_nnz);
+  // as for one matrix: the LDS slice capacity, lowered until the whole batch spreads over >= 1024 tiles
+  const int tile = (opt && opt->tile > 0) ? opt->tile : with_tile(sh, tot_d, tot_nnz, 0).tile_rows;
   sh.tile_rows = (tile + rpi - 1) / rpi * rpi;
 
   const bool pair = use_pairs(opt);
