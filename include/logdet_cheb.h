@@ -81,7 +81,8 @@ typedef struct {
 } ld_result;
 
 typedef struct {
-    void *workspace;          /* device scratch or NULL (then the library allocates on `stream`) */
+    void *workspace;          /* device scratch, or NULL: then the library takes one of its own
+                                 device buffers, kept for reuse until ld_clear_cache */
     size_t workspace_bytes;
     int32_t vec_f64;          /* recurrence vectors: 0 = FP64 for FP64 values, else FP32;
                                  1 = FP64; 2 = FP32 */
@@ -220,8 +221,9 @@ size_t ld_workspace_bytes(const ld_csr *B, int n, int M, int mode, int vec_f64);
  * 16-byte aligned (LD_EINVAL otherwise); any byte count is copied exactly. */
 int ld_copy(void *dst, const void *src, size_t bytes, void *stream, double *ms);
 
-/* Release the library's cached batched graphs (with their device memory) and autotuning
- * results.  Not safe to call while another thread is inside the library. */
+/* Release the library's cached batched graphs (with their device memory), its idle internal
+ * workspaces and its autotuning results.  Not safe to call while another thread is inside the
+ * library. */
 int ld_clear_cache(void);
 
 /* Message for the last non-zero status returned on this thread. */

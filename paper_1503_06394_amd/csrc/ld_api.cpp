@@ -84,15 +84,43 @@ struct Carve {
   }
 };
 
-// Workspace: the caller's, or a stream-ordered allocation released on scope exit.
+// Device buffers the library reuses across calls that bring no workspace of their own: per device,
+// at most kPoolKeep idle buffers are kept (until ld_clear_cache); a call takes the smallest idle one
+// that is large enough, or allocates a new one.  Nested and concurrent calls take different buffers.
+struct PoolBuf {
+  void* ptr;
+  size_t bytes;
+};
+std::mutex g_pool_mu;
+std::map<int, std::vector<PoolBuf>> g_pool;  // device -> idle buffers
+constexpr size_t kPoolKeep = 4;
+
+void pool_release_all() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (auto& kv : g_pool)
+    for (auto& b : kv.second) (void)hipFree(b.ptr);
+  g_pool.clear();
+}
+
+// Workspace: the caller's, or a pooled buffer returned to the pool on scope exit (after the stream
+// it served has drained, so no later call can overlap work still reading it).
 struct Workspace {
   void* ptr = nullptr;
-  bool owned = false;
+  size_t bytes = 0;
+  int device = -1;
+  bool pooled = false;
   hipStream_t stream = nullptr;
   ~Workspace() {
-    if (owned && ptr) {
-      (void)hipFreeAsync(ptr, stream);
-      (void)hipStreamSynchronize(stream);
+    if (!pooled) return;
+    (void)hipStreamSynchronize(stream);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto& idle = g_pool[device];
+    idle.push_back(PoolBuf{ptr, bytes});
+    if (idle.size() > kPoolKeep) {  // drop the smallest
+      auto it = std::min_element(idle.begin(), idle.end(),
+                                 [](const PoolBuf& x, const PoolBuf& y) { return x.bytes < y.bytes; });
+      (void)hipFree(it->ptr);
+      idle.erase(it);
     }
   }
 };
@@ -107,9 +135,32 @@ int get_workspace(const ld_opts* opt, size_t need, hipStream_t s, Workspace& ws)
     return LD_OK;
   }
   if (need == 0) return LD_OK;
-  hipError_t e = hipMallocAsync(&ws.ptr, need, s);
-  if (e != hipSuccess) return fail(LD_ENOMEM, "hipMallocAsync(%zu): %s", need, hipGetErrorString(e));
-  ws.owned = true;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto& idle = g_pool[dev];
+    auto best = idle.end();
+    for (auto it = idle.begin(); it != idle.end(); ++it)
+      if (it->bytes >= need && (best == idle.end() || it->bytes < best->bytes)) best = it;
+    if (best != idle.end()) {
+      ws.ptr = best->ptr;
+      ws.bytes = best->bytes;
+      idle.erase(best);
+    }
+  }
+  if (!ws.ptr) {
+    e = hipMalloc(&ws.ptr, need);
+    if (e != hipSuccess) {
+      pool_release_all();  // idle buffers may be what stands in the way
+      e = hipMalloc(&ws.ptr, need);
+    }
+    if (e != hipSuccess) return fail(LD_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+    ws.bytes = need;
+  }
+  ws.device = dev;
+  ws.pooled = true;
   return LD_OK;
 }
 
@@ -1822,6 +1873,7 @@ static int clear_cache_impl(void) {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     g_batch.clear();
   }
+  pool_release_all();
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.clear();
   return LD_OK;

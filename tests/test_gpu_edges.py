@@ -143,3 +143,36 @@ def test_degree_zero_gradient_is_zero(ld, oracle_lib):
     assert float(g.abs().max()) == 0.0 and r["grad_shift"] == 0.0
     o = oracle_lib.logdet_grad(B, a, b, 0, 8, seed=1)
     assert np.all(o["grad"] == 0.0) and o["grad_shift"] == 0.0
+
+
+def test_internal_workspaces_reused_across_sizes_threads_and_clears(ld):
+    """Calls without a workspace of their own draw on the library's pooled buffers: results stay
+    bit-identical across alternating sizes, concurrent calls from two threads on two streams, and
+    ld_clear_cache."""
+    import threading
+
+    import torch
+
+    mats = [synth.random_sparse_spd(d, 3, 30 + i, 1.0, "f32") for i, d in enumerate([700, 30_000, 5_000])]
+    D = [dev(B) for B in mats]
+    ab = [ld.ld_gershgorin(x) for x in D]
+    say("pooled workspaces: reference results")
+    ref = [ld.ld_logdet_cheb(D[i], *ab[i], 20, 16, 4)["logdet"] for i in range(3)]
+    for _ in range(3):
+        for i in (2, 0, 1):
+            assert ld.ld_logdet_cheb(D[i], *ab[i], 20, 16, 4)["logdet"] == ref[i]
+    ld.ld_clear_cache()
+    assert [ld.ld_logdet_cheb(D[i], *ab[i], 20, 16, 4)["logdet"] for i in range(3)] == ref
+    say("pooled workspaces: two threads")
+    out = {}
+
+    def work(tag, order, stream):
+        with torch.cuda.stream(stream):
+            out[tag] = [ld.ld_logdet_cheb(D[i], *ab[i], 20, 16, 4, stream=stream)["logdet"] for i in order * 4]
+
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    t1 = threading.Thread(target=work, args=("a", [0, 1, 2], s1))
+    t2 = threading.Thread(target=work, args=("b", [2, 1, 0], s2))
+    t1.start(); t2.start(); t1.join(); t2.join()
+    assert out["a"] == [ref[i] for i in [0, 1, 2] * 4]
+    assert out["b"] == [ref[i] for i in [2, 1, 0] * 4]
