@@ -8,14 +8,16 @@
 //  * Vector blocks are d x M row-major (probe index contiguous): the LPR lanes of a row
 //    group read a whole row of W_k (M * 4 bytes) as VPL-wide vector loads, so every
 //    gathered row is one fully coalesced segment.
-//  * A row's column indices and values are loaded once, cooperatively, by the LPR lanes
-//    of its group and broadcast with cross-lane shuffles.
+//  * Each workgroup stages its row tile's CSR slice (row offsets, columns, values) in LDS
+//    once, so a row pass waits on a single global round trip: its gathers.
 //  * The diagonal term of 2 At = alpha B + beta I is folded into the coefficient of the
 //    stored diagonal entry, so W_k[r] is not read twice.
 //  * Probes are never stored: v_j[r] is regenerated from a SplitMix64 counter hash.
-//  * The probe moments v_j^T W_{k+1} are fused into the step's epilogue: FP64 per-lane
-//    sums, a wave butterfly, a fixed-order sum over waves and one partial per tile, later
-//    reduced in a fixed order (deterministic, no floating-point atomics).
+//  * Moments are fused into the step's epilogue: v_j^T W_{k+1}, or W_k^T W_{k+1} and
+//    W_{k+1}^T W_{k+1} for the Chebyshev product identities (half the products).  Lanes
+//    sum their rows in the vector type; from the wave butterfly on everything is FP64: a
+//    fixed-order sum over waves, one partial per tile, a fixed-order reduction over tiles
+//    (deterministic, no floating-point atomics).
 //  * One workgroup per row tile; workgroup ids are remapped so that each of the eight
 //    XCDs walks a contiguous range of tiles in order, which keeps the W_k rows that
 //    banded patterns reuse (neighbours at +-N, +-N^2) inside that XCD's L2.
