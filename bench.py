@@ -169,7 +169,8 @@ def main() -> None:
     ap.add_argument("--workload", default="random1m",
                     choices=["random1m", "grid32", "gmrf128", "grid4096", "batch256", "nonsingular1m", "gmrf5000"])
     ap.add_argument("--compare-perprobe", action="store_true",
-                    help="also time the plain per-probe FP64 form (one probe per call, FP64 values and vectors)")
+                    help="also time the plain per-probe forms (one probe per call, one product per degree, "
+                         "FP64 and FP32) and the block form with the plain recurrence")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-only", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -325,32 +326,53 @@ def main() -> None:
     if copy_gbps is not None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
     if args.compare_perprobe:
-        out["perprobe_fp64"] = perprobe_fp64([B], [a], [b], [n], M, W["seed"], W["shift"])
+        log("plain per-probe forms and the plain block form")
+        out["perprobe_fp64"] = perprobe([B], [a], [b], [n], M, W["seed"], W["shift"], "f64")
+        out["perprobe_fp32"] = perprobe([B], [a], [b], [n], M, W["seed"], W["shift"], "f32")
+        out["block_plain_forward_ms"] = block_plain_ms(D, a, b, n, M, W["seed"])
     print(json.dumps(out), flush=True)
 
 
-def perprobe_fp64(mats, a, b, ns, M, seed, shift=0.0) -> dict:
-    """The plain per-probe FP64 form: every probe is its own call with M = 1, FP64 values and
-    vectors (one sparse matrix-vector product per degree).  Probe j of matrix i uses seed
-    (seed + i) * 100003 + j, so the estimator is statistically the same as the block form."""
+def perprobe(mats, a, b, ns, M, seed, shift=0.0, dtype="f64") -> dict:
+    """The plain per-probe form as Algorithm 1 states it: every probe is its own call with M = 1 and
+    one sparse matrix-vector product per degree (plain recurrence), values and vectors in `dtype`.
+    Probe j of matrix i uses seed (seed + i) * 100003 + j, so the estimator is statistically the
+    same as the block form."""
     import numpy as np
     import torch
 
     import paper_1503_06394_amd as ld
 
-    devs = [ld.DeviceCSR.from_host(B, device="cuda:0", dtype=torch.float64, diag_shift=shift) for B in mats]
-    ld.ld_logdet_cheb(devs[0], a[0], b[0], ns[0], 1, 0)  # warm
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    devs = [ld.DeviceCSR.from_host(B, device="cuda:0", dtype=tdt, diag_shift=shift) for B in mats]
+    ld.ld_logdet_cheb(devs[0], a[0], b[0], ns[0], 1, 0, plain=True)  # warm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     est = []
     for i, D in enumerate(devs):
-        s = [ld.ld_logdet_cheb(D, a[i], b[i], ns[i], 1, (seed + i) * 100003 + j)["logdet"] for j in range(M)]
+        s = [ld.ld_logdet_cheb(D, a[i], b[i], ns[i], 1, (seed + i) * 100003 + j, plain=True)["logdet"]
+             for j in range(M)]
         est.append((float(np.mean(s)), float(np.std(s, ddof=1) / np.sqrt(M))))
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
     work = sum(M * ns[i] * mats[i].nnz for i in range(len(mats)))
     return {"ms": round(ms, 3), "matvec_nnz_per_s": work / (ms / 1e3),
             "std_err_rel_first": abs(est[0][1] / est[0][0]), "logdet_first": est[0][0]}
+
+
+def block_plain_ms(D, a, b, n, M, seed, reps=3) -> float:
+    """The block form with the plain recurrence (n products instead of ceil(n/2))."""
+    import torch
+
+    import paper_1503_06394_amd as ld
+
+    ld.ld_logdet_cheb(D, a, b, n, M, seed, plain=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ld.ld_logdet_cheb(D, a, b, n, M, seed, plain=True)
+    torch.cuda.synchronize()
+    return round((time.perf_counter() - t0) * 1e3 / reps, 3)
 
 
 def bench_batch(args, W, copy_gbps) -> None:
@@ -414,7 +436,7 @@ def bench_batch(args, W, copy_gbps) -> None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
     if args.compare_perprobe:
         log("plain per-probe FP64 form")
-        out["perprobe_fp64"] = perprobe_fp64(mats, a, b, ns, M, seed)
+        out["perprobe_fp64"] = perprobe(mats, a, b, ns, M, seed, 0.0, "f64")
     print(json.dumps(out), flush=True)
 
 
