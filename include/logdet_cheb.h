@@ -152,8 +152,10 @@ int ld_logdet_cheb_batched(int count, const ld_csr *Bs, const double *a, const d
                            const int *n, int M, uint64_t seed, const ld_opts *opt, void *stream,
                            ld_result *outs);
 
-/* Gershgorin interval of B + diag_shift I (FP64):
- * a = min_i (B_ii + shift - sum_{j != i} |B_ij|), b = max_i (B_ii + shift + sum_{j != i} |B_ij|). */
+/* Gershgorin interval of B + diag_shift I (FP64), an interval [a, b] holding the spectrum, the
+ * input Algorithm 1 needs (Section 3.2 discusses how such bounds are obtained):
+ * a = min_i (B_ii + shift - sum_{j != i} |B_ij|), b = max_i (B_ii + shift + sum_{j != i} |B_ij|).
+ * a and b are host doubles; LD_EINVAL for an empty matrix. */
 int ld_gershgorin(const ld_csr *B, double *a, double *b, void *stream);
 
 /* Gershgorin intervals of `count` matrices (host array of descriptors of device data, one
@@ -192,8 +194,8 @@ int ld_laplacian_minor(const ld_csr *adj, int64_t hub, int64_t *row_ptr_out, int
 /* log tau(G) for a graph whose vertex `hub` is adjacent to every other vertex (Section 3.3):
  * method 1 runs Algorithm 2 with C = L(hub) and singular values in [1, 2 Delta_max - 1], as the
  * spanning-tree corollary states; method 0 runs Algorithm 1 on the symmetric positive definite
- * L(hub) with spectrum in [1, 2 Delta_max - 1].  The minor is built on the device in a
- * stream-ordered allocation of its own (opt->workspace only serves the estimator); values and
+ * L(hub) with spectrum in [1, 2 Delta_max - 1].  The minor is built on the device in one of the
+ * library's internal buffers (opt->workspace only serves the estimator); values and
  * vectors are FP64 when opt->vec_f64 = 1, else FP32.  out->logdet is the estimate of log tau(G).
  * When Delta_max = 1 the minor is the identity and 0 is returned exactly (probe_out zeroed,
  * moments_out untouched).  Errors as for ld_laplacian_minor and ld_logdet_cheb. */
@@ -205,11 +207,14 @@ int ld_log_spanning_trees(const ld_csr *adj, int64_t hub, int n, int M, uint64_t
  * product into library scratch and a fixed-order FP64 dot; *out is a host double. */
 int ld_quadratic_form(const ld_csr *B, const double *x, void *stream, double *out);
 
-/* Write the probe block: out[r * M + j] = v_j[r] (int8, +1/-1), r < rows, j < M. */
+/* The Rademacher probes of Hutchinson's estimator (Section 2.2) as every kernel regenerates them:
+ * out[r * M + j] = v_j[r] (int8, +1/-1) for r < rows, j < M, out a caller-owned device array of
+ * rows * M bytes.  For tests and inspection; the estimators never store probes. */
 int ld_probes(uint64_t seed, int M, int64_t rows, int8_t *out, void *stream);
 
-/* C^T of a square CSR matrix into caller buffers (row_ptr_t: rows+1, col_t and val_t:
- * nnz, same dtype); rows of the result have ascending column indices. */
+/* C^T of a square CSR matrix (Algorithm 2 applies C^T (C w), Section 3.2) into caller-owned
+ * device buffers: row_ptr_t (rows + 1), col_t and val_t (nnz, C's dtype).  Rows of the result have
+ * ascending column indices; the result is deterministic. */
 int ld_transpose(const ld_csr *C, int64_t *row_ptr_t, int32_t *col_t, void *val_t, void *stream);
 
 /* Device bytes the entry point `mode` (0 logdet, 1 logabsdet, 2 grad, 3 taylor) needs as
