@@ -120,3 +120,26 @@ def test_spanning_tree_corollary_guarantee(oracle_lib):
     for seed in range(3):
         r = oracle_lib.log_spanning_trees(synth.wheel_graph(20), 0, n, m, seed=seed, method=1)
         assert abs(r["gamma"] - log_tau) <= eps * log_tau
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_tree_estimate_uses_the_corollary_interval(oracle_lib, method):
+    """At low degree the estimate depends on the interval: averaged over all sign patterns it must
+    equal the trace of the degree-3 first-kind Chebyshev interpolant of log on [1, 2 Delta_max - 1]
+    (Algorithm 1 on L(hub)), or half that of log on [1, (2 Delta_max - 1)^2] over L(hub)^2
+    (Algorithm 2), built here with numpy from the minor's eigenvalues."""
+    from numpy.polynomial import chebyshev as C
+
+    G = synth.wheel_graph(6)
+    L, dmax = oracle_lib.laplacian_minor(G, 0)
+    lam = np.linalg.eigvalsh(_dense(L))
+    hi = 2.0 * dmax - 1.0
+    if method == 0:
+        a, b, x = 1.0, hi, lam
+    else:
+        a, b, x = 1.0, hi * hi, lam * lam
+    coef = C.chebinterpolate(lambda t: np.log(((b - a) * t + (a + b)) / 2.0), 3)
+    want = float(C.chebval((2.0 * x - (a + b)) / (b - a), coef).sum()) * (1.0 if method == 0 else 0.5)
+    V = np.array(list(itertools.product([1.0, -1.0], repeat=L.d)))
+    r = oracle_lib.log_spanning_trees(G, 0, 3, V.shape[0], V=V, method=method)
+    assert abs(r["gamma"] - want) < 1e-11 * max(1.0, abs(want))
