@@ -316,6 +316,7 @@ bool sym_enabled() {
   return !(e && e[0] == '0');
 }
 
+// LD_AUTOTUNE=0 keeps the default tile height and probe layout (no timing of candidates).
 bool autotune_enabled() {
   const char* e = std::getenv("LD_AUTOTUNE");
   return !(e && e[0] == '0');
