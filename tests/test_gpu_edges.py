@@ -176,3 +176,17 @@ def test_internal_workspaces_reused_across_sizes_threads_and_clears(ld):
     t1.start(); t2.start(); t1.join(); t2.join()
     assert out["a"] == [ref[i] for i in [0, 1, 2] * 4]
     assert out["b"] == [ref[i] for i in [2, 1, 0] * 4]
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_high_degree_fp32(ld, oracle_lib, plain):
+    """n = 400 on the FP32 path: the product identities form mu_2k = 2 |W_k|^2 - d, a difference of
+    O(d) terms; parity with the oracle must still hold at the FP32 tolerance."""
+    B = synth.random_sparse_spd(20_000, 4, 27, 1.0, "f32")
+    a, b = oracle_lib.gershgorin(B)
+    say(f"n = 400 FP32 plain={plain}")
+    r = ld.ld_logdet_cheb(dev(B), a, b, 400, 16, 8, plain=plain, want_probes=True)
+    o = oracle_lib.logdet(B, a, b, 400, 16, seed=8)
+    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-4
+    for j in range(16):
+        assert rel(r["s"][j], o["s"][j], FLOOR * B.d) <= 1e-4, j
