@@ -468,6 +468,16 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
     VT acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
+    // the row's streamed seed operands, issued ahead of the gathers so their latency overlaps
+    VT xm[VPL], xp[VPL], x2[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) xm[i] = xp[i] = x2[i] = VT(0);
+    if constexpr (SPMM) {
+      if (has && A.Wm) vload_nt<VT, VPL>(static_cast<const VT*>(A.Wm) + roff, xm);
+      if (has && A.Wp) vload_nt<VT, VPL>(static_cast<const VT*>(A.Wp) + roff, xp);
+      if constexpr (Y2)
+        if (has) vload_nt<VT, VPL>(Y2p + roff, x2);
+    }
 
     for (int64_t t = s; t < e; t += kUnroll) {
       int cc[kUnroll];
@@ -563,24 +573,18 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(AdjDesc A, int M, int l
           acc[i] = fma(cv, vv[i], o);
         }
         if (A.Wm) {
-          VT x[VPL];
-          vload_nt<VT, VPL>(static_cast<const VT*>(A.Wm) + roff, x);
           const VT c = (VT)A.cwm;
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(c, x[i], acc[i]);
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(c, xm[i], acc[i]);
         }
         if (A.Wp) {
-          VT x[VPL];
-          vload_nt<VT, VPL>(static_cast<const VT*>(A.Wp) + roff, x);
           const VT c = (VT)A.cwp;
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(c, x[i], acc[i]);
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(c, xp[i], acc[i]);
         }
         if constexpr (Y2) {
-          VT y2v[VPL];
-          vload_nt<VT, VPL>(Y2p + roff, y2v);
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, y2v[i], acc[i]);
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, x2[i], acc[i]);
         }
         if (pact) vstore_nt<VT, VPL>(out + roff, acc);
       }
