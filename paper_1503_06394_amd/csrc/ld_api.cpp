@@ -522,7 +522,22 @@ int64_t max_tiles(const ld_csr* B, int vec_f64, int M, const ld_opts* opt) {
   return (B->rows + min_rows - 1) / min_rows;
 }
 
+// Probe block the forward actually runs.  Below 16 probes, a row of M probes that is not a whole
+// number of 64-byte segments is widened to the lane group the kernel gives it anyway (LPR lanes x
+// VPL probes): every lane then issues an aligned vector load and no gathered row straddles a
+// segment boundary, which costs less than the extra probes (10 probes take longer per step than
+// 16).  Probes are indexed, so the first M are the same probes; the rest are dropped.
+int padded_probes(int M, int vec_f64, const ld_opts* opt) {
+  if (opt && opt->probe_tile > 0) return M;
+  const int vb = vec_f64 ? 8 : 4;
+  if (M >= 16 || (M * vb) % 64 == 0) return M;
+  const Shape sh = base_shape(vec_f64, M);
+  const int width = (1 << sh.lpr_log2) * sh.vpl;
+  return (sh.probe_tiles == 1 && width <= 16) ? width : M;
+}
+
 size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, const ld_opts* opt) {
+  M = padded_probes(M, vec_f64, opt);
   const size_t vb = vec_f64 ? 8 : 4;
   const int64_t tiles = max_tiles(B, vec_f64, M, opt);
   Carve c;
@@ -545,15 +560,16 @@ size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, const 
 }
 
 // Shared body of ld_logdet_cheb and ld_logabsdet_cheb.
-int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double b, int n, int M, uint64_t seed,
+int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double b, int n, int M_out, uint64_t seed,
                 const ld_opts* opt, hipStream_t s, ld_result* out) {
   const int valt = valt_of(B->dtype);
   const int vec_f64 = vec_f64_of(opt, valt);
   const int64_t d = B->rows;
+  const int M = padded_probes(M_out, vec_f64, opt);  // probes run; the estimate uses the first M_out
   const bool pair = use_pairs(opt);
   const int nsteps = steps_for(n, pair);
   const int nrows = partial_rows(n, pair);
-  const size_t need = fwd_workspace(B, n, M, vec_f64, ns, opt);
+  const size_t need = fwd_workspace(B, n, M_out, vec_f64, ns, opt);
   Workspace ws;
   int rc = get_workspace(opt, need, s, ws);
   if (rc) return rc;
@@ -695,9 +711,9 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
     LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * nrows * 8, hipMemcpyDeviceToHost, s));
   }
   LD_HIP(hipStreamSynchronize(s));
-  std::vector<double> mu((size_t)M * (n + 1), 0.0);
-  assemble_moments(red, nrows, pair, n, M, d, mu);
-  combine(mu, c, n, M, d, ns ? 0.5 : 1.0, out, opt);
+  std::vector<double> mu((size_t)M_out * (n + 1), 0.0);
+  assemble_moments(red, nrows, pair, n, M_out, d, mu);  // rows of red are per probe: the first M_out
+  combine(mu, c, n, M_out, d, ns ? 0.5 : 1.0, out, opt);
   out->poly_bound = lemma_bound(a, b, n, d) * (ns ? 0.5 : 1.0);
   out->grad_shift = 0.0;
   tm.report(out);
