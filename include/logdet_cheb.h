@@ -81,8 +81,9 @@ typedef struct {
 } ld_result;
 
 typedef struct {
-    void *workspace;          /* device scratch, or NULL: then the library takes one of its own
-                                 device buffers, kept for reuse until ld_clear_cache */
+    void *workspace;          /* device scratch, 256-byte aligned (LD_EINVAL otherwise), or NULL:
+                                 then the library takes one of its own device buffers, kept for
+                                 reuse until ld_clear_cache */
     size_t workspace_bytes;
     int32_t vec_f64;          /* recurrence vectors: 0 = FP64 for FP64 values, else FP32;
                                  1 = FP64; 2 = FP32 */

@@ -128,6 +128,8 @@ struct Workspace {
 int get_workspace(const ld_opts* opt, size_t need, hipStream_t s, Workspace& ws) {
   ws.stream = s;
   if (opt && opt->workspace) {
+    if (reinterpret_cast<uintptr_t>(opt->workspace) % kAlign)
+      return fail(LD_EINVAL, "workspace must be %zu-byte aligned", kAlign);
     if (opt->workspace_bytes < need)
       return fail(LD_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes needed", opt->workspace_bytes,
                   need);

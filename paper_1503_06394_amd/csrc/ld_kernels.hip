@@ -604,7 +604,9 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
 }
 
 // perm[t] = index of the entry (col[t], row(t)); flag set when some transposed entry is missing.
-// One thread per stored entry: its row by binary search over row_ptr, then a scan of row col[t].
+// One thread per stored entry: its row by binary search over row_ptr, then a binary search of
+// row col[t] (columns are usually sorted) with a linear scan as the fallback for rows that are
+// not, so that a lookup in a long row costs log(length).
 __global__ void __launch_bounds__(256) transpose_index_kernel(const int64_t* row_ptr, const int32_t* col, int64_t d,
                                                               int64_t nnz, int64_t* perm, int* missing) {
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nnz; t += (int64_t)gridDim.x * 256) {
@@ -618,12 +620,19 @@ __global__ void __launch_bounds__(256) transpose_index_kernel(const int64_t* row
     }
     const int64_t r = lo;
     const int64_t j = col[t];
-    int64_t found = -1;
-    for (int64_t u = row_ptr[j]; u < row_ptr[j + 1]; ++u)
-      if (col[u] == r) {
-        found = u;
-        break;
-      }
+    const int64_t u0 = row_ptr[j], u1 = row_ptr[j + 1];
+    lo = u0;
+    hi = u1;
+    while (lo < hi) {  // first u with col[u] >= r
+      const int64_t mid = (lo + hi) >> 1;
+      if (col[mid] < r)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    int64_t found = (lo < u1 && col[lo] == r) ? lo : -1;
+    for (int64_t u = u0; found < 0 && u < u1; ++u)
+      if (col[u] == r) found = u;
     perm[t] = found;
     if (found < 0) atomicOr(missing, 1);
   }
@@ -908,20 +917,50 @@ __global__ void __launch_bounds__(256) scale_kernel(const TA* a, int64_t n, doub
     out[t] = (TO)((double)a[t] * scale);
 }
 
-template <typename VT>
+// out[r, j] = cv v_j[r] + cw W[r, j] + cwm Wm[r, j] + cwp Wp[r, j] (W, Wm, Wp nullable).  A thread
+// takes N consecutive probes of one row (N divides M and 64, so they share one hash word); the
+// (row, group) index advances by a fixed stride, so no division runs inside the loop.
+template <typename VT, int N>
 __global__ void __launch_bounds__(256) seed_kernel(VT* out, const VT* W, const VT* Wm, const VT* Wp, double cv,
                                                    double cw, double cwm, double cwp, uint64_t seed, int64_t d,
                                                    int M) {
-  const int64_t total = d * (int64_t)M;
-  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
-    const int64_t r = x / M;
-    const int j = (int)(x - r * M);
-    const uint64_t w = probe_word(seed, (uint64_t)r, (uint32_t)(j >> 6));
-    VT o = (VT)(((w >> (j & 63)) & 1u) ? -cv : cv);
-    if (W) o = fma((VT)cw, W[x], o);
-    if (Wm) o = fma((VT)cwm, Wm[x], o);
-    if (Wp) o = fma((VT)cwp, Wp[x], o);
-    out[x] = o;
+  const int groups = M / N;
+  const int64_t total = d * (int64_t)groups;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t r = x / groups;
+  int g = (int)(x - r * groups);
+  const int64_t step_r = stride / groups;
+  const int step_g = (int)(stride - step_r * groups);
+  for (; x < total; x += stride) {
+    const int j0 = g * N;
+    const int64_t off = r * M + j0;
+    VT o[N], t[N];
+    probe_signs<VT, N>(seed, r, j0, o);
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] *= (VT)cv;
+    if (W) {
+      vload_nt<VT, N>(W + off, t);
+#pragma unroll
+      for (int i = 0; i < N; ++i) o[i] = fma((VT)cw, t[i], o[i]);
+    }
+    if (Wm) {
+      vload_nt<VT, N>(Wm + off, t);
+#pragma unroll
+      for (int i = 0; i < N; ++i) o[i] = fma((VT)cwm, t[i], o[i]);
+    }
+    if (Wp) {
+      vload_nt<VT, N>(Wp + off, t);
+#pragma unroll
+      for (int i = 0; i < N; ++i) o[i] = fma((VT)cwp, t[i], o[i]);
+    }
+    vstore_nt<VT, N>(out + off, o);
+    r += step_r;
+    g += step_g;
+    if (g >= groups) {
+      g -= groups;
+      ++r;
+    }
   }
 }
 
@@ -1240,18 +1279,31 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <typename VT, int N>
+static void go_seed(void* out, const void* W, const void* Wm, const void* Wp, double cv, double cw, double cwm,
+                    double cwp, uint64_t seed, int64_t d, int M, hipStream_t s) {
+  const unsigned g = grid_for(d * (int64_t)(M / N), 256, 1u << 20);
+  hipLaunchKernelGGL((seed_kernel<VT, N>), dim3(g), dim3(256), 0, s, static_cast<VT*>(out),
+                     static_cast<const VT*>(W), static_cast<const VT*>(Wm), static_cast<const VT*>(Wp), cv, cw, cwm,
+                     cwp, seed, d, M);
+}
+
 hipError_t launch_seed(void* out, int vec_f64, const void* W, const void* Wm, const void* Wp, double cv, double cw,
                        double cwm, double cwp, uint64_t seed, int64_t d, int M, hipStream_t s) {
   if (d <= 0) return hipSuccess;
-  const unsigned g = grid_for(d * (int64_t)M, 256, 1u << 20);
-  if (vec_f64)
-    hipLaunchKernelGGL(seed_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(out),
-                       static_cast<const double*>(W), static_cast<const double*>(Wm), static_cast<const double*>(Wp),
-                       cv, cw, cwm, cwp, seed, d, M);
-  else
-    hipLaunchKernelGGL(seed_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(out),
-                       static_cast<const float*>(W), static_cast<const float*>(Wm), static_cast<const float*>(Wp), cv,
-                       cw, cwm, cwp, seed, d, M);
+  if (vec_f64) {
+    if (M % 2 == 0)
+      go_seed<double, 2>(out, W, Wm, Wp, cv, cw, cwm, cwp, seed, d, M, s);
+    else
+      go_seed<double, 1>(out, W, Wm, Wp, cv, cw, cwm, cwp, seed, d, M, s);
+  } else {
+    if (M % 4 == 0)
+      go_seed<float, 4>(out, W, Wm, Wp, cv, cw, cwm, cwp, seed, d, M, s);
+    else if (M % 2 == 0)
+      go_seed<float, 2>(out, W, Wm, Wp, cv, cw, cwm, cwp, seed, d, M, s);
+    else
+      go_seed<float, 1>(out, W, Wm, Wp, cv, cw, cwm, cwp, seed, d, M, s);
+  }
   return hipGetLastError();
 }
 

@@ -220,6 +220,11 @@ def test_caller_workspace_and_timing(ld, oracle_lib):
     small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
     with pytest.raises(ld.LogdetChebError):
         ld.ld_logdet_cheb(D, 0.3, 8.3, n, M, 3, workspace=small)
+    big = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ld.LogdetChebError, match="aligned"):
+        ld.ld_logdet_cheb(D, 0.3, 8.3, n, M, 3, workspace=big[4:])
+    r2 = ld.ld_logdet_cheb(D, 0.3, 8.3, n, M, 3, workspace=big[256:])
+    assert r2["logdet"] == r["logdet"]
 
 
 def test_autotuned_large_matrix(ld, oracle_lib):

@@ -79,6 +79,42 @@ def test_grad_fp32_gmrf_parity(ld, oracle_lib, M, plain):
     assert rel(r["logdet"], o["gamma"]) <= 1e-4
 
 
+def _pattern_case(kind: str):
+    """Symmetric matrices whose patterns stress the transpose lookup of the symmetric adjoint:
+    a hub row joined to every vertex, rows left empty (carried by the diagonal shift alone), and
+    rows whose columns are stored out of order."""
+    rng = np.random.default_rng(61)
+    if kind == "hub":
+        G = synth.hub_graph(3000, 2, mseed=5)  # L + I of a graph with one vertex of degree 2999
+        deg = np.diff(G.row_ptr).astype(np.float64)
+        rp, col, val = synth._insert_diagonal(G.d, G.row_ptr, G.col, -G.val, deg)
+        return synth.CSR(G.d, rp, col, val, "f64"), 1.0
+    B = synth.random_sparse_spd(1500, 3, 31, 1.0, "f64")
+    rows = B.row_of_entry()
+    if kind == "empty_rows":
+        gone = np.zeros(B.d, dtype=bool)
+        gone[::7] = True
+        keep = ~(gone[rows] | gone[B.col])
+        rp = np.zeros(B.d + 1, dtype=np.int64)
+        np.cumsum(np.bincount(rows[keep], minlength=B.d), out=rp[1:])
+        return synth.CSR(B.d, rp, B.col[keep], B.val[keep], "f64"), 0.5
+    order = np.concatenate([B.row_ptr[r] + rng.permutation(B.row_ptr[r + 1] - B.row_ptr[r])
+                            for r in range(B.d)])
+    return synth.CSR(B.d, B.row_ptr, B.col[order], B.val[order], "f64"), 0.0
+
+
+@pytest.mark.parametrize("kind", ["hub", "empty_rows", "unsorted"])
+def test_grad_pattern_layouts(ld, oracle_lib, kind):
+    C, shift = _pattern_case(kind)
+    a, b = oracle_lib.gershgorin(C, shift)
+    say(f"grad pattern layout {kind} d={C.d} nnz={C.nnz}")
+    r, g = ld.ld_logdet_cheb_grad(dev(C, shift=shift), a, b, 15, 8, 3)
+    o = oracle_lib.logdet_grad(C, a, b, 15, 8, seed=3, shift=shift)
+    assert _nw(g.cpu().numpy(), o["grad"]) <= 1e-10
+    assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-10
+    assert rel(r["logdet"], o["gamma"]) <= 1e-10
+
+
 def test_grad_rejects_too_many_probes(ld):
     B = synth.grid_laplacian_2d(8, "f32")
     with pytest.raises(ld.LogdetChebError):
