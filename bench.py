@@ -179,8 +179,9 @@ def main() -> None:
                          "FP64 and FP32) and the block form with the plain recurrence")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-only", action="store_true")
-    ap.add_argument("--copy-bytes", type=int, default=0,
-                    help="first run the library's streaming copy kernel on this many bytes (HBM calibration)")
+    ap.add_argument("--copy-bytes", type=int, default=2 << 30,
+                    help="first run the library's streaming copy kernel on this many bytes (what a streaming "
+                         "kernel reaches on this GPU; 0 skips it)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -310,6 +311,10 @@ def main() -> None:
                                    "algorithmic_GBps": round(ab_ / (adj_ms / adj_n / 1e3) / 1e9, 1)}
     if fwd_ms is not None:
         extra["forward_only"] = {"ms": round(fwd_ms, 3), "matvec_nnz_per_s": work / (fwd_ms / 1e3)}
+    # sparse products the kernels actually executed (product identities: ceil(n/2) per forward; every
+    # adjoint launch runs the SDDMM and all but the last of a call also the SpMM), per second of step time
+    executed = nnz * M * (step_n + (2 * adj_n - args.steps if adj_n else 0))
+    extra["executed_spmm_sddmm_nnz_ops_per_s"] = executed / args.steps / (ms_per_step / 1e3)
 
     cpu = None
     parity = None
@@ -333,6 +338,7 @@ def main() -> None:
     }
     if copy_gbps is not None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbps, 4)
     if args.compare_perprobe:
         log("plain per-probe forms and the plain block form")
         out["perprobe_fp64"] = perprobe([B], [a], [b], [n], M, W["seed"], W["shift"], "f64")
@@ -442,6 +448,7 @@ def bench_batch(args, W, copy_gbps) -> None:
     }
     if copy_gbps is not None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbps, 4)
     if args.compare_perprobe:
         log("plain per-probe FP64 form")
         out["perprobe_fp64"] = perprobe(mats, a, b, ns, M, seed, 0.0, "f64")
@@ -541,6 +548,7 @@ def bench_gmrf(args, W, copy_gbps) -> None:
     }
     if copy_gbps is not None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbps, 4)
     print(json.dumps(out), flush=True)
 
 
@@ -617,6 +625,7 @@ def bench_sec51(args, W, copy_gbps) -> None:
     }
     if copy_gbps is not None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbps, 4)
     print(json.dumps(out), flush=True)
 
 
