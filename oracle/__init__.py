@@ -299,3 +299,44 @@ def log_spanning_trees(adj, hub: int, n: int, m: int, seed: int = 0, method: int
     r["minor"] = L
     r["delta_max"] = dmax
     return r
+
+
+def lanczos_extremes(B, iters: int, seed: int = 0, shift: float = 0.0, gram: bool = False) -> tuple:
+    """Estimates of the extreme eigenvalues of B + shift I (gram False, B symmetric) or of C^T C
+    (gram True, C = B): the extreme Ritz values after ``iters`` steps of the Lanczos process in FP64
+    without reorthogonalisation, started from probe 0 of ``seed`` scaled to unit length.  Section 3.2
+    asks for bounds on the extreme eigenvalues (singular values) and points to power-type
+    iteration; the Lanczos process is the Krylov method that converges fastest to both ends at once.
+    Returns (lo, hi, alphas, betas): the smallest and largest eigenvalue of the tridiagonal matrix
+    T with diagonal alphas and off-diagonal betas."""
+    d = int(B.d)
+    rows = np.repeat(np.arange(d), np.diff(np.asarray(B.row_ptr)))
+    col = np.asarray(B.col, dtype=np.int64)
+    val = np.asarray(B.val, dtype=np.float64)
+
+    def apply(x):  # B x, or C^T (C x)
+        y = np.bincount(rows, weights=val * x[col], minlength=d)
+        if gram:
+            return np.bincount(col, weights=val * y[rows], minlength=d)
+        return y + shift * x
+
+    v = probe(seed, 0, d) / math.sqrt(d)
+    v_prev = np.zeros(d)
+    beta = 0.0
+    alphas, betas = [], []
+    for j in range(iters):
+        w = apply(v)
+        alpha = float(w @ v)
+        w = w - alpha * v - beta * v_prev
+        alphas.append(alpha)
+        bb = float(w @ w)
+        if not (bb > 0.0 and math.isfinite(bb)):
+            break  # the Krylov space is invariant
+        beta = math.sqrt(bb)
+        if j + 1 < iters:
+            betas.append(beta)
+        v_prev, v = v, w / beta
+    betas = betas[:len(alphas) - 1]
+    T = np.diag(alphas) + np.diag(betas, 1) + np.diag(betas, -1)
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1]), np.array(alphas), np.array(betas)

@@ -105,3 +105,18 @@ def test_spectral_estimate_gram_vs_svd(ld):
     # with the transpose given
     lo2, hi2 = ld.ld_spectral_estimate(dev(C), iters=400, gram=True, seed=3, Ct=ld.ld_transpose(dev(C)))
     assert abs(lo2 - lo) <= 1e-9 * abs(lo) and abs(hi2 - hi) <= 1e-9 * abs(hi)
+
+
+@pytest.mark.parametrize("case", ["spd_f64", "spd_f32", "gram_f32"])
+@pytest.mark.parametrize("iters", [2, 7, 25])
+def test_spectral_estimate_matches_oracle_lanczos(ld, oracle_lib, case, iters):
+    """The device Lanczos process against the oracle's, step count for step count: before the
+    Ritz values converge they depend on every step (start vector, products, orthogonalisation)."""
+    if case == "gram_f32":
+        B, shift, gram = synth.random_nonsingular(3000, 8, 21, 3.0, "f32"), 0.0, True
+    else:
+        B, shift, gram = synth.random_sparse_spd(3000, 4, 22, 1.0, case[-3:]), 0.2, False
+    say(f"spectral estimate vs oracle {case} iters={iters}")
+    lo, hi = ld.ld_spectral_estimate(dev(B, shift=shift), iters=iters, gram=gram, seed=9)
+    olo, ohi, _, _ = oracle_lib.lanczos_extremes(B, iters, seed=9, shift=shift, gram=gram)
+    assert rel(lo, olo) <= 1e-9 and rel(hi, ohi) <= 1e-9
