@@ -127,6 +127,20 @@ def traffic_from_profiles(kernel_tag: str, workload_name: str):
 # CPU baseline: the oracle on a bounded sample
 # ----------------------------------------------------------------------------------------
 
+def host_cpu() -> str:
+    """Model name of the host CPU (from /proc/cpuinfo) and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} cores available"
+
+
 def cpu_baseline(W: dict, a: float, b: float, gpu_probe_values) -> tuple:
     import numpy as np
 
@@ -154,7 +168,7 @@ def cpu_baseline(W: dict, a: float, b: float, gpu_probe_values) -> tuple:
     kind = "fwd+grad" if W["grad"] else "fwd"
     base = {"value": work / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
             "sample": f"{kind} of probes 0..{done - 1} of {M} on the full matrix (degree {n}), single-threaded "
-                      f"FP64 C oracle, {secs:.1f} s"}
+                      f"FP64 C oracle, {secs:.1f} s", "host_cpu": host_cpu()}
     parity = None
     if gpu_probe_values is not None:
         ref = float(r["s"][0])
