@@ -166,9 +166,9 @@ def cpu_baseline(W: dict, a: float, b: float, gpu_probe_values) -> tuple:
         r = oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]), shift=W["shift"])
     work = done * n * B.nnz * (2 if W.get("nonsingular") else 1)
     kind = "fwd+grad" if W["grad"] else "fwd"
-    base = {"value": work / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+    base = {"value": work / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
             "sample": f"{kind} of probes 0..{done - 1} of {M} on the full matrix (degree {n}), single-threaded "
-                      f"FP64 C oracle, {secs:.1f} s", "host_cpu": host_cpu()}
+                      f"FP64 C oracle, {secs:.1f} s"}
     parity = None
     if gpu_probe_values is not None:
         ref = float(r["s"][0])
@@ -440,7 +440,7 @@ def bench_batch(args, W, copy_gbps) -> None:
         t1 = time.perf_counter()
         o = oracle.logdet(mats[i], a[i], b[i], ns[i], M, seed=seed + i)
         secs = time.perf_counter() - t1
-        cpu = {"value": M * ns[i] * mats[i].nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": M * ns[i] * mats[i].nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
                "sample": f"member {i} of the batch (d={mats[i].d}, n={ns[i]}, {M} probes), single-threaded FP64 "
                          f"C oracle, {secs:.1f} s"}
         parity = abs(res[i]["logdet"] - o["gamma"]) / max(abs(o["gamma"]), 1e-3 * mats[i].d)
@@ -541,7 +541,7 @@ def bench_gmrf(args, W, copy_gbps) -> None:
         t1 = time.perf_counter()
         o = oracle.logdet(Jh, a, b, deg, 1, seed=seed, ids=np.array([0]))
         secs = time.perf_counter() - t1
-        cpu = {"value": deg * Jh.nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": deg * Jh.nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
                "sample": f"probe 0 at degree {deg} of J(-0.22) on the full grid, single-threaded FP64 C oracle, "
                          f"{secs:.1f} s"}
         parity = abs(rg["s"][0] - o["s"][0]) / max(abs(o["s"][0]), 1e-3 * d)
@@ -617,7 +617,7 @@ def bench_sec51(args, W, copy_gbps) -> None:
         t1 = time.perf_counter()
         o = oracle.logabsdet(C, smin, smax, deg, 1, seed=seed, ids=np.array([0]))
         secs = time.perf_counter() - t1
-        cpu = {"value": 2 * deg * nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": 2 * deg * nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
                "sample": f"probe 0 at degree {deg} of Algorithm 2 on the full matrix, single-threaded FP64 C oracle, "
                          f"{secs:.1f} s"}
         parity = abs(rg["s"][0] - o["s"][0]) / max(abs(o["s"][0]), 1e-3 * d)
