@@ -407,7 +407,6 @@ def bench_batch(args, W, copy_gbps) -> None:
     import numpy as np
     import torch
 
-    import oracle
     import paper_1503_06394_amd as ld
 
     mats, M, seed = W["mats"], W["M"], W["seed"]
@@ -437,10 +436,14 @@ def bench_batch(args, W, copy_gbps) -> None:
     if not args.no_cpu_baseline:
         order = np.argsort([B.d for B in mats])
         i = int(order[len(order) // 2])
+        import oracle
+
+        oracle.build()
         t1 = time.perf_counter()
         o = oracle.logdet(mats[i], a[i], b[i], ns[i], M, seed=seed + i)
         secs = time.perf_counter() - t1
-        cpu = {"value": M * ns[i] * mats[i].nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
+        cpu = {"value": M * ns[i] * mats[i].nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
                "sample": f"member {i} of the batch (d={mats[i].d}, n={ns[i]}, {M} probes), single-threaded FP64 "
                          f"C oracle, {secs:.1f} s"}
         parity = abs(res[i]["logdet"] - o["gamma"]) / max(abs(o["gamma"]), 1e-3 * mats[i].d)
@@ -475,7 +478,6 @@ def bench_gmrf(args, W, copy_gbps) -> None:
     import numpy as np
     import torch
 
-    import oracle
     import paper_1503_06394_amd as ld
     import synth
     from paper_1503_06394_amd.gmrf import GMRF
@@ -538,10 +540,14 @@ def bench_gmrf(args, W, copy_gbps) -> None:
         Jh = synth.gmrf_grid_precision(N, W["rho0"], "f32")
         a, b = g.bounds(W["rho0"])
         rg = ld.ld_logdet_cheb(g.precision(W["rho0"]), a, b, deg, M, seed, want_probes=True)
+        import oracle
+
+        oracle.build()
         t1 = time.perf_counter()
         o = oracle.logdet(Jh, a, b, deg, 1, seed=seed, ids=np.array([0]))
         secs = time.perf_counter() - t1
-        cpu = {"value": deg * Jh.nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
+        cpu = {"value": deg * Jh.nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
                "sample": f"probe 0 at degree {deg} of J(-0.22) on the full grid, single-threaded FP64 C oracle, "
                          f"{secs:.1f} s"}
         parity = abs(rg["s"][0] - o["s"][0]) / max(abs(o["s"][0]), 1e-3 * d)
@@ -577,7 +583,6 @@ def bench_sec51(args, W, copy_gbps) -> None:
     import numpy as np
     import torch
 
-    import oracle
     import paper_1503_06394_amd as ld
     import synth
 
@@ -614,10 +619,14 @@ def bench_sec51(args, W, copy_gbps) -> None:
         deg = 2  # about 10 s of oracle work on one core
         log(f"cpu baseline (oracle, probe 0 at degree {deg})")
         rg = ld.ld_logabsdet_cheb(D, Ct, smin, smax, deg, M, seed, want_probes=True)
+        import oracle
+
+        oracle.build()
         t1 = time.perf_counter()
         o = oracle.logabsdet(C, smin, smax, deg, 1, seed=seed, ids=np.array([0]))
         secs = time.perf_counter() - t1
-        cpu = {"value": 2 * deg * nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
+        cpu = {"value": 2 * deg * nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
                "sample": f"probe 0 at degree {deg} of Algorithm 2 on the full matrix, single-threaded FP64 C oracle, "
                          f"{secs:.1f} s"}
         parity = abs(rg["s"][0] - o["s"][0]) / max(abs(o["s"][0]), 1e-3 * d)
