@@ -78,6 +78,19 @@ def test_gmrf_128_fwd_grad(ld, oracle_lib):
     fm = oracle_lib.logdet(B, a, b, n, M, seed=seed, shift=shift - h)["gamma"]
     fd = (fp - fm) / (2 * h)
     assert rel(r["grad_shift"], fd) <= TOL32, (r["grad_shift"], fd)
+    # closed forms of Q = tau (kappa^2 I + L) at tau = 1, kappa = 0.3 from the grid's eigenvalues:
+    # d log det Q / d tau = d / tau exactly, and d/d kappa = sum_i 2 kappa / (kappa^2 + lambda_i).
+    # The estimator's d/d tau = sum_t g_t L_t + kappa^2 d/d shift has a tiny probe variance (its
+    # matrix is p'(Q) Q, close to I); d/d kappa = 2 kappa d/d shift is compared within five times
+    # the bound sqrt(2 ||2 kappa p'(Q)||_F^2 / M) on its probe standard error.
+    kappa, N = 0.3, 128
+    mu = 2.0 - 2.0 * np.cos(np.pi * np.arange(1, N + 1) / (N + 1))
+    lam = (mu[:, None, None] + mu[None, :, None] + mu[None, None, :]).ravel()
+    dtau = float(g.double().cpu().numpy() @ B.val) + kappa ** 2 * r["grad_shift"]
+    assert rel(dtau, float(B.d)) <= 1e-5, dtau
+    exact_dk = float((2 * kappa / (kappa ** 2 + lam)).sum())
+    se_bound = float(np.sqrt(2 * ((2 * kappa / (kappa ** 2 + lam)) ** 2).sum() / M))
+    assert abs(2 * kappa * r["grad_shift"] - exact_dk) <= 5 * se_bound, (2 * kappa * r["grad_shift"], exact_dk)
 
 
 @pytest.mark.timeout(600)
