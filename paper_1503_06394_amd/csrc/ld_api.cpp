@@ -524,13 +524,24 @@ int64_t max_tiles(const ld_csr* B, int vec_f64, int M, const ld_opts* opt) {
   return (B->rows + min_rows - 1) / min_rows;
 }
 
-// Probe block the forward actually runs.  Below 16 probes, a row of M probes that is not a whole
-// number of 64-byte segments is widened to the lane group the kernel gives it anyway (LPR lanes x
-// VPL probes): every lane then issues an aligned vector load and no gathered row straddles a
-// segment boundary, which costs less than the extra probes (10 probes take longer per step than
-// 16).  Probes are indexed, so the first M are the same probes; the rest are dropped.
+// Probe block the forward actually runs.  Some block widths run slower than a wider one (forward
+// times on random patterns at d = 10^6 and 3 10^6):
+//  * under 16 probes, rows that are not a whole number of 64-byte segments: widened to the lane
+//    group the shape gives them anyway (LPR lanes x VPL probes), so every lane issues an aligned
+//    vector load and no gathered row straddles a segment (10 probes take longer per step than 16);
+//  * rows held by a single 16-byte lane (FP32 M = 3, 4; FP64 M = 2): widened to two lanes;
+//  * FP32 rows that straddle 128-byte lines (17..31 and 49..63 probes): widened to the next whole
+//    line (24 probes take 7.6 ms, 32 take 6.3 ms; 56 take 13.1 ms, 64 take 11.8 ms).
+// Probes are indexed, so the first M are the same probes; the estimate drops the rest.
 int padded_probes(int M, int vec_f64, const ld_opts* opt) {
   if (opt && opt->probe_tile > 0) return M;
+  if (!vec_f64) {
+    if (M == 3 || M == 4) return 8;
+    if (M > 16 && M < 32) return 32;
+    if (M > 48 && M < 64) return 64;
+  } else if (M == 2) {
+    return 4;
+  }
   const int vb = vec_f64 ? 8 : 4;
   if (M >= 16 || (M * vb) % 64 == 0) return M;
   const Shape sh = base_shape(vec_f64, M);

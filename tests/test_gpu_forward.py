@@ -116,10 +116,11 @@ def test_fp64_vectors_with_fp32_values(ld, oracle_lib):
     _compare(r, o, TOL64, B.d, "f64vec")
 
 
-@pytest.mark.parametrize("M", [1, 2, 3, 7, 33, 64, 130, 300])
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 7, 10, 24, 33, 56, 64, 130, 300])
 @pytest.mark.parametrize("vec64", [True, False])
 def test_probe_counts_and_tiles(ld, oracle_lib, M, vec64):
-    """Probe counts that leave lanes idle, need narrow groups, or span several probe tiles; odd degree."""
+    """Probe counts that leave lanes idle, need narrow groups, are widened to a faster block (3, 4, 10,
+    24, 56 in FP32; 2 in FP64), or span several probe tiles; odd degree."""
     B = synth.random_sparse_spd(777, 3, 9, 1.0, "f64" if vec64 else "f32")
     a, b = oracle_lib.gershgorin(B)
     say(f"M={M} vec64={vec64}")
