@@ -125,6 +125,18 @@ struct Workspace {
   }
 };
 
+// Bytes of the idle pooled buffers on the current device: memory the library can reuse at once.
+size_t pool_idle_bytes() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  size_t sum = 0;
+  auto it = g_pool.find(dev);
+  if (it != g_pool.end())
+    for (const PoolBuf& b : it->second) sum += b.bytes;
+  return sum;
+}
+
 int get_workspace(const ld_opts* opt, size_t need, hipStream_t s, Workspace& ws) {
   ws.stream = s;
   if (opt && opt->workspace) {
@@ -894,29 +906,42 @@ size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, int stride
 }
 
 // A non-symmetric pattern falls back to the plain recurrence, so size for both plans.
-size_t grad_workspace_stride(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, int stride) {
-  size_t w = grad_workspace_for(B, n, M, vec_f64, stride, false);
-  if (use_pairs(opt)) w = std::max(w, grad_workspace_for(B, n, M, vec_f64, stride, true));
-  return w;
-}
+// Checkpoint stride of each form of the gradient (the paired form with the product identities,
+// and the plain recurrence that patterns without their transpose run): the caller's, else 1
+// (every W_k kept, no recomputation) when that form's plan fits the memory available -- the
+// caller's workspace, or 40% of the device's free memory -- else 0 (ceil(sqrt(steps))).  The
+// form is known only once the pattern has been checked, so each is planned on its own: the
+// plain form keeps twice as many blocks and may have to recompute where the paired one need not.
+struct GradStrides {
+  int pair, plain;
+};
 
-// Checkpoint stride: the caller's, else 1 (every W_k kept, no recomputation) when that plan
-// fits the memory available -- the caller's workspace, or 40% of the device's free memory --
-// else ceil(sqrt(steps)).
-int choose_stride(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
-  if (opt && opt->ckpt_stride > 0) return opt->ckpt_stride;
+GradStrides choose_strides(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
+  if (opt && opt->ckpt_stride > 0) return {opt->ckpt_stride, opt->ckpt_stride};
   size_t avail = 0;
   if (opt && opt->workspace) {
     avail = opt->workspace_bytes;
   } else {
+    // counting the library's idle pooled buffers as free: they are reused before anything new is
+    // allocated, so a repeated call plans as the first one did
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) avail = fr / 5 * 2;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) avail = (fr + pool_idle_bytes()) / 5 * 2;
   }
-  return grad_workspace_stride(B, n, M, vec_f64, opt, 1) <= avail ? 1 : 0;
+  GradStrides st;
+  st.pair = grad_workspace_for(B, n, M, vec_f64, 1, true) <= avail ? 1 : 0;
+  st.plain = grad_workspace_for(B, n, M, vec_f64, 1, false) <= avail ? 1 : 0;
+  return st;
+}
+
+// Workspace for either form with its stride.
+size_t grad_workspace_strides(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, const GradStrides& st) {
+  size_t w = grad_workspace_for(B, n, M, vec_f64, st.plain, false);
+  if (use_pairs(opt)) w = std::max(w, grad_workspace_for(B, n, M, vec_f64, st.pair, true));
+  return w;
 }
 
 size_t grad_workspace(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt) {
-  return grad_workspace_stride(B, n, M, vec_f64, opt, choose_stride(B, n, M, vec_f64, opt));
+  return grad_workspace_strides(B, n, M, vec_f64, opt, choose_strides(B, n, M, vec_f64, opt));
 }
 
 }  // namespace
@@ -1387,8 +1412,8 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   if (sh.probe_tiles != 1)
     return fail(LD_EINVAL, "gradient needs M <= %d probes per call with these vectors", (1 << sh.lpr_log2) * sh.vpl);
   const int64_t ntiles = d > 0 ? (d + sh.tile_rows - 1) / sh.tile_rows : 0;
-  const int stride = choose_stride(B, n, M, vec_f64, opt);
-  const size_t need = grad_workspace_stride(B, n, M, vec_f64, opt, stride);
+  const GradStrides strides = choose_strides(B, n, M, vec_f64, opt);
+  const size_t need = grad_workspace_strides(B, n, M, vec_f64, opt, strides);
   Workspace ws;
   rc = get_workspace(opt, need, s, ws);
   if (rc) return rc;
@@ -1406,7 +1431,8 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
     LD_HIP(hipStreamSynchronize(s));
   }
   const bool sym_pattern = miss == 0;
-  const GradPlan g = plan_grad(n, use_pairs(opt) && sym_pattern, stride);
+  const bool pair_form = use_pairs(opt) && sym_pattern;
+  const GradPlan g = plan_grad(n, pair_form, pair_form ? strides.pair : strides.plain);
   const bool pair = g.pair;
   const int nrows = partial_rows(n, pair);
   const size_t vecb = (size_t)d * M * vb;

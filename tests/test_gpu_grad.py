@@ -215,3 +215,22 @@ def test_grad_bitwise_reproducible(ld, stride):
     r2, g2 = ld.ld_logdet_cheb_grad(D, a, b, 24, 32, 13, ckpt_stride=stride)
     assert r1["logdet"] == r2["logdet"] and r1["grad_shift"] == r2["grad_shift"]
     assert torch.equal(g1, g2)
+
+
+def test_grad_full_store_planned_per_form(ld):
+    """A caller workspace too small for the plain form's full checkpoint store but large enough for
+    the paired form's: a symmetric pattern runs the paired form and keeps every W_k (no
+    recomputation), and the result equals the default call's bit for bit."""
+    import torch
+
+    B = synth.random_sparse_spd(20000, 5, 41, 1.0, "f32")
+    D = dev(B, shift=0.05)
+    a, b = ld.ld_gershgorin(D)
+    n, M = 50, 32
+    full = ld.ld_workspace_bytes(D, n, M, 2)  # either form with every W_k kept
+    ws = torch.empty(int(full * 0.7) // 256 * 256, dtype=torch.uint8, device="cuda")
+    say("grad full store planned per form")
+    r1, g1 = ld.ld_logdet_cheb_grad(D, a, b, n, M, 13, workspace=ws, timing=True)
+    assert r1["kernel_launches"] == (n + 1) // 2
+    r2, g2 = ld.ld_logdet_cheb_grad(D, a, b, n, M, 13)
+    assert r1["logdet"] == r2["logdet"] and torch.equal(g1, g2)
