@@ -1670,12 +1670,14 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
     tot_nnz += Bs[i].nnz;
   }
   // as for one matrix: the LDS slice capacity, lowered until the whole batch spreads over >= 1024 tiles
-  const int tile = (opt && opt->tile > 0) ? opt->tile : with_tile(sh, tot_d, tot_nnz, 0).tile_rows;
+  const bool fixed_tile = opt && opt->tile > 0;
+  const int tile = fixed_tile ? opt->tile : with_tile(sh, tot_d, tot_nnz, 0).tile_rows;
   sh.tile_rows = (tile + rpi - 1) / rpi * rpi;
+  const bool tune = !fixed_tile && autotune_enabled() && tot_d >= 65536;
 
   const bool pair = use_pairs(opt);
   std::vector<double> key = {(double)count, (double)M, (double)(seed >> 32), (double)(seed & 0xffffffffu),
-                             (double)vec_f64, (double)sh.tile_rows, pair ? 1.0 : 0.0};
+                             (double)vec_f64, fixed_tile ? (double)sh.tile_rows : 0.0, pair ? 1.0 : 0.0};
   for (int i = 0; i < count; ++i) {
     const double v[] = {bits_of(Bs[i].row_ptr), bits_of(Bs[i].col_idx), bits_of(Bs[i].values), (double)Bs[i].rows,
                         (double)Bs[i].nnz, (double)Bs[i].dtype, Bs[i].diag_shift, a[i], b[i], (double)n[i]};
@@ -1691,9 +1693,58 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
         if (jt->second->last_use < lru->second->last_use) lru = jt;
       g_batch.erase(lru);
     }
-    auto ent = std::make_unique<BatchEntry>();
-    int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, pair, sh, *ent);
-    if (rc) return rc;
+    std::unique_ptr<BatchEntry> ent;
+    if (!tune) {
+      ent = std::make_unique<BatchEntry>();
+      int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, pair, sh, *ent);
+      if (rc) return rc;
+    } else {
+      // The batch's autotuner: build the graph for each candidate shape (the full probe block at
+      // three tile heights, narrower probe tiles at the tallest), time one replay of each after a
+      // warm-up replay, keep the fastest.  Runs once per batch signature; later calls replay it.
+      std::vector<Shape> cands;
+      const std::vector<Shape> shapes = shape_candidates(vec_f64, M);
+      for (size_t si = 0; si < shapes.size(); ++si) {
+        const std::vector<int> tiles = tile_candidates(shapes[si], tot_d, tot_nnz);
+        for (size_t ti = 0; ti < tiles.size() && (si == 0 || ti == 0); ++ti) {
+          Shape c = shapes[si];
+          c.tile_rows = tiles[ti];
+          cands.push_back(c);
+        }
+      }
+      float best = INFINITY;
+      for (const Shape& c : cands) {
+        auto cand = std::make_unique<BatchEntry>();
+        int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, pair, c, *cand);
+        if (rc) {
+          if (ent) continue;  // keep the best graph built so far (e.g. out of memory for this one)
+          return rc;
+        }
+        float ms = 0.f;
+        if (cand->exec) {
+          hipEvent_t e0, e1;
+          LD_HIP(hipEventCreate(&e0));
+          if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(LD_EHIP, "hipEventCreate failed");
+          }
+          hipError_t he = hipGraphLaunch(cand->exec, s);
+          if (he == hipSuccess) he = hipEventRecord(e0, s);
+          if (he == hipSuccess) he = hipGraphLaunch(cand->exec, s);
+          if (he == hipSuccess) he = hipEventRecord(e1, s);
+          if (he == hipSuccess) he = hipEventSynchronize(e1);
+          if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          if (he != hipSuccess) return fail_hip(he, "batch autotuning replay");
+        }
+        if (!ent || ms < best) {
+          best = ms;
+          ent = std::move(cand);
+        }
+        if (!ent->exec) break;  // nothing to launch (every degree 0): any shape will do
+      }
+    }
     E = ent.get();
     g_batch[key] = std::move(ent);
   } else {
