@@ -145,7 +145,11 @@ int ld_logdet_cheb_grad(const ld_csr *B, double a, double b, int n, int M, uint6
 
 /* Batched Algorithm 1: matrix i (count of them, uneven sizes) uses its own bounds
  * [a[i], b[i]], degree n[i] and probe seed seed + i, all with M probes.  The whole batch
- * runs as one captured HIP graph.  a, b, n, outs are host arrays of `count` entries;
+ * runs as one captured HIP graph, cached per batch signature (device pointers, sizes, bounds,
+ * degrees, seed; at most 8 graphs, least recently used dropped).  Without opt->tile, the first
+ * call on a signature whose members total 65536 rows or more captures one graph per candidate
+ * shape and keeps the fastest replay (LD_AUTOTUNE=0 in the environment skips that).
+ * a, b, n, outs are host arrays of `count` entries;
  * Bs is a host array of descriptors pointing at device data.  a and b may both be NULL:
  * then every member gets its Gershgorin interval (ld_gershgorin_batched).  opt->moments_out
  * and opt->probe_out are ignored. */
