@@ -223,7 +223,9 @@ int ld_probes(uint64_t seed, int M, int64_t rows, int8_t *out, void *stream);
 int ld_transpose(const ld_csr *C, int64_t *row_ptr_t, int32_t *col_t, void *val_t, void *stream);
 
 /* Device bytes the entry point `mode` (0 logdet, 1 logabsdet, 2 grad, 3 taylor) needs as
- * workspace; vec_f64: 1 = FP64 recurrence vectors, 0 = FP32. */
+ * workspace; vec_f64: 1 = FP64 recurrence vectors, 0 = FP32.  The estimators' figure covers every
+ * shape their autotuner may pick; the gradient's assumes the default tile height (a smaller
+ * opt->tile needs more room for per-tile partials, and a short workspace gives LD_EWORKSPACE). */
 size_t ld_workspace_bytes(const ld_csr *B, int n, int M, int mode, int vec_f64);
 
 /* Device-to-device streaming copy with the library's own kernel (HBM bandwidth probe);

@@ -885,10 +885,16 @@ GradPlan plan_grad(int n, bool pair, int stride) {
   return g;
 }
 
-size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, int stride, bool pair) {
+// Kernel shape of the gradient: the whole probe block in one lane group (the adjoint reduces
+// across it), the caller's tile height or the default one.
+Shape grad_shape(const ld_csr* B, int M, int vec_f64, const ld_opts* opt) {
+  return with_tile(base_shape(vec_f64, M), B->rows, B->nnz, opt ? opt->tile : 0);
+}
+
+size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, int stride, bool pair) {
   const size_t vb = vec_f64 ? 8 : 4;
   const GradPlan g = plan_grad(n, pair, stride);
-  Shape sh = with_tile(base_shape(vec_f64, M), B->rows, B->nnz, 0);
+  const Shape sh = grad_shape(B, M, vec_f64, opt);
   const int64_t ntiles = B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
   const int rows = std::max(partial_rows(n, g.pair), 1);
   Carve c;
@@ -928,15 +934,15 @@ GradStrides choose_strides(const ld_csr* B, int n, int M, int vec_f64, const ld_
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) avail = (fr + pool_idle_bytes()) / 5 * 2;
   }
   GradStrides st;
-  st.pair = grad_workspace_for(B, n, M, vec_f64, 1, true) <= avail ? 1 : 0;
-  st.plain = grad_workspace_for(B, n, M, vec_f64, 1, false) <= avail ? 1 : 0;
+  st.pair = grad_workspace_for(B, n, M, vec_f64, opt, 1, true) <= avail ? 1 : 0;
+  st.plain = grad_workspace_for(B, n, M, vec_f64, opt, 1, false) <= avail ? 1 : 0;
   return st;
 }
 
 // Workspace for either form with its stride.
 size_t grad_workspace_strides(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, const GradStrides& st) {
-  size_t w = grad_workspace_for(B, n, M, vec_f64, st.plain, false);
-  if (use_pairs(opt)) w = std::max(w, grad_workspace_for(B, n, M, vec_f64, st.pair, true));
+  size_t w = grad_workspace_for(B, n, M, vec_f64, opt, st.plain, false);
+  if (use_pairs(opt)) w = std::max(w, grad_workspace_for(B, n, M, vec_f64, opt, st.pair, true));
   return w;
 }
 
@@ -1408,7 +1414,7 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   const int vec_f64 = vec_f64_of(opt, valt);
   const int64_t d = B->rows;
   const size_t vb = vec_f64 ? 8 : 4;
-  Shape sh = with_tile(base_shape(vec_f64, M), d, B->nnz, 0);
+  const Shape sh = grad_shape(B, M, vec_f64, opt);
   if (sh.probe_tiles != 1)
     return fail(LD_EINVAL, "gradient needs M <= %d probes per call with these vectors", (1 << sh.lpr_log2) * sh.vpl);
   const int64_t ntiles = d > 0 ? (d + sh.tile_rows - 1) / sh.tile_rows : 0;

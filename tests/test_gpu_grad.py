@@ -234,3 +234,17 @@ def test_grad_full_store_planned_per_form(ld):
     assert r1["kernel_launches"] == (n + 1) // 2
     r2, g2 = ld.ld_logdet_cheb_grad(D, a, b, n, M, 13)
     assert r1["logdet"] == r2["logdet"] and torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("tile", [32, 96, 512])
+def test_grad_caller_tile_height(ld, oracle_lib, tile):
+    """The caller's tile height (opt->tile) also shapes the gradient's kernels, including tiles
+    too tall for the LDS slice (read from global memory)."""
+    B = synth.random_sparse_spd(3000, 4, 29, 1.0, "f64")
+    a, b = oracle_lib.gershgorin(B)
+    say(f"grad tile={tile}")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=0.1), a + 0.1, b + 0.1, 17, 8, 6, tile=tile)
+    o = oracle_lib.logdet_grad(B, a + 0.1, b + 0.1, 17, 8, seed=6, shift=0.1)
+    assert _nw(g.cpu().numpy(), o["grad"]) <= 1e-10
+    assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-10
+    assert rel(r["logdet"], o["gamma"]) <= 1e-10
