@@ -199,8 +199,8 @@ def main() -> None:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (probes would shard "
-              "across GPUs with one all-reduce of the moment table; see the design notes).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (probes would shard "
+              "across GPUs with one all-reduce of the moment table).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
