@@ -6,7 +6,7 @@
  * paper and checked against closed forms, library routines and brute force in the
  * test suite.  Nothing in the GPU library includes, links or calls this file.
  *
- * Readings of the paper taken here (each one listed with its reason in the design notes):
+ * Readings of the paper taken here:
  *  - Algorithm 1 computes coefficients of f o g with g(x) = ((1 - 2 delta) x + 1)/2 mapping
  *    [-1, 1] onto [delta, 1 - delta] (Section 4.1), so its recurrence runs on the mapped
  *    matrix X = g^{-1}(A) = (2A - I)/(1 - 2 delta), whose spectrum lies in [-1, 1].
