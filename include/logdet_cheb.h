@@ -136,7 +136,9 @@ int ld_logdet_taylor(const ld_csr *B, double a, double b, int n, int M, uint64_t
  * the same for both orientations of a pair; for a pattern without its transpose the plain
  * recurrence runs and grad_values[t] = grad_output * dGamma/dB_ij.
  * The adjoint recurrence y_k = c_k v + 2 At y_{k+1} - y_{k+2} runs backwards over
- * segments recomputed from checkpoints every ckpt_stride steps.  grad_values is a device
+ * segments recomputed from checkpoints every ckpt_stride steps.  Probes run in passes of at
+ * most 128 (FP32 vectors) or 64 (FP64), whose contributions add up; 1 <= M <= 4096 as for
+ * ld_logdet_cheb, with the same probes.  grad_values is a device
  * array of nnz elements of type grad_dtype (LD_F64 or LD_F32).  out->grad_shift receives
  * grad_output * dGamma/d diag_shift and out->logdet the forward estimate. */
 int ld_logdet_cheb_grad(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,

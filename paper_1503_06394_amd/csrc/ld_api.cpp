@@ -885,29 +885,62 @@ GradPlan plan_grad(int n, bool pair, int stride) {
   return g;
 }
 
-// Kernel shape of the gradient: the whole probe block in one lane group (the adjoint reduces
-// across it), the caller's tile height or the default one.
+// Kernel shape of a gradient pass: the pass's whole probe block in one lane group (the adjoint
+// reduces across it), the caller's tile height or the default one.
 Shape grad_shape(const ld_csr* B, int M, int vec_f64, const ld_opts* opt) {
   return with_tile(base_shape(vec_f64, M), B->rows, B->nnz, opt ? opt->tile : 0);
+}
+
+// Probes per gradient pass.  Wider blocks would hold one row per wave, where the adjoint's
+// cross-lane reductions cost more than a second pass over the matrix (FP32: 256 probes in one
+// pass take 13 % longer than two passes of 128).  A chunk size that is a multiple of 64 keeps
+// every pass's probes on whole words of the probe hash.
+struct GradChunks {
+  int size, count, last;  // probes per full pass, passes, probes in the last pass
+};
+
+GradChunks grad_chunks(int M, int vec_f64) {
+  const int cap = vec_f64 ? 64 : 128;
+  GradChunks c;
+  c.size = std::min(M, cap);
+  c.count = (M + c.size - 1) / c.size;
+  c.last = M - (c.count - 1) * c.size;
+  return c;
+}
+
+// Seed under which a pass's local probe j is global probe probe0 + j, for probe0 a multiple of
+// 64.  The counter hash takes the SplitMix64 state seed + (ctr + 1) * gamma with
+// ctr = (row << 16) | (probe >> 6) (gamma = 0x9E3779B97F4A7C15, the generator's increment);
+// fewer than 2^16 words per row means the | is a +, so moving the probe-word index by probe0/64
+// is the same as adding (probe0/64) * gamma to the seed (mod 2^64).
+uint64_t pass_seed(uint64_t seed, int probe0) {
+  return seed + (uint64_t)(probe0 >> 6) * 0x9E3779B97F4A7C15ull;
+}
+
+int64_t tiles_of(const ld_csr* B, const Shape& sh) {
+  return B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
 }
 
 size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, int stride, bool pair) {
   const size_t vb = vec_f64 ? 8 : 4;
   const GradPlan g = plan_grad(n, pair, stride);
-  const Shape sh = grad_shape(B, M, vec_f64, opt);
-  const int64_t ntiles = B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
+  const GradChunks ch = grad_chunks(M, vec_f64);
+  const int64_t nt_full = tiles_of(B, grad_shape(B, ch.size, vec_f64, opt));
+  const int64_t nt_last = tiles_of(B, grad_shape(B, ch.last, vec_f64, opt));
+  const int64_t ntiles = std::max(nt_full, nt_last);
+  const int64_t part_cols = std::max(nt_full * ch.size, nt_last * ch.last);  // per partial row
   const int rows = std::max(partial_rows(n, g.pair), 1);
   Carve c;
-  const size_t vecb = (size_t)B->rows * M * vb;
+  const size_t vecb = (size_t)B->rows * ch.size * vb;
   for (int i = 0; i < g.nslots + g.nseg_buf + 2; ++i) c.take(vecb);
   c.take((size_t)B->nnz * vb);                       // gradient accumulators
   c.take((size_t)B->nnz * 8);                        // transposed-entry index
   c.take(256);                                       // missing-transpose flag
   c.take((size_t)std::max<int64_t>(ntiles, 1) * 8);  // diagonal partials
   c.take(8);                                         // diagonal total
-  c.take((size_t)rows * ntiles * M * 8);             // per-tile moment partials
-  c.take((size_t)M * rows * 8);                      // reduced partials
-  c.take(reduce_scratch_bytes(rows, M));
+  c.take((size_t)rows * part_cols * 8);              // per-tile moment partials
+  c.take((size_t)ch.size * rows * 8);                // reduced partials
+  c.take(reduce_scratch_bytes(rows, ch.size));
   return align_up(c.off);
 }
 
@@ -1414,10 +1447,13 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   const int vec_f64 = vec_f64_of(opt, valt);
   const int64_t d = B->rows;
   const size_t vb = vec_f64 ? 8 : 4;
-  const Shape sh = grad_shape(B, M, vec_f64, opt);
-  if (sh.probe_tiles != 1)
-    return fail(LD_EINVAL, "gradient needs M <= %d probes per call with these vectors", (1 << sh.lpr_log2) * sh.vpl);
-  const int64_t ntiles = d > 0 ? (d + sh.tile_rows - 1) / sh.tile_rows : 0;
+  // the probes run in passes of ch.size (the last one ch.last); the gradient accumulators and
+  // the per-probe moments collect over the passes
+  const GradChunks ch = grad_chunks(M, vec_f64);
+  const int64_t nt_max =
+      std::max(tiles_of(B, grad_shape(B, ch.size, vec_f64, opt)), tiles_of(B, grad_shape(B, ch.last, vec_f64, opt)));
+  const int64_t part_cols = std::max(tiles_of(B, grad_shape(B, ch.size, vec_f64, opt)) * ch.size,
+                                     tiles_of(B, grad_shape(B, ch.last, vec_f64, opt)) * ch.last);
   const GradStrides strides = choose_strides(B, n, M, vec_f64, opt);
   const size_t need = grad_workspace_strides(B, n, M, vec_f64, opt, strides);
   Workspace ws;
@@ -1441,20 +1477,19 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   const GradPlan g = plan_grad(n, pair_form, pair_form ? strides.pair : strides.plain);
   const bool pair = g.pair;
   const int nrows = partial_rows(n, pair);
-  const size_t vecb = (size_t)d * M * vb;
+  const size_t vecb = (size_t)d * ch.size * vb;
   std::vector<void*> slots(g.nslots), seg(g.nseg_buf);
   for (auto& p : slots) p = cv.take(vecb);
   for (auto& p : seg) p = cv.take(vecb);
   void* Ya = cv.take(vecb);
   void* Yb = cv.take(vecb);
   void* Gacc = cv.take((size_t)B->nnz * vb);
-  double* gdiag_part = static_cast<double*>(cv.take((size_t)std::max<int64_t>(ntiles, 1) * 8));
+  double* gdiag_part = static_cast<double*>(cv.take((size_t)std::max<int64_t>(nt_max, 1) * 8));
   double* gdiag_tot = static_cast<double*>(cv.take(8));
   const int rows_alloc = std::max(nrows, 1);
-  double* part = static_cast<double*>(cv.take((size_t)rows_alloc * ntiles * M * 8));
-  double* red_out = static_cast<double*>(cv.take((size_t)M * rows_alloc * 8));
-  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(rows_alloc, M)));
-  const int64_t kstride = ntiles * M;
+  double* part = static_cast<double*>(cv.take((size_t)rows_alloc * part_cols * 8));
+  double* red_out = static_cast<double*>(cv.take((size_t)ch.size * rows_alloc * 8));
+  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(rows_alloc, ch.size)));
 
   const std::vector<double> c = cheb_coeffs(a, b, n);
   const double alpha = 4.0 / (b - a);
@@ -1479,140 +1514,152 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   tm.on = opt && opt->timing;
   tm.s = s;
   LD_HIP(launch_fill_zero(Gacc, (size_t)B->nnz * vb, s));
-  LD_HIP(launch_fill_zero(gdiag_part, (size_t)std::max<int64_t>(ntiles, 1) * 8, s));
+  LD_HIP(launch_fill_zero(gdiag_part, (size_t)std::max<int64_t>(nt_max, 1) * 8, s));
   LD_HIP(tm.mark(T_OTHER));
-
-  StepLaunch L{};
-  L.nmat = 1;
-  L.ntiles = ntiles;
-  L.tile_rows = sh.tile_rows;
-  L.M = M;
-  L.shape = sh;
-  auto step = [&](int gsrc, int psrc, int mu, const void* G, const void* P, void* o, double h, double cp,
-                  int k) -> hipError_t {
-    StepDesc D{};
-    D.row_ptr = B->row_ptr;
-    D.col = B->col_idx;
-    D.val = B->values;
-    D.seed = seed;
-    D.d = d;
-    D.active = 1;
-    D.G = G;
-    D.P = P;
-    D.out = o;
-    D.ag = h * alpha;
-    D.bd = h * beff;
-    D.cp = cp;
-    if (mu != MU_NONE) {
-      D.mu_part = part + (int64_t)(pair ? 2 * k : k) * kstride;
-      D.mu_part2 = pair ? part + (int64_t)(2 * k + 1) * kstride : nullptr;
-    }
-    L.d0 = D;
-    return launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu, s);
-  };
-
-  // forward recurrence with checkpoints: W_k lives in bufW[k] (nullptr = probe hash)
-  std::vector<void*> bufW(g.m + 2, nullptr);
-  void* R0 = seg[0];
-  void* R1 = seg[1];
-  for (int k = 0; k < g.m && d > 0; ++k) {
-    void* o;
-    if (g.slot_of[k + 1] >= 0) {
-      o = slots[g.slot_of[k + 1]];
-    } else {
-      void* prev = k >= 1 ? bufW[k - 1] : nullptr;
-      if (prev == R0 || prev == R1)
-        o = prev;
-      else
-        o = (bufW[k] == R0) ? R1 : R0;
-    }
-    const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
-    const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
-    LD_HIP(step(gsrc, psrc, pair ? MU_PAIR : MU_PROBE, bufW[k], k >= 2 ? bufW[k - 1] : nullptr, o,
-                k == 0 ? 0.5 : 1.0, k == 0 ? 0.0 : -1.0, k));
-    LD_HIP(tm.mark(T_STEP));
-    bufW[k + 1] = o;
-  }
-  if (nrows >= 1 && d > 0)
-    LD_HIP(launch_reduce_moments(part, ntiles, M, 0, nrows - 1, kstride, red_out, nrows, red_tmp, s));
-
-  // backward.  A symmetric pattern lets each row accumulate its transposed entries from the
-  // rows of y_{j+1} that the SpMM gathers anyway (one gather per nonzero instead of two).
   const bool sym = sym_pattern && sym_enabled();
-  auto ckpt = [&](int k) -> void* { return k == 0 ? nullptr : slots[g.slot_of[k]]; };
-  if (n >= 1 && d > 0) {
-    // y_top: c_n V (plain) or al[top-1] W_{top-1} + 2 be[top-1] W_top (pairs; W_0 = V)
-    if (!pair) {
-      LD_HIP(launch_seed(Ya, vec_f64, nullptr, nullptr, nullptr, c[n], 0.0, 0.0, 0.0, seed, d, M, s));
-    } else {
-      const int t = g.top;
-      LD_HIP(launch_seed(Ya, vec_f64, ckpt(t), t - 1 >= 1 ? ckpt(t - 1) : nullptr, nullptr,
-                         t - 1 == 0 ? al[t - 1] : 0.0, 2.0 * be[t - 1], al[t - 1], 0.0, seed, d, M, s));
-    }
-    LD_HIP(tm.mark(T_OTHER));
-    void* y1 = Ya;       // y_{j+1}
-    void* y2 = nullptr;  // y_{j+2}
-    AdjDesc A{};
-    A.row_ptr = B->row_ptr;
-    A.col = B->col_idx;
-    A.val = B->values;
-    A.Gacc = Gacc;
-    A.gdiag_part = gdiag_part;
-    A.seed = seed;
-    A.d = d;
-    A.ag = alpha;
-    A.bd = beff;
-    A.cp = -1.0;
-    for (int q = g.nseg - 1; q >= 0; --q) {
-      const int lo = g.lo[q], hi = g.hi[q];
-      // segW[i] = W_{lo-1+i}, i = 0 .. hi-lo+1 (+1 with pairs: W_{hi+1})
-      std::vector<void*> segW(hi - lo + 3, nullptr);
-      segW[0] = ckpt(lo - 1);
-      segW[1] = ckpt(lo);
-      for (int i = 2; i <= hi - lo + 1; ++i) {
-        const int k = lo - 1 + i;  // recompute W_k = 2 At W_{k-1} - W_{k-2}
-        const bool p_hash = (k - 2) == 0;
-        LD_HIP(step(SRC_BUF, p_hash ? SRC_HASH : SRC_BUF, MU_NONE, segW[i - 1], p_hash ? nullptr : segW[i - 2],
-                    seg[i - 2], 1.0, -1.0, 0));
-        LD_HIP(tm.mark(T_STEP));
-        segW[i] = seg[i - 2];
+  std::vector<double> red((size_t)M * rows_alloc, 0.0);  // per-probe partial rows, all passes
+
+  for (int pass = 0; pass < ch.count; ++pass) {
+    const int probe0 = pass * ch.size;  // a multiple of 64 whenever there is more than one pass
+    const uint64_t pseed = pass_seed(seed, probe0);
+    const int Mp = pass + 1 < ch.count ? ch.size : ch.last;
+    const Shape sh = grad_shape(B, Mp, vec_f64, opt);
+    const int64_t ntiles = tiles_of(B, sh);
+    const int64_t kstride = ntiles * Mp;
+    StepLaunch L{};
+    L.nmat = 1;
+    L.ntiles = ntiles;
+    L.tile_rows = sh.tile_rows;
+    L.M = Mp;
+    L.shape = sh;
+    auto step = [&](int gsrc, int psrc, int mu, const void* G, const void* P, void* o, double h, double cp,
+                    int k) -> hipError_t {
+      StepDesc D{};
+      D.row_ptr = B->row_ptr;
+      D.col = B->col_idx;
+      D.val = B->values;
+      D.seed = pseed;
+      D.d = d;
+      D.active = 1;
+      D.G = G;
+      D.P = P;
+      D.out = o;
+      D.ag = h * alpha;
+      D.bd = h * beff;
+      D.cp = cp;
+      if (mu != MU_NONE) {
+        D.mu_part = part + (int64_t)(pair ? 2 * k : k) * kstride;
+        D.mu_part2 = pair ? part + (int64_t)(2 * k + 1) * kstride : nullptr;
       }
-      if (pair) segW[hi - lo + 2] = ckpt(hi + 1);
-      for (int j = hi; j >= lo; --j) {
-        void* o = y2 ? y2 : (y1 == Ya ? Yb : Ya);
-        A.Y1 = y1;
-        A.Y2 = y2;
-        A.out = o;
-        A.W = segW[j - lo + 1];
-        A.gw = 2.0;
-        if (!pair) {
-          A.cv = c[j];
-          A.cw = A.cwm = A.cwp = 0.0;
-          A.Wm = A.Wp = nullptr;
-        } else {
-          A.cw = 2.0 * be[j - 1];
-          A.cv = j - 1 == 0 ? al[j - 1] : 0.0;  // W_0 = V
-          A.Wm = j - 1 == 0 ? nullptr : segW[j - lo];
-          A.cwm = al[j - 1];
-          A.Wp = segW[j - lo + 2];
-          A.cwp = al[j];
+      L.d0 = D;
+      return launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu, s);
+    };
+
+    // forward recurrence with checkpoints: W_k lives in bufW[k] (nullptr = probe hash)
+    std::vector<void*> bufW(g.m + 2, nullptr);
+    void* R0 = seg[0];
+    void* R1 = seg[1];
+    for (int k = 0; k < g.m && d > 0; ++k) {
+      void* o;
+      if (g.slot_of[k + 1] >= 0) {
+        o = slots[g.slot_of[k + 1]];
+      } else {
+        void* prev = k >= 1 ? bufW[k - 1] : nullptr;
+        if (prev == R0 || prev == R1)
+          o = prev;
+        else
+          o = (bufW[k] == R0) ? R1 : R0;
+      }
+      const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
+      const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
+      LD_HIP(step(gsrc, psrc, pair ? MU_PAIR : MU_PROBE, bufW[k], k >= 2 ? bufW[k - 1] : nullptr, o,
+                  k == 0 ? 0.5 : 1.0, k == 0 ? 0.0 : -1.0, k));
+      LD_HIP(tm.mark(T_STEP));
+      bufW[k + 1] = o;
+    }
+    if (nrows >= 1 && d > 0) {
+      LD_HIP(launch_reduce_moments(part, ntiles, Mp, 0, nrows - 1, kstride, red_out, nrows, red_tmp, s));
+      LD_HIP(hipMemcpyAsync(red.data() + (size_t)probe0 * nrows, red_out, (size_t)Mp * nrows * 8,
+                            hipMemcpyDeviceToHost, s));
+    }
+
+    // backward.  A symmetric pattern lets each row accumulate its transposed entries from the
+    // rows of y_{j+1} that the SpMM gathers anyway (one gather per nonzero instead of two).
+    auto ckpt = [&](int k) -> void* { return k == 0 ? nullptr : slots[g.slot_of[k]]; };
+    if (n >= 1 && d > 0) {
+      // y_top: c_n V (plain) or al[top-1] W_{top-1} + 2 be[top-1] W_top (pairs; W_0 = V)
+      if (!pair) {
+        LD_HIP(launch_seed(Ya, vec_f64, nullptr, nullptr, nullptr, c[n], 0.0, 0.0, 0.0, pseed, d, Mp, s));
+      } else {
+        const int t = g.top;
+        LD_HIP(launch_seed(Ya, vec_f64, ckpt(t), t - 1 >= 1 ? ckpt(t - 1) : nullptr, nullptr,
+                           t - 1 == 0 ? al[t - 1] : 0.0, 2.0 * be[t - 1], al[t - 1], 0.0, pseed, d, Mp, s));
+      }
+      LD_HIP(tm.mark(T_OTHER));
+      void* y1 = Ya;       // y_{j+1}
+      void* y2 = nullptr;  // y_{j+2}
+      AdjDesc A{};
+      A.row_ptr = B->row_ptr;
+      A.col = B->col_idx;
+      A.val = B->values;
+      A.Gacc = Gacc;
+      A.gdiag_part = gdiag_part;
+      A.seed = pseed;
+      A.d = d;
+      A.ag = alpha;
+      A.bd = beff;
+      A.cp = -1.0;
+      for (int q = g.nseg - 1; q >= 0; --q) {
+        const int lo = g.lo[q], hi = g.hi[q];
+        // segW[i] = W_{lo-1+i}, i = 0 .. hi-lo+1 (+1 with pairs: W_{hi+1})
+        std::vector<void*> segW(hi - lo + 3, nullptr);
+        segW[0] = ckpt(lo - 1);
+        segW[1] = ckpt(lo);
+        for (int i = 2; i <= hi - lo + 1; ++i) {
+          const int k = lo - 1 + i;  // recompute W_k = 2 At W_{k-1} - W_{k-2}
+          const bool p_hash = (k - 2) == 0;
+          LD_HIP(step(SRC_BUF, p_hash ? SRC_HASH : SRC_BUF, MU_NONE, segW[i - 1], p_hash ? nullptr : segW[i - 2],
+                      seg[i - 2], 1.0, -1.0, 0));
+          LD_HIP(tm.mark(T_STEP));
+          segW[i] = seg[i - 2];
         }
-        LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, true, false, y2 != nullptr, sym, s));
-        LD_HIP(tm.mark(T_ADJ));
-        y2 = y1;
-        y1 = o;
+        if (pair) segW[hi - lo + 2] = ckpt(hi + 1);
+        for (int j = hi; j >= lo; --j) {
+          void* o = y2 ? y2 : (y1 == Ya ? Yb : Ya);
+          A.Y1 = y1;
+          A.Y2 = y2;
+          A.out = o;
+          A.W = segW[j - lo + 1];
+          A.gw = 2.0;
+          if (!pair) {
+            A.cv = c[j];
+            A.cw = A.cwm = A.cwp = 0.0;
+            A.Wm = A.Wp = nullptr;
+          } else {
+            A.cw = 2.0 * be[j - 1];
+            A.cv = j - 1 == 0 ? al[j - 1] : 0.0;  // W_0 = V
+            A.Wm = j - 1 == 0 ? nullptr : segW[j - lo];
+            A.cwm = al[j - 1];
+            A.Wp = segW[j - lo + 2];
+            A.cwp = al[j];
+          }
+          LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, true, false, y2 != nullptr, sym, s));
+          LD_HIP(tm.mark(T_ADJ));
+          y2 = y1;
+          y1 = o;
+        }
       }
+      // the y_1 w_0^T term, w_0 = v
+      A.Y1 = y1;
+      A.Y2 = nullptr;
+      A.out = nullptr;
+      A.W = nullptr;
+      A.Wm = A.Wp = nullptr;
+      A.cv = A.cw = A.cwm = A.cwp = 0.0;
+      A.gw = 1.0;
+      LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, false, true, false, sym, s));
+      LD_HIP(tm.mark(T_ADJ));
     }
-    // the y_1 w_0^T term, w_0 = v
-    A.Y1 = y1;
-    A.Y2 = nullptr;
-    A.out = nullptr;
-    A.W = nullptr;
-    A.Wm = A.Wp = nullptr;
-    A.cv = A.cw = A.cwm = A.cwp = 0.0;
-    A.gw = 1.0;
-    LD_HIP(launch_adjoint(A, M, sh, vec_f64, valt, false, true, false, sym, s));
-    LD_HIP(tm.mark(T_ADJ));
   }
   const double scale = grad_output * (2.0 / (b - a)) / M;
   if (B->nnz > 0) {
@@ -1623,12 +1670,10 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
       LD_HIP(launch_scale_grad(Gacc, vec_f64, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
   }
   double gd = 0.0;
-  if (ntiles > 0) {
-    LD_HIP(launch_sum_doubles(gdiag_part, ntiles, gdiag_tot, s));
+  if (nt_max > 0) {
+    LD_HIP(launch_sum_doubles(gdiag_part, nt_max, gdiag_tot, s));
     LD_HIP(hipMemcpyAsync(&gd, gdiag_tot, 8, hipMemcpyDeviceToHost, s));
   }
-  std::vector<double> red((size_t)M * rows_alloc, 0.0);
-  if (nrows >= 1 && d > 0) LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * nrows * 8, hipMemcpyDeviceToHost, s));
   LD_HIP(tm.mark(T_OTHER));
   LD_HIP(hipStreamSynchronize(s));
   std::vector<double> mu((size_t)M * (n + 1), 0.0);

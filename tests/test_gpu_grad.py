@@ -115,10 +115,28 @@ def test_grad_pattern_layouts(ld, oracle_lib, kind):
     assert rel(r["logdet"], o["gamma"]) <= 1e-10
 
 
+@pytest.mark.parametrize("storage,M", [("f32", 300), ("f32", 256), ("f64", 150), ("f64", 128)])
+def test_grad_probe_passes(ld, oracle_lib, storage, M):
+    """Probe blocks wider than one pass (128 FP32 / 64 FP64 probes): the passes' probes are
+    probes probe0.. of the same seed, so value, per-entry gradient and d/d(shift) match the
+    oracle's over all M probes."""
+    B = synth.random_sparse_spd(1200, 3, 33, 1.0, storage)
+    a, b = oracle_lib.gershgorin(B)
+    tol = 1e-10 if storage == "f64" else 1e-4
+    say(f"grad probe passes {storage} M={M}")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=0.2), a + 0.2, b + 0.2, 14, M, 12)
+    o = oracle_lib.logdet_grad(B, a + 0.2, b + 0.2, 14, M, seed=12, shift=0.2)
+    assert _nw(g.cpu().numpy(), o["grad"]) <= tol
+    assert rel(r["grad_shift"], o["grad_shift"]) <= tol
+    assert rel(r["logdet"], o["gamma"]) <= tol
+    f = ld.ld_logdet_cheb(dev(B, shift=0.2), a + 0.2, b + 0.2, 14, M, 12)
+    assert rel(r["logdet"], f["logdet"]) <= tol
+
+
 def test_grad_rejects_too_many_probes(ld):
     B = synth.grid_laplacian_2d(8, "f32")
     with pytest.raises(ld.LogdetChebError):
-        ld.ld_logdet_cheb_grad(dev(B, shift=0.1), 0.1, 8.1, 5, 300, 0)
+        ld.ld_logdet_cheb_grad(dev(B, shift=0.1), 0.1, 8.1, 5, 4097, 0)
 
 
 def test_autograd_function_and_gmrf_chain_rule(ld, oracle_lib):
