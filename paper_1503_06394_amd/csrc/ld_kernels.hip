@@ -410,8 +410,11 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
 //    row that the SpMM gathers anyway and the row's own w[i]; H is permuted once at the end
 //    (entry (i, j) takes H at the index of (j, i)).  One gather per nonzero.
 template <typename VT, int VALT, int VPL, bool SPMM, bool WHASH, bool Y2, bool SYM>
-// FP32: fit five waves per SIMD (96 VGPRs, no spills); the FP64 form keeps its registers.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(VT) == 4 ? 5 : 1)))
+// FP32 vectors, single-gather form, FP32 or BF16 values: fit five waves per SIMD (96 VGPRs, no
+// spills).  The two-gather form (a second gathered row per nonzero), FP64 values and FP64
+// vectors would spill at that budget: those keep the compiler's choice.
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((sizeof(VT) == 4 && SYM && VALT != VAL_F64) ? 5 : 1)))
 adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles) {
   typedef typename Val<VALT>::T MV;
   const int64_t tile = xcd_tile(ntiles);
