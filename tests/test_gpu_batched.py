@@ -154,3 +154,25 @@ def test_batched_low_degrees_and_single_member(ld, oracle_lib, ns):
     for i, B in enumerate(mats):
         o = oracle_lib.logdet(B, ab[i][0], ab[i][1], ns[i], 8, seed=5 + i)
         assert rel(res[i]["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10, (i, ns[i])
+
+
+@pytest.mark.parametrize("autotune", ["1", "0"])
+def test_batched_autotuned_graph(ld, oracle_lib, monkeypatch, autotune):
+    """A batch of more than 65536 rows in all is captured once per candidate shape and timed;
+    whichever graph wins, every member matches the oracle and a replay reproduces it bit for
+    bit (LD_AUTOTUNE=0 keeps the default shape)."""
+    monkeypatch.setenv("LD_AUTOTUNE", autotune)
+    mats = synth.random_batch(12, mseed0=4400, d_min=3000, d_max=20000, n_min=8, n_max=24, storage="f32")
+    assert sum(B.d for B in mats) >= 65536
+    ab = [oracle_lib.gershgorin(B) for B in mats]
+    ns = [B.meta["n"] for B in mats]
+    D = [dev(B) for B in mats]
+    M, seed = 32, 61
+    say(f"batched autotuned graph LD_AUTOTUNE={autotune}")
+    ld.ld_clear_cache()
+    res = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, M, seed)
+    for i in (0, 5, 11):
+        o = oracle_lib.logdet(mats[i], ab[i][0], ab[i][1], ns[i], M, seed=seed + i)
+        assert rel(res[i]["logdet"], o["gamma"], FLOOR * mats[i].d) <= 1e-4
+    res2 = ld.ld_logdet_cheb_batched(D, [x[0] for x in ab], [x[1] for x in ab], ns, M, seed)
+    assert [r["logdet"] for r in res2] == [r["logdet"] for r in res]
