@@ -78,6 +78,22 @@ def workload(name: str):
                     desc="Section 5.1's largest run: random symmetric C, d=3e7, 5 off-diagonals per row U[-1,1] "
                          "mirrored, diagonal = sum|off| + 1e-3 (about 3.3e8 nnz), FP32; Algorithm 2 with m=10, "
                          "n=15, sigma_min=1e-3, sigma_max=||C||_1")
+    if name == "trees1m":
+        return dict(B=None, nv=1_000_000, k_off=5, mseed=7, n=100, M=32, seed=8, grad=False,
+                    desc="spanning trees of a hub graph with 1e6 vertices (vertex 0 joined to all, 5 random "
+                         "neighbours drawn per vertex, edges mirrored): Laplacian minor L(hub) on the device, then "
+                         "Algorithm 2 with sigma in [1, 2 Delta_max - 1] (Section 3.3), FP32, M=32, n=100")
+    if name == "taylor4096":
+        B = synth.grid_laplacian_2d(4096, "bf16")
+        return dict(B=B, shift=0.01, a=0.01, b=8.01, n=100, M=32, seed=5, grad=False,
+                    desc="Taylor-series comparator of Section 5.1 on the 2D Dirichlet grid 4096x4096 + 0.01 I "
+                         "(BF16 values, FP32 vectors, M=32, n=100), beside the Chebyshev estimate with the same "
+                         "probes; both against the closed-form log det")
+    if name == "lanczos1m":
+        B = synth.random_sparse_spd(1_000_000, k_off=5, mseed=2, diag_add=1.0, storage="f32")
+        return dict(B=B, iters=300, seed=2, grad=False,
+                    desc="spectral estimate (Section 3.2's bounds): 300 FP64 Lanczos steps on the random d=1e6 "
+                         "matrix of the main workload, extreme Ritz values")
     if name == "grid4096":
         B = synth.grid_laplacian_2d(4096, "bf16")
         return dict(B=B, shift=0.01, a=0.01, b=8.01, n=100, M=32, seed=5, grad=False,
@@ -187,6 +203,7 @@ def main() -> None:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="random1m",
                     choices=["random1m", "grid32", "gmrf128", "grid4096", "batch256", "nonsingular1m", "gmrf5000",
+                             "trees1m", "taylor4096", "lanczos1m",
                              "sec51_3e7"])
     ap.add_argument("--compare-perprobe", action="store_true",
                     help="also time the plain per-probe forms (one probe per call, one product per degree, "
@@ -227,6 +244,12 @@ def main() -> None:
         return bench_gmrf(args, W, copy_gbps)
     if args.workload == "sec51_3e7":
         return bench_sec51(args, W, copy_gbps)
+    if args.workload == "trees1m":
+        return bench_trees(args, W, copy_gbps)
+    if args.workload == "taylor4096":
+        return bench_taylor(args, W, copy_gbps)
+    if args.workload == "lanczos1m":
+        return bench_lanczos(args, W, copy_gbps)
     B = W["B"]
     d, nnz, M, n = B.d, B.nnz, W["M"], W["n"]
     D = ld.DeviceCSR.from_host(B, device="cuda:0", diag_shift=W["shift"])
@@ -650,6 +673,182 @@ def bench_sec51(args, W, copy_gbps) -> None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
         out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbps, 4)
     print(json.dumps(out), flush=True)
+
+
+def _finish(out: dict, copy_gbps) -> None:
+    if copy_gbps is not None:
+        out["copy_kernel_GBps"] = round(copy_gbps, 1)
+        out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbps, 4)
+    print(json.dumps(out), flush=True)
+
+
+def _line(args, W, value, ms, dtype, config, achieved, avg_ms, bytes_, kernel, cpu, accuracy) -> dict:
+    return {
+        "metric": METRIC, "value": value, "unit": "matvec-nnz/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": dict({"workload": W["desc"], "parallelism": "single GPU"}, **config),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": kernel,
+                     "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_},
+        "cpu_baseline": cpu, "accuracy": accuracy,
+    }
+
+
+def bench_trees(args, W, copy_gbps) -> None:
+    """Spanning-tree counting (Section 3.3) on a hub graph with 1e6 vertices: each step builds the
+    Laplacian minor on the device and runs Algorithm 2 on it."""
+    import numpy as np
+    import torch
+
+    import paper_1503_06394_amd as ld
+    import synth
+
+    G = synth.hub_graph(W["nv"], W["k_off"], W["mseed"])
+    D = ld.DeviceCSR.from_host(G, device="cuda:0")
+    n, M, seed = W["n"], W["M"], W["seed"]
+    dm, nnz_l = G.d - 1, G.nnz - (G.d - 1)  # the minor: hub row and column out, the diagonal in
+    log(f"graph: {G.d} vertices, {G.nnz} adjacency entries; minor d={dm} nnz={nnz_l}")
+    for _ in range(args.warmup):
+        ld.ld_log_spanning_trees(D, 0, n, M, seed)
+    torch.cuda.synchronize()
+    kms = kn = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = ld.ld_log_spanning_trees(D, 0, n, M, seed, timing=True, want_probes=True)
+        kms += r["kernel_ms"]
+        kn += r["kernel_launches"]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = 2 * M * n * nnz_l / (ms / 1e3)
+    sb = step_bytes(dm, nnz_l, M, 4, 4)
+    avg = kms / max(kn, 1)
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        deg = 4
+        log(f"cpu baseline (oracle minor, then Algorithm 2 probe 0 at degree {deg})")
+        L, dmax = oracle.laplacian_minor(G, 0)
+        rg = ld.ld_log_spanning_trees(D, 0, deg, M, seed, want_probes=True)
+        t1 = time.perf_counter()
+        o = oracle.logabsdet(L, 1.0, 2.0 * dmax - 1.0, deg, 1, seed=seed, ids=np.array([0]))
+        secs = time.perf_counter() - t1
+        cpu = {"value": 2 * deg * nnz_l / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
+               "sample": f"probe 0 at degree {deg} of Algorithm 2 on the minor (built beforehand), single-threaded "
+                         f"FP64 C oracle, {secs:.1f} s"}
+        parity = abs(rg["s"][0] - o["s"][0]) / max(abs(o["s"][0]), 1e-3 * dm)
+    out = _line(args, W, value, ms, "f32",
+                {"d": G.d, "nnz": G.nnz, "M": M, "n": n, "minor_nnz": nnz_l,
+                 "step": "Laplacian minor + Algorithm 2 (Section 3.3)"},
+                sb / (avg / 1e3) / 1e9, avg, sb, "step kernel", cpu,
+                {"log_spanning_trees": r["logdet"], "std_err_rel": abs(r["std_err"] / r["logdet"]),
+                 "oracle_parity_rel_probe0_deg4": parity, "parity_tolerance": 1e-4})
+    _finish(out, copy_gbps)
+
+
+def bench_taylor(args, W, copy_gbps) -> None:
+    """The Taylor-series comparator of Section 5.1 at scale, beside the Chebyshev estimate with the
+    same probes and degree; both against the grid's closed-form log det."""
+    import numpy as np
+    import torch
+
+    import paper_1503_06394_amd as ld
+
+    B = W["B"]
+    D = ld.DeviceCSR.from_host(B, device="cuda:0", diag_shift=W["shift"])
+    a, b, n, M, seed = W["a"], W["b"], W["n"], W["M"], W["seed"]
+    for _ in range(args.warmup):
+        ld.ld_logdet_taylor(D, a, b, n, M, seed)
+    torch.cuda.synchronize()
+    kms = kn = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = ld.ld_logdet_taylor(D, a, b, n, M, seed, timing=True, want_probes=True)
+        kms += r["kernel_ms"]
+        kn += r["kernel_launches"]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    rc = ld.ld_logdet_cheb(D, a, b, n, M, seed)
+    N = 4096
+    mu = 2.0 - 2.0 * np.cos(np.pi * np.arange(1, N + 1) / (N + 1))
+    exact = float(np.log((mu[:, None] + mu[None, :]).ravel() + W["shift"]).sum())
+    value = M * n * B.nnz / (ms / 1e3)
+    sb = step_bytes(B.d, B.nnz, M, 2, 4)
+    avg = kms / max(kn, 1)
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        deg = 10
+        log(f"cpu baseline (oracle Taylor comparator, probe 0 at degree {deg})")
+        rg = ld.ld_logdet_taylor(D, a, b, deg, M, seed, want_probes=True)
+        t1 = time.perf_counter()
+        o = oracle.logdet_taylor(B, a, b, deg, 1, seed=seed, ids=np.array([0]), shift=W["shift"])
+        secs = time.perf_counter() - t1
+        cpu = {"value": deg * B.nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
+               "sample": f"probe 0 at degree {deg} of the Taylor comparator on the full grid, single-threaded FP64 C "
+                         f"oracle, {secs:.1f} s"}
+        parity = abs(rg["s"][0] - o["s"][0]) / max(abs(o["s"][0]), 1e-3 * B.d)
+    out = _line(args, W, value, ms, "f32",
+                {"d": B.d, "nnz": B.nnz, "M": M, "n": n, "values": "bf16", "step": "Taylor comparator forward"},
+                sb / (avg / 1e3) / 1e9, avg, sb, "step kernel", cpu,
+                {"logdet_exact": exact, "taylor": r["logdet"], "taylor_rel_err": abs(r["logdet"] - exact) / abs(exact),
+                 "taylor_truncation_bound_rel": abs(r["poly_bound"] / exact),
+                 "chebyshev": rc["logdet"], "chebyshev_rel_err": abs(rc["logdet"] - exact) / abs(exact),
+                 "oracle_parity_rel_probe0_deg10": parity, "parity_tolerance": 1e-4})
+    _finish(out, copy_gbps)
+
+
+def bench_lanczos(args, W, copy_gbps) -> None:
+    """The spectral estimate that feeds the bounds (Section 3.2): FP64 Lanczos on the main
+    workload's matrix, one product per step (M = 1)."""
+    import numpy as np
+    import torch
+
+    import paper_1503_06394_amd as ld
+
+    B, iters, seed = W["B"], W["iters"], W["seed"]
+    D = ld.DeviceCSR.from_host(B, device="cuda:0")
+    for _ in range(args.warmup):
+        ld.ld_spectral_estimate(D, iters=iters, seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lo, hi = ld.ld_spectral_estimate(D, iters=iters, seed=seed)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = iters * B.nnz / (ms / 1e3)
+    # per Lanczos step: the product (matrix, x gathered, y written) and three FP64 vector passes
+    per_step = B.nnz * 8 + (B.d + 1) * 8 + 2 * B.d * 8 + 7 * B.d * 8
+    achieved = per_step / (ms / iters / 1e3) / 1e9
+    ga, gb = ld.ld_gershgorin(D)
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        k = 25
+        log(f"cpu baseline (oracle Lanczos, {k} steps)")
+        glo, ghi = ld.ld_spectral_estimate(D, iters=k, seed=seed)
+        t1 = time.perf_counter()
+        olo, ohi, _, _ = oracle.lanczos_extremes(B, k, seed=seed)
+        secs = time.perf_counter() - t1
+        cpu = {"value": k * B.nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+               "host_cpu": host_cpu(),
+               "sample": f"{k} Lanczos steps on the full matrix, FP64 numpy oracle, {secs:.1f} s"}
+        parity = max(abs(glo - olo) / abs(olo), abs(ghi - ohi) / abs(ohi))
+    out = _line(args, W, value, ms, "f64",
+                {"d": B.d, "nnz": B.nnz, "M": 1, "iters": iters, "step": "300 Lanczos steps and the tridiagonal's "
+                 "extreme eigenvalues"},
+                achieved, ms / iters, per_step, "one Lanczos step (product, dots, update)", cpu,
+                {"ritz_lo": lo, "ritz_hi": hi, "gershgorin": [ga, gb],
+                 "oracle_parity_rel_25_steps": parity, "parity_tolerance": 1e-9})
+    _finish(out, copy_gbps)
 
 
 if __name__ == "__main__":
