@@ -1928,7 +1928,8 @@ static int spectral_estimate_impl(const ld_csr* B, const ld_csr* Ct_in, int gram
   Carve c;
   for (int i = 0; i < 4; ++i) c.take((size_t)d * 8);
   c.take(kDotScratch * 8);
-  c.take(8);
+  c.take((size_t)iters * 8);  // alpha_j
+  c.take((size_t)iters * 8);  // beta_j^2
   const bool build_t = gram && !Ct_in;
   if (build_t) {
     c.take((size_t)(d + 1) * 8);
@@ -1946,7 +1947,8 @@ static int spectral_estimate_impl(const ld_csr* B, const ld_csr* Ct_in, int gram
   for (auto& p : buf) p = static_cast<double*>(cv.take((size_t)d * 8));
   double* tmp = static_cast<double*>(cv.take((size_t)d * 8));
   double* part = static_cast<double*>(cv.take(kDotScratch * 8));
-  double* scal = static_cast<double*>(cv.take(8));
+  double* al_dev = static_cast<double*>(cv.take((size_t)iters * 8));
+  double* bb_dev = static_cast<double*>(cv.take((size_t)iters * 8));
   ld_csr Ct{};
   if (gram) {
     if (Ct_in) {
@@ -1986,19 +1988,13 @@ static int spectral_estimate_impl(const ld_csr* B, const ld_csr* Ct_in, int gram
     L.d0 = D;
     return launch_step(L, 1, valt, SRC_BUF, with_shift ? SRC_SAME : SRC_NONE, SRC_NONE, MU_NONE, s);
   };
-  auto dot = [&](const double* x, const double* y, double* out) -> int {
-    LD_HIP(launch_dot(x, y, d, part, scal, s));
-    LD_HIP(hipMemcpyAsync(out, scal, 8, hipMemcpyDeviceToHost, s));
-    LD_HIP(hipStreamSynchronize(s));
-    return LD_OK;
-  };
   double* vprev = buf[0];
   double* v = buf[1];
   double* w = buf[2];
   LD_HIP(launch_fill_zero(vprev, (size_t)d * 8, s));
   LD_HIP(launch_seed(v, 1, nullptr, nullptr, nullptr, 1.0 / std::sqrt((double)d), 0.0, 0.0, 0.0, seed, d, 1, s));
-  std::vector<double> al, b2{0.0};
-  double beta = 0.0;
+  // every step is queued at once: alpha_j and beta_j^2 stay in device memory (al_dev, bb_dev)
+  // and the host reads them after the last step
   for (int j = 0; j < iters; ++j) {
     if (gram) {
       LD_HIP(product(B, v, tmp, false));
@@ -2006,19 +2002,23 @@ static int spectral_estimate_impl(const ld_csr* B, const ld_csr* Ct_in, int gram
     } else {
       LD_HIP(product(B, v, w, true));
     }
-    double alpha = 0.0;
-    rc = dot(w, v, &alpha);
-    if (rc) return rc;
-    LD_HIP(launch_lanczos_update(w, v, vprev, alpha, beta, d, s));
-    al.push_back(alpha);
-    double bb = 0.0;
-    rc = dot(w, w, &bb);
-    if (rc) return rc;
-    if (!(bb > 0.0) || !std::isfinite(bb)) break;  // invariant subspace found (or breakdown)
-    beta = std::sqrt(bb);
-    if (j + 1 < iters) b2.push_back(bb);
-    LD_HIP(launch_scale_vec(w, 1.0 / beta, d, vprev, s));  // v_{j+1} into the old v_{j-1} slot
-    std::swap(vprev, v);                                  // v_{j-1} <- v_j, v_j <- v_{j+1}
+    LD_HIP(launch_dot(w, v, d, part, al_dev + j, s));  // alpha_j = w^T v
+    LD_HIP(launch_lanczos_update(w, v, vprev, al_dev + j, j > 0 ? bb_dev + j - 1 : nullptr, d, s));
+    LD_HIP(launch_dot(w, w, d, part, bb_dev + j, s));   // beta_j^2
+    LD_HIP(launch_lanczos_scale(w, bb_dev + j, d, vprev, s));  // v_{j+1} into the old v_{j-1} slot
+    std::swap(vprev, v);                                       // v_{j-1} <- v_j, v_j <- v_{j+1}
+  }
+  std::vector<double> alh(iters), bbh(iters);
+  LD_HIP(hipMemcpyAsync(alh.data(), al_dev, (size_t)iters * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipMemcpyAsync(bbh.data(), bb_dev, (size_t)iters * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  // the tridiagonal matrix ends at the first step whose residual vanishes (an invariant subspace)
+  // or breaks down; the steps queued after it only carried non-finite values
+  std::vector<double> al, b2{0.0};
+  for (int j = 0; j < iters; ++j) {
+    al.push_back(alh[j]);
+    if (!(bbh[j] > 0.0) || !std::isfinite(bbh[j])) break;
+    if (j + 1 < iters) b2.push_back(bbh[j]);
   }
   b2.resize(al.size());
   *lo = tridiag_eig(al, b2, 0);

@@ -169,12 +169,14 @@ hipError_t launch_scale_grad(const void* Gacc, int acc_f64, int64_t nnz, double 
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-// Lanczos helpers (FP64): *out = x^T y (part: 512 doubles of scratch); w -= alpha v + beta u;
-// y = c x.
+// FP64 dot product into device memory: *out = x^T y (part: 512 doubles of scratch).
 hipError_t launch_dot(const double* x, const double* y, int64_t n, double* part, double* out, hipStream_t s);
-hipError_t launch_lanczos_update(double* w, const double* v, const double* u, double alpha, double beta, int64_t n,
-                                 hipStream_t s);
-hipError_t launch_scale_vec(const double* x, double c, int64_t n, double* y, hipStream_t s);
+
+// Lanczos steps with coefficients that stay in device memory (no host round trip per step):
+// w <- w - (*alpha) v - sqrt(*bb_prev) u (bb_prev null: no u term);  y <- x / sqrt(*bb).
+hipError_t launch_lanczos_update(double* w, const double* v, const double* u, const double* alpha,
+                                 const double* bb_prev, int64_t n, hipStream_t s);
+hipError_t launch_lanczos_scale(const double* x, const double* bb, int64_t n, double* y, hipStream_t s);
 
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

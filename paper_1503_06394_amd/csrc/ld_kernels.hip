@@ -785,18 +785,6 @@ __global__ void __launch_bounds__(256) dot_partials_kernel(const double* x, cons
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// w <- w - alpha v - beta u
-__global__ void __launch_bounds__(256) lanczos_update_kernel(double* w, const double* v, const double* u, double alpha,
-                                                             double beta, int64_t n) {
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256)
-    w[t] = w[t] - alpha * v[t] - beta * u[t];
-}
-
-// y <- c x
-__global__ void __launch_bounds__(256) scale_vec_kernel(const double* x, double c, int64_t n, double* y) {
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) y[t] = c * x[t];
-}
-
 __global__ void __launch_bounds__(256) probes_kernel(uint64_t seed, int M, int64_t rows, int8_t* out) {
   const int64_t total = rows * (int64_t)M;
   for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total; x += (int64_t)gridDim.x * 256) {
@@ -1194,17 +1182,6 @@ constexpr int kDotBlocks = 512;
 hipError_t launch_dot(const double* x, const double* y, int64_t n, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(dot_partials_kernel, dim3(kDotBlocks), dim3(256), 0, s, x, y, n, part);
   hipLaunchKernelGGL(sum_doubles_kernel, dim3(1), dim3(1024), 0, s, part, (int64_t)kDotBlocks, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_lanczos_update(double* w, const double* v, const double* u, double alpha, double beta, int64_t n,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(lanczos_update_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, w, v, u, alpha, beta, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale_vec(const double* x, double c, int64_t n, double* y, hipStream_t s) {
-  hipLaunchKernelGGL(scale_vec_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, c, n, y);
   return hipGetLastError();
 }
 

@@ -1,6 +1,9 @@
 // Preparation kernels for gfx950 that run once per matrix, before the estimator's loop (Han,
 // Malioutov & Shin, arXiv 1503.06394): Gershgorin bounds for a whole batch of matrices in one
-// launch, and the Laplacian minor used to count spanning trees (Section 3.3).
+// launch, the Lanczos steps of the spectral estimate (the bounds Section 3.2 asks for), and the
+// Laplacian minor used to count spanning trees (Section 3.3).
+#include <algorithm>
+
 #include "ld_internal.h"
 
 namespace ld {
@@ -149,6 +152,43 @@ hipError_t launch_laplacian_minor(const int64_t* row_ptr, const int32_t* col, in
   else
     hipLaunchKernelGGL(laplacian_minor_kernel<float>, dim3(nblocks), dim3(256), 0, s, row_ptr, col, d, hub, deg_hub,
                        rp_out, col_out, static_cast<float*>(val_out), max_part, bad_part);
+  return hipGetLastError();
+}
+
+// --- Lanczos steps with device-resident coefficients ---
+//
+// alpha_j = w^T v and beta_j^2 = w^T w are written to device memory by the dot-product kernel;
+// these kernels read them there, so a whole run of steps is queued without waiting for the host.
+// The arithmetic is that of host-side coefficients: w - alpha v - beta u with beta = sqrt(bb), and
+// (1 / sqrt(bb)) x, every operation IEEE-rounded in FP64.
+__global__ void __launch_bounds__(256) lanczos_update_kernel(double* w, const double* v, const double* u,
+                                                             const double* alpha, const double* bb_prev, int64_t n) {
+  const double a = *alpha;
+  const double b = bb_prev ? sqrt(*bb_prev) : 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256)
+    w[t] = w[t] - a * v[t] - b * u[t];
+}
+
+__global__ void __launch_bounds__(256) lanczos_scale_kernel(const double* x, const double* bb, int64_t n, double* y) {
+  const double c = 1.0 / sqrt(*bb);
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) y[t] = c * x[t];
+}
+
+static unsigned lanczos_grid(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+hipError_t launch_lanczos_update(double* w, const double* v, const double* u, const double* alpha,
+                                 const double* bb_prev, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lanczos_update_kernel, dim3(lanczos_grid(n)), dim3(256), 0, s, w, v, u, alpha, bb_prev, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_scale(const double* x, const double* bb, int64_t n, double* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lanczos_scale_kernel, dim3(lanczos_grid(n)), dim3(256), 0, s, x, bb, n, y);
   return hipGetLastError();
 }
 
