@@ -120,3 +120,24 @@ def test_spectral_estimate_matches_oracle_lanczos(ld, oracle_lib, case, iters):
     lo, hi = ld.ld_spectral_estimate(dev(B, shift=shift), iters=iters, gram=gram, seed=9)
     olo, ohi, _, _ = oracle_lib.lanczos_extremes(B, iters, seed=9, shift=shift, gram=gram)
     assert rel(lo, olo) <= 1e-9 and rel(hi, ohi) <= 1e-9
+
+
+@pytest.mark.parametrize("gram", [False, True])
+def test_spectral_estimate_invariant_subspace(ld, gram):
+    """B = 2.5 I with d = 4096, so that the start vector's entries +-1/64 and every product are
+    exact: the first residual vanishes exactly, the steps queued after it only carry non-finite
+    values, and the estimate is the single Ritz value (2.5, or 6.25 for B^T B)."""
+    B = synth.diagonal_matrix(np.full(4096, 2.5), "f64")
+    say(f"spectral estimate invariant subspace gram={gram}")
+    lo, hi = ld.ld_spectral_estimate(dev(B), iters=20, gram=gram, seed=4)
+    want = 6.25 if gram else 2.5
+    assert lo == want and hi == want
+
+
+def test_spectral_estimate_near_invariant_subspace(ld):
+    """d = 5000: the residual of the first step is rounding noise, not zero; the process goes on
+    inside the same eigenspace and the Ritz values stay at 2.5 to rounding."""
+    B = synth.diagonal_matrix(np.full(5000, 2.5), "f64")
+    say("spectral estimate near-invariant subspace")
+    lo, hi = ld.ld_spectral_estimate(dev(B), iters=20, seed=4)
+    assert abs(lo - 2.5) <= 1e-12 and abs(hi - 2.5) <= 1e-12
