@@ -91,7 +91,8 @@ typedef struct {
                                  W_k when that fits (the workspace given, or 40% of free device
                                  memory), else every ceil(sqrt(steps)) */
     int32_t tile;             /* kernel shape: 0 = autotuned, > 0 = rows per workgroup */
-    int32_t probe_tile;       /* kernel shape: 0 = autotuned, > 0 = probes per pass over the matrix */
+    int32_t probe_tile;       /* kernel shape: 0 = autotuned, > 0 = probes per pass over the matrix
+                                 (the estimators; the gradient's passes are fixed) */
     int32_t timing;           /* 1 = time recurrence-step kernels with HIP events on `stream` */
     int32_t plain_recurrence; /* 1 = one sparse product per degree (Algorithm 1's loop as written);
                                  0 = ceil(n/2) products: moments 2k and 2k+1 from the Chebyshev
