@@ -1713,7 +1713,8 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int valt = valt_of(Bs[0].dtype);
   const int vec_f64 = vec_f64_of(opt, valt);
-  Shape sh = base_shape(vec_f64, M);
+  const int Mr = padded_probes(M, vec_f64, opt);  // probes the graph runs; results use the first M
+  Shape sh = base_shape(vec_f64, Mr);
   const int rpi = rows_per_iter(sh);
   int64_t tot_d = 0, tot_nnz = 0;
   for (int i = 0; i < count; ++i) {
@@ -1727,7 +1728,7 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
   const bool tune = !fixed_tile && autotune_enabled() && tot_d >= 65536;
 
   const bool pair = use_pairs(opt);
-  std::vector<double> key = {(double)count, (double)M, (double)(seed >> 32), (double)(seed & 0xffffffffu),
+  std::vector<double> key = {(double)count, (double)Mr, (double)(seed >> 32), (double)(seed & 0xffffffffu),
                              (double)vec_f64, fixed_tile ? (double)sh.tile_rows : 0.0, pair ? 1.0 : 0.0};
   for (int i = 0; i < count; ++i) {
     const double v[] = {bits_of(Bs[i].row_ptr), bits_of(Bs[i].col_idx), bits_of(Bs[i].values), (double)Bs[i].rows,
@@ -1747,14 +1748,14 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
     std::unique_ptr<BatchEntry> ent;
     if (!tune) {
       ent = std::make_unique<BatchEntry>();
-      int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, pair, sh, *ent);
+      int rc = build_batch(count, Bs, a, b, n, Mr, seed, vec_f64, valt, pair, sh, *ent);
       if (rc) return rc;
     } else {
       // The batch's autotuner: build the graph for each candidate shape (the full probe block at
       // three tile heights, narrower probe tiles at the tallest), time one replay of each after a
       // warm-up replay, keep the fastest.  Runs once per batch signature; later calls replay it.
       std::vector<Shape> cands;
-      const std::vector<Shape> shapes = shape_candidates(vec_f64, M);
+      const std::vector<Shape> shapes = shape_candidates(vec_f64, Mr);
       for (size_t si = 0; si < shapes.size(); ++si) {
         const std::vector<int> tiles = tile_candidates(shapes[si], tot_d, tot_nnz);
         for (size_t ti = 0; ti < tiles.size() && (si == 0 || ti == 0); ++ti) {
@@ -1766,7 +1767,7 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
       float best = INFINITY;
       for (const Shape& c : cands) {
         auto cand = std::make_unique<BatchEntry>();
-        int rc = build_batch(count, Bs, a, b, n, M, seed, vec_f64, valt, pair, c, *cand);
+        int rc = build_batch(count, Bs, a, b, n, Mr, seed, vec_f64, valt, pair, c, *cand);
         if (rc) {
           if (ent) continue;  // keep the best graph built so far (e.g. out of memory for this one)
           return rc;
@@ -1809,7 +1810,7 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
   if (E->exec) LD_HIP(hipGraphLaunch(E->exec, s));
   LD_HIP(tm.mark(T_STEP));
   const int kmax = E->kmax;
-  std::vector<double> mu_all((size_t)count * M * (kmax + 1));
+  std::vector<double> mu_all((size_t)count * Mr * (kmax + 1));
   if (kmax > 0) LD_HIP(hipMemcpyAsync(mu_all.data(), E->mu_dev, mu_all.size() * 8, hipMemcpyDeviceToHost, s));
   LD_HIP(hipStreamSynchronize(s));
   int status = LD_OK;
@@ -1817,7 +1818,7 @@ static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a
     const int rows = partial_rows(n[i], pair);
     std::vector<double> red((size_t)M * std::max(rows, 1), 0.0);
     for (int j = 0; j < M; ++j)
-      for (int r = 0; r < rows; ++r) red[(size_t)j * rows + r] = mu_all[((size_t)i * M + j) * (kmax + 1) + r + 1];
+      for (int r = 0; r < rows; ++r) red[(size_t)j * rows + r] = mu_all[((size_t)i * Mr + j) * (kmax + 1) + r + 1];
     std::vector<double> mu((size_t)M * (n[i] + 1));
     assemble_moments(red, rows, pair, n[i], M, Bs[i].rows, mu);
     ld_result r{};

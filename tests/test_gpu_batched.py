@@ -130,9 +130,10 @@ def test_graph_cache_evicts_least_recently_used(ld, oracle_lib):
     ld.ld_clear_cache()
 
 
-@pytest.mark.parametrize("M", [1, 100, 300])
+@pytest.mark.parametrize("M", [1, 4, 10, 24, 100, 300])
 def test_batched_probe_counts(ld, oracle_lib, M):
-    """Probe blocks of one lane, of one wide tile and of several probe tiles per pass (M = 300)."""
+    """Probe blocks of one lane, widened blocks (4, 10, 24 run as 8, 16, 32 probes, the extra ones
+    dropped), one wide tile and several probe tiles per pass (M = 300)."""
     mats = _batch(4, "f32", d_max=3000, seed0=640)
     ab = [oracle_lib.gershgorin(B) for B in mats]
     ns = [B.meta["n"] for B in mats]
@@ -142,6 +143,8 @@ def test_batched_probe_counts(ld, oracle_lib, M):
     for i, B in enumerate(mats):
         o = oracle_lib.logdet(B, ab[i][0], ab[i][1], ns[i], M, seed=9 + i)
         assert rel(res[i]["logdet"], o["gamma"], FLOOR * B.d) <= 1e-4, i
+        if M > 1:  # one probe has no standard error
+            assert rel(res[i]["std_err"], o["std_err"]) <= 1e-3, i
 
 
 @pytest.mark.parametrize("ns", [[0], [0, 1, 2, 5], [1, 1], [7]])
