@@ -38,7 +38,7 @@ class _Probes(ctypes.Structure):
 
 def build(verbose: bool = False) -> str:
     """Compile ``liboracle.so`` with gcc (plain C99, -O2, no fast-math)."""
-    from .build import build as _build
+    from .make_lib import build as _build
 
     return _build(verbose=verbose)
 

@@ -248,6 +248,16 @@ static void pd_matvec(const void *vctx, const double *x, double *y)
         y[i] = (y[i] + p->shift * x[i]) * p->scale;
 }
 
+/* y = (B + shift I)^T x / (a + b): the transposed operator, which the reverse-mode
+ * recurrence of the gradient applies. */
+static void pd_matvec_t(const void *vctx, const double *x, double *y)
+{
+    const pd_ctx *p = (const pd_ctx *)vctx;
+    csr_mv_t(p->B, x, y);
+    for (int64_t i = 0; i < p->B->d; ++i)
+        y[i] = (y[i] + p->shift * x[i]) * p->scale;
+}
+
 static int check_csr(const ldo_csr *B)
 {
     if (!B || B->d < 0 || B->nnz < 0 || !B->row_ptr || (B->nnz > 0 && (!B->col || !B->val)))
@@ -378,12 +388,13 @@ int ldo_logabsdet(const ldo_csr *C, double smin, double smax, int n, int m,
 /* Gradient (not in the paper; reverse mode through Algorithm 1)              */
 /* ------------------------------------------------------------------------- */
 /* The recurrence evaluates v^T p(X) v for any square X, so this is the derivative with
- * respect to independent entries; at a symmetric X it is itself symmetric, i.e. it is also
- * the derivative along symmetric perturbations. */
+ * respect to independent entries, for symmetric and non-symmetric B alike; at a symmetric X
+ * it is itself symmetric, i.e. it is also the derivative along symmetric perturbations. */
 /*
  * Per probe v the estimate is s = v^T u with u = sum_k c_k w_k, w_0 = v, w_1 = X v and
- * w_k = 2 X w_{k-1} - w_{k-2}.  With y_k = ds/dw_k (X symmetric):
- *   y_n = c_n v,  y_{n-1} = c_{n-1} v + 2 X y_n,  y_k = c_k v + 2 X y_{k+1} - y_{k+2},
+ * w_k = 2 X w_{k-1} - w_{k-2}.  w_k enters s directly (c_k v^T w_k), through w_{k+1} (via 2X)
+ * and through w_{k+2} (via -1), so the adjoints y_k = ds/dw_k obey
+ *   y_n = c_n v,  y_{n-1} = c_{n-1} v + 2 X^T y_n,  y_k = c_k v + 2 X^T y_{k+1} - y_{k+2},
  * and ds/dX = y_1 v^T + sum_{k=2}^{n} 2 y_k w_{k-1}^T.
  * X = ((a + b) I - 2 (B + shift I)) / (b - a), so dX/dB_ij = -2/(b - a) e_i e_j^T and
  * dX/dshift = -2/(b - a) I.  The lift d log(a + b) does not depend on B (a, b fixed).
@@ -428,7 +439,7 @@ int ldo_logdet_grad(const ldo_csr *B, double shift, double a, double b, int n, i
         G += sv / m;
         if (n == 0)
             continue;
-        /* backward: y_{n+1} = 0, y_n = c_n v, y_k = c_k v + 2 X y_{k+1} - y_{k+2} */
+        /* backward: y_{n+1} = 0, y_n = c_n v, y_k = c_k v + 2 X^T y_{k+1} - y_{k+2} */
         double *ynp1 = Y + (int64_t)(n + 1) * (d + 1);
         for (int64_t r = 0; r < d; ++r)
             ynp1[r] = 0.0;
@@ -437,7 +448,7 @@ int ldo_logdet_grad(const ldo_csr *B, double shift, double a, double b, int n, i
             yn[r] = c[n] * v[r];
         for (int k = n - 1; k >= 1; --k) {
             double *yk = Y + (int64_t)k * (d + 1);
-            apply_X(d, pd_matvec, &ctx, delta, Y + (int64_t)(k + 1) * (d + 1), tmp2, yk);
+            apply_X(d, pd_matvec_t, &ctx, delta, Y + (int64_t)(k + 1) * (d + 1), tmp2, yk); /* X^T y */
             for (int64_t r = 0; r < d; ++r)
                 yk[r] = c[k] * v[r] + 2.0 * yk[r] - Y[(int64_t)(k + 2) * (d + 1) + r];
         }

@@ -97,7 +97,8 @@ int ldo_logabsdet(const ldo_csr *C, double smin, double smax, int n, int m,
 
 /* Gradient of the ldo_logdet estimate with respect to every stored entry of B (and to the
  * diagonal shift), at fixed a, b and probes, by reverse-mode differentiation of Algorithm 1's
- * recurrence (entries treated as independent; for symmetric B the result is symmetric).
+ * recurrence: the adjoint recurrence applies X^T, so the result is the derivative with respect
+ * to each stored entry on its own, for any square B (for symmetric B it is symmetric).
  * grad: nnz entries; grad_shift: nullable; gamma: nullable. */
 int ldo_logdet_grad(const ldo_csr *B, double shift, double a, double b, int n, int m,
                     const ldo_probes *probes, double *grad, double *grad_shift, double *gamma);

@@ -346,6 +346,57 @@ def test_theorem2_guarantee(oracle_lib):
         assert abs(exact - g) <= eps * d
 
 
+def test_lemma7_value_on_the_32_grid(oracle_lib):
+    """Lemma 7 on the 32x32 grid + 0.1 I with [a, b] = [0.1, 8.1] (delta = a/(a+b)), n = 30, d = 1024:
+    the bound is 5,525 (to the four figures quoted for this configuration, computed when the
+    configurations were surveyed)."""
+    assert abs(oracle_lib.lemma_bound(0.1 / 8.2, 30, 1024) - 5525.0) < 0.5
+
+
+@pytest.mark.parametrize("delta", [0.012195121951219514, 0.05, 0.1, 0.3, 0.45])
+def test_lemma7_rate_is_the_ellipse_parameter(oracle_lib, delta):
+    """Lemma 7's bound decays by 1/K per degree and grows linearly in d, where K is the sum of
+    the semi-axes of the ellipse with foci +-1 and semi-major axis 1/(1 - delta) (Section 4.1,
+    Theorem 6): K = 1/(1-delta) + sqrt(1/(1-delta)^2 - 1), the form before the paper simplifies it."""
+    ax = 1.0 / (1.0 - delta)
+    K = ax + math.sqrt(ax * ax - 1.0)
+    for n in (0, 1, 7, 40):
+        r = oracle_lib.lemma_bound(delta, n + 1, 5) / oracle_lib.lemma_bound(delta, n, 5)
+        assert abs(r - 1.0 / K) < 1e-13
+        assert abs(oracle_lib.lemma_bound(delta, n, 14) - 2.0 * oracle_lib.lemma_bound(delta, n, 7)) <= \
+            1e-14 * oracle_lib.lemma_bound(delta, n, 14)
+    # n = 0: Theorem 6's constant 4M/(K - 1) with M = 5 log(2(1/delta - 1)), per unit of d
+    M = 5.0 * math.log(2.0 * (1.0 / delta - 1.0))
+    assert abs(oracle_lib.lemma_bound(delta, 0, 1) - 4.0 * M / (K - 1.0)) < 1e-12 * abs(4.0 * M / (K - 1.0))
+
+
+@pytest.mark.parametrize("eps,zeta,delta", [(0.01, 0.5, 0.1), (0.1, 0.2, 0.3), (0.05, 0.01, 0.02)])
+def test_theorem1_requirements_from_the_proof(oracle_lib, eps, zeta, delta):
+    """Theorem 1's two requirements, tied to the steps of its proof (Section 4.3):
+    the degree is where Lemma 7's bound per unit of d reaches (eps/2) log(1/(1 - delta)) (eq. (3));
+    the sample count is Theorem 8's requirement 6 eps0^-2 log(2/zeta0) at eps0 = eps/3 (eq. (4))."""
+    m_req, n_req = oracle_lib.thm1_params(eps, zeta, delta)
+    assert abs(oracle_lib.lemma_bound(delta, 0, 1) / ((1.0 / ((1.0 / (1.0 - delta)) + math.sqrt(
+        (1.0 / (1.0 - delta)) ** 2 - 1.0))) ** -n_req) - eps / 2.0 * math.log(1.0 / (1.0 - delta))) < \
+        1e-12 * eps * math.log(1.0 / (1.0 - delta))
+    assert abs(m_req - 6.0 / (eps / 3.0) ** 2 * math.log(2.0 / zeta)) < 1e-12 * m_req
+
+
+@pytest.mark.parametrize("eps,kappa,zeta", [(0.2, math.sqrt(2.0), 0.2), (0.05, 10.0, 0.05), (0.3, 3.0, 0.1)])
+def test_theorem2_requirements_from_theorem1(oracle_lib, eps, kappa, zeta):
+    """Theorem 2's M and N follow from Theorem 1 applied to B = C^T C/(smin^2 + smax^2), whose
+    delta is 1/(1 + kappa^2) and whose |log det B| is at most d log(1 + kappa^2) (its proof):
+    N(eps, kappa) is Theorem 1's degree at eps/log(1 + kappa^2), and M(eps, kappa, zeta) is Theorem 1's
+    sample count at 2 eps/log(1 + kappa^2), 13.5 log(1 + kappa^2)^2 eps^-2 log(2/zeta), rounded up to 14."""
+    Mv, Nv = oracle_lib.thm2_params(eps, kappa, zeta)
+    L = math.log(1.0 + kappa ** 2)
+    delta = 1.0 / (1.0 + kappa ** 2)
+    _, n1 = oracle_lib.thm1_params(eps / L, zeta, delta)
+    m1, _ = oracle_lib.thm1_params(2.0 * eps / L, zeta, delta)
+    assert abs(Nv - n1) < 1e-12 * abs(n1)
+    assert abs(Mv - m1 * 14.0 / 13.5) < 1e-12 * Mv
+
+
 def test_theorem1_degree_example():
     """Section 3.1 quotes n = 14 for delta = 0.1, eps = 0.01; the printed formula gives 25.95,
     i.e. n = 26 (a discrepancy in the paper, recorded rather than enforced)."""
@@ -441,6 +492,53 @@ def test_gradient_vs_central_differences(oracle_lib):
     fp = oracle_lib.logdet(B, a, b, n, m, seed=seed, shift=shift + h)["gamma"]
     fm = oracle_lib.logdet(B, a, b, n, m, seed=seed, shift=shift - h)["gamma"]
     assert abs((fp - fm) / (2 * h) - g["grad_shift"]) <= 1e-7 * max(1.0, abs(g["grad_shift"]))
+
+
+def test_gradient_vs_central_differences_nonsymmetric(oracle_lib):
+    """P10 off the symmetric premise: for a non-symmetric B the recurrence still evaluates
+    v^T p(X) v, and its derivative with respect to each stored entry on its own is what central
+    differences of the estimate give.  The adjoint recurrence must apply X^T: with X in its
+    place the entries of this matrix are off by up to about 200 %."""
+    C = synth.random_nonsingular(24, per_row=3, mseed=21, diag_add=3.0, storage="f64")
+    a, b, n, m, seed, shift = 0.5, 6.0, 9, 3, 17, 0.05
+    g = oracle_lib.logdet_grad(C, a, b, n, m, seed=seed, shift=shift)
+    base = oracle_lib.logdet(C, a, b, n, m, seed=seed, shift=shift)["gamma"]
+    assert abs(g["gamma"] - base) < 1e-12 * abs(base)
+    h = 1e-5
+    fds = np.empty(C.nnz)
+    for t in range(C.nnz):
+        vp = C.val.copy(); vp[t] += h
+        vm = C.val.copy(); vm[t] -= h
+        fp = oracle_lib.logdet(synth.CSR(C.d, C.row_ptr, C.col, vp), a, b, n, m, seed=seed, shift=shift)["gamma"]
+        fm = oracle_lib.logdet(synth.CSR(C.d, C.row_ptr, C.col, vm), a, b, n, m, seed=seed, shift=shift)["gamma"]
+        fds[t] = (fp - fm) / (2 * h)
+    scale = np.abs(fds).max()
+    np.testing.assert_allclose(g["grad"], fds, rtol=1e-6, atol=1e-8 * scale)
+    # the matrix really is off the symmetric set
+    Cd = synth.dense(C)
+    assert np.abs(Cd - Cd.T).max() > 0.5
+    fp = oracle_lib.logdet(C, a, b, n, m, seed=seed, shift=shift + h)["gamma"]
+    fm = oracle_lib.logdet(C, a, b, n, m, seed=seed, shift=shift - h)["gamma"]
+    assert abs((fp - fm) / (2 * h) - g["grad_shift"]) <= 1e-7 * max(1.0, abs(g["grad_shift"]))
+
+
+def test_gradient_enumeration_nonsymmetric_trace_derivative(oracle_lib):
+    """Averaged over all 2^d sign patterns the estimate is tr p_n(B) for any square B, and
+    d tr p_n(B)/dB_ij = [p_n'(B)]_ji; for a non-symmetric B that is the transpose of p_n'(B), which
+    a dense eigendecomposition (complex eigenvalues, numpy) gives independently."""
+    C = synth.random_nonsingular(9, per_row=2, mseed=13, diag_add=3.0, storage="f64")
+    Cd = synth.dense(C)
+    assert np.abs(Cd - Cd.T).max() > 0.1
+    a, b, n = 0.5, 6.0, 7
+    V = _ref.all_sign_vectors(C.d)
+    g = oracle_lib.logdet_grad(C, a, b, n, V.shape[0], V=V)
+    lam, Q = np.linalg.eig(Cd)
+    D = ((Q * _ref.dp_n_on_interval(a, b, n, lam)) @ np.linalg.inv(Q)).real
+    rows = C.row_of_entry()
+    np.testing.assert_allclose(g["grad"], D[C.col, rows], rtol=1e-9, atol=1e-10 * np.abs(D).max())
+    assert abs(g["grad_shift"] - np.trace(D)) < 1e-10 * abs(np.trace(D))
+    # the transposed reading differs here, so the pin tells the two apart
+    assert np.abs(D[C.col, rows] - D[rows, C.col]).max() > 1e-2 * np.abs(D).max()
 
 
 def test_gradient_enumeration_equals_exact_trace_derivative(oracle_lib):
