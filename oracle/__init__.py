@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# LDO_SANITIZE=1 selects the AddressSanitizer/UBSan build (see make_lib.py for the command line).
+SANITIZE = os.environ.get("LDO_SANITIZE", "0") == "1"
+LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
 
 _lib = None
 
@@ -37,10 +39,11 @@ class _Probes(ctypes.Structure):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile ``liboracle.so`` with gcc (plain C99, -O2, no fast-math)."""
+    """Compile ``liboracle.so`` with gcc (plain C99, -O2, no fast-math), or the sanitizer build
+    ``liboracle_san.so`` when LDO_SANITIZE=1."""
     from .make_lib import build as _build
 
-    return _build(verbose=verbose)
+    return _build(verbose=verbose, sanitize=SANITIZE)
 
 
 def lib():
