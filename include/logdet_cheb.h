@@ -88,13 +88,14 @@ typedef struct {
     int32_t vec_f64;          /* recurrence vectors: 0 = FP64 for FP64 values, else FP32;
                                  1 = FP64; 2 = FP32 */
     int32_t ckpt_stride;      /* gradient: checkpoint every s steps; 0 = automatic: keep every
-                                 W_k when that fits (the workspace given, or 40% of free device
-                                 memory), else every ceil(sqrt(steps)) */
+                                 W_k when that fits (the workspace given, or half of the free
+                                 device memory), else every ceil(sqrt(steps)) */
     int32_t tile;             /* kernel shape: 0 = autotuned, > 0 = rows per workgroup */
     int32_t probe_tile;       /* kernel shape: 0 = autotuned, > 0 = probes per pass over the matrix
                                  (the estimators; the gradient's passes are fixed) */
     int32_t timing;           /* 1 = time recurrence-step kernels with HIP events on `stream` */
-    int32_t plain_recurrence; /* 1 = one sparse product per degree (Algorithm 1's loop as written);
+    int32_t plain_recurrence; /* 1 = one sparse product per degree (Algorithm 1's loop as written;
+                                 the gradient then assumes no symmetry);
                                  0 = ceil(n/2) products: moments 2k and 2k+1 from the Chebyshev
                                  product identities T_2k = 2 T_k^2 - T_0, T_2k+1 = 2 T_k+1 T_k - T_1
                                  (needs a symmetric matrix; same estimate up to rounding) */
@@ -105,7 +106,9 @@ typedef struct {
 /* Algorithm 1 in the [a, b] form: estimate log det(B + diag_shift I) for a symmetric B.
  * Requires 0 < a < b finite, n >= 0, 1 <= M <= 4096.  With vec_f64 = 0 the recurrence runs
  * in FP32 and the moments, coefficients and final sum in FP64.  By default the moments
- * v^T T_k(At) v come from ceil(n/2) sparse products (see ld_opts.plain_recurrence). */
+ * v^T T_k(At) v come from ceil(n/2) sparse products (see ld_opts.plain_recurrence), which
+ * assumes B = B^T (not checked); plain_recurrence = 1 evaluates Algorithm 1's recurrence as
+ * written, the same v^T p(At) v for any square B. */
 int ld_logdet_cheb(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
                    const ld_opts *opt, void *stream, ld_result *out);
 
@@ -130,18 +133,28 @@ int ld_logdet_taylor(const ld_csr *B, double a, double b, int n, int M, uint64_t
                      const ld_opts *opt, void *stream, ld_result *out);
 
 /* Gradient of the ld_logdet_cheb estimate (same B, a, b, n, M, seed, with a and b held
- * fixed) with respect to every stored entry of B, scaled by grad_output.  B is symmetric, so
- * for a symmetric pattern each stored entry receives the derivative along symmetric
- * perturbations,
- *     grad_values[t] = grad_output * (dGamma/dB_ij + dGamma/dB_ji) / 2,  (i, j) = entry t,
- * the same for both orientations of a pair; for a pattern without its transpose the plain
- * recurrence runs and grad_values[t] = grad_output * dGamma/dB_ij.
- * The adjoint recurrence y_k = c_k v + 2 At y_{k+1} - y_{k+2} runs backwards over
- * segments recomputed from checkpoints every ckpt_stride steps.  Probes run in passes of at
- * most 128 (FP32 vectors) or 64 (FP64), whose contributions add up; 1 <= M <= 4096 as for
- * ld_logdet_cheb, with the same probes.  grad_values is a device
- * array of nnz elements of type grad_dtype (LD_F64 or LD_F32).  out->grad_shift receives
- * grad_output * dGamma/d diag_shift and out->logdet the forward estimate. */
+ * fixed) with respect to every stored entry of B, scaled by grad_output (not in the paper: a
+ * reverse-mode derivation of Algorithm 1's recurrence).  Two forms:
+ *  - default, pattern holding its transpose: B is taken as symmetric (Algorithm 1's premise; the
+ *    values are not checked), the forward uses the product identities, and each stored entry
+ *    receives the derivative along symmetric perturbations,
+ *        grad_values[t] = grad_output * (dGamma/dB_ij + dGamma/dB_ji) / 2,  (i, j) = entry t,
+ *    which at a symmetric B equals dGamma/dB_ij;
+ *  - a pattern without its transpose, or opt->plain_recurrence = 1: no symmetry is assumed.  The
+ *    forward runs Algorithm 1's recurrence as written and the adjoint
+ *    y_k = c_k v + 2 At^T y_{k+1} - y_{k+2} runs on B^T, so that
+ *        grad_values[t] = grad_output * dGamma/dB_ij   for each stored entry on its own.
+ * The adjoint runs backwards over segments recomputed from checkpoints every ckpt_stride steps.
+ * Probes run in passes of at most 128 (FP32 vectors) or 64 (FP64), whose contributions add up;
+ * 1 <= M <= 4096 as for ld_logdet_cheb, with the same probes.  grad_values is a device array of
+ * nnz elements of type grad_dtype (LD_F64 or LD_F32).  out->grad_shift receives
+ * grad_output * dGamma/d diag_shift and out->logdet the forward estimate.
+ * Pattern analysis: the first call on a pattern (keyed by device, row_ptr, col_idx, rows, nnz)
+ * learns whether it holds its transpose, and keeps the transposed-entry index (or the pattern of
+ * B^T) in library device memory until ld_clear_cache (at most 8 patterns, least recently used
+ * dropped); only that first call synchronises before the forward.  Every call also hashes the
+ * pattern on the device; if the hash no longer matches (the arrays were rewritten in place), the
+ * pattern is analysed again and the call repeated before it returns. */
 int ld_logdet_cheb_grad(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
                         double grad_output, void *grad_values, int grad_dtype,
                         const ld_opts *opt, void *stream, ld_result *out);
@@ -237,8 +250,8 @@ size_t ld_workspace_bytes(const ld_csr *B, int n, int M, int mode, int vec_f64);
 int ld_copy(void *dst, const void *src, size_t bytes, void *stream, double *ms);
 
 /* Release the library's cached batched graphs (with their device memory), its idle internal
- * workspaces and its autotuning results.  Not safe to call while another thread is inside the
- * library. */
+ * workspaces, the gradient's pattern analyses and its autotuning results.  Not safe to call while
+ * another thread is inside the library. */
 int ld_clear_cache(void);
 
 /* Message for the last non-zero status returned on this thread. */

@@ -921,6 +921,138 @@ int64_t tiles_of(const ld_csr* B, const Shape& sh) {
   return B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
 }
 
+// Pattern analysis of the gradient, cached per (device, row_ptr, col_idx, rows, nnz):
+//  sym:   every stored (i, j) has its transposed entry (j, i) stored as well;
+//  perm:  (sym) the index of the transposed entry of every entry;
+//  rp_t, col_t, src_t: (not sym) the pattern of B^T and, for each of its entries, the entry of B it
+//         comes from;
+//  hash:  the pattern hash at analysis time.  Every gradient call hashes the pattern again on the
+//         device and compares once its results are back (no extra synchronisation); a pattern
+//         rewritten in place at the same addresses is then analysed afresh and the call repeated.
+// Only the first call on a pattern synchronises to learn its symmetry.
+struct PatternInfo {
+  bool sym = false;
+  int64_t* perm = nullptr;
+  int64_t* rp_t = nullptr;
+  int32_t* col_t = nullptr;
+  int64_t* src_t = nullptr;
+  uint64_t hash = 0;
+  uint64_t last_use = 0;
+  ~PatternInfo() {
+    for (void* p : {(void*)perm, (void*)rp_t, (void*)col_t, (void*)src_t})
+      if (p) (void)hipFree(p);
+  }
+};
+
+struct PatternKey {
+  int dev;
+  const void *rp, *col;
+  int64_t rows, nnz;
+  bool operator<(const PatternKey& o) const {
+    return std::tie(dev, rp, col, rows, nnz) < std::tie(o.dev, o.rp, o.col, o.rows, o.nnz);
+  }
+};
+std::mutex g_pat_mu;
+std::map<PatternKey, std::shared_ptr<PatternInfo>> g_pat;  // entries in use are also held by their call
+uint64_t g_pat_clock = 0;
+constexpr size_t kPatternCacheEntries = 8;
+constexpr int kRetryPattern = 1 << 20;  // internal status: repeat the call with a fresh analysis
+
+int pattern_key(const ld_csr* B, PatternKey& k) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  k = PatternKey{dev, B->row_ptr, B->col_idx, B->rows, B->nnz};
+  return LD_OK;
+}
+
+// Device allocation owned by a PatternInfo or by a temporary below.
+template <typename T>
+int dev_alloc(T** p, size_t count, const char* what) {
+  *p = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(LD_ENOMEM, "hipMalloc for %s: %s", what, hipGetErrorString(e));
+  }
+  return LD_OK;
+}
+
+struct DevTmp {
+  void* p = nullptr;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+int analyze_pattern(const ld_csr* B, hipStream_t s, PatternInfo& P) {
+  const int64_t d = B->rows, nnz = B->nnz;
+  DevTmp scratch;  // [0]: missing flag (int), [8]: hash (uint64)
+  LD_HIP(hipMalloc(&scratch.p, 256));
+  int* missing = static_cast<int*>(scratch.p);
+  uint64_t* hash = reinterpret_cast<uint64_t*>(static_cast<char*>(scratch.p) + 8);
+  int rc = dev_alloc(&P.perm, (size_t)nnz, "the transposed-entry index");
+  if (rc) return rc;
+  LD_HIP(launch_fill_zero(missing, sizeof(int), s));
+  LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, nnz, P.perm, missing, s));
+  LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, nnz, hash, s));
+  int miss = 0;
+  LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipMemcpyAsync(&P.hash, hash, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  P.sym = miss == 0;
+  if (P.sym) return LD_OK;
+  (void)hipFree(P.perm);
+  P.perm = nullptr;
+  if ((rc = dev_alloc(&P.rp_t, (size_t)d + 1, "the pattern of B^T")) || (rc = dev_alloc(&P.col_t, (size_t)nnz, "B^T")) ||
+      (rc = dev_alloc(&P.src_t, (size_t)nnz, "B^T")))
+    return rc;
+  DevTmp cursor, scan;
+  LD_HIP(hipMalloc(&cursor.p, (size_t)std::max<int64_t>(d, 1) * 8));
+  LD_HIP(hipMalloc(&scan.p, transpose_scratch_bytes(d)));
+  LD_HIP(launch_transpose(B->row_ptr, B->col_idx, nullptr, valt_of(B->dtype), d, nnz, P.rp_t, P.col_t, nullptr,
+                          static_cast<int64_t*>(cursor.p), scan.p, transpose_scratch_bytes(d), s, P.src_t));
+  LD_HIP(hipStreamSynchronize(s));
+  return LD_OK;
+}
+
+// The cached analysis of B's pattern, made on first sight.
+int get_pattern(const ld_csr* B, hipStream_t s, std::shared_ptr<PatternInfo>& out) {
+  PatternKey key;
+  int rc = pattern_key(B, key);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_pat_mu);
+    auto it = g_pat.find(key);
+    if (it != g_pat.end()) {
+      it->second->last_use = ++g_pat_clock;
+      out = it->second;
+      return LD_OK;
+    }
+  }
+  auto P = std::make_shared<PatternInfo>();
+  rc = analyze_pattern(B, s, *P);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_pat_mu);
+  if (g_pat.size() >= kPatternCacheEntries) {
+    auto lru = g_pat.begin();
+    for (auto it = g_pat.begin(); it != g_pat.end(); ++it)
+      if (it->second->last_use < lru->second->last_use) lru = it;
+    g_pat.erase(lru);
+  }
+  P->last_use = ++g_pat_clock;
+  g_pat[key] = P;
+  out = P;
+  return LD_OK;
+}
+
+void drop_pattern(const ld_csr* B) {
+  PatternKey key;
+  if (pattern_key(B, key)) return;
+  std::lock_guard<std::mutex> lk(g_pat_mu);
+  g_pat.erase(key);
+}
+
 size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, int stride, bool pair) {
   const size_t vb = vec_f64 ? 8 : 4;
   const GradPlan g = plan_grad(n, pair, stride);
@@ -934,8 +1066,8 @@ size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_o
   const size_t vecb = (size_t)B->rows * ch.size * vb;
   for (int i = 0; i < g.nslots + g.nseg_buf + 2; ++i) c.take(vecb);
   c.take((size_t)B->nnz * vb);                       // gradient accumulators
-  c.take((size_t)B->nnz * 8);                        // transposed-entry index
-  c.take(256);                                       // missing-transpose flag
+  if (!pair) c.take((size_t)B->nnz * val_bytes(valt_of(B->dtype)));  // values of B^T (adjoint of the plain form)
+  c.take(256);                                       // pattern hash
   c.take((size_t)std::max<int64_t>(ntiles, 1) * 8);  // diagonal partials
   c.take(8);                                         // diagonal total
   c.take((size_t)rows * part_cols * 8);              // per-tile moment partials
@@ -948,7 +1080,7 @@ size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_o
 // Checkpoint stride of each form of the gradient (the paired form with the product identities,
 // and the plain recurrence that patterns without their transpose run): the caller's, else 1
 // (every W_k kept, no recomputation) when that form's plan fits the memory available -- the
-// caller's workspace, or 40% of the device's free memory -- else 0 (ceil(sqrt(steps))).  The
+// caller's workspace, or half of the device's free memory -- else 0 (ceil(sqrt(steps))).  The
 // form is known only once the pattern has been checked, so each is planned on its own: the
 // plain form keeps twice as many blocks and may have to recompute where the paired one need not.
 struct GradStrides {
@@ -964,7 +1096,7 @@ GradStrides choose_strides(const ld_csr* B, int n, int M, int vec_f64, const ld_
     // counting the library's idle pooled buffers as free: they are reused before anything new is
     // allocated, so a repeated call plans as the first one did
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) avail = (fr + pool_idle_bytes()) / 5 * 2;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) avail = (fr + pool_idle_bytes()) / 2;
   }
   GradStrides st;
   st.pair = grad_workspace_for(B, n, M, vec_f64, opt, 1, true) <= avail ? 1 : 0;
@@ -1432,8 +1564,18 @@ static int copy_impl(void* dst, const void* src, size_t bytes, void* stream, dou
   return LD_OK;
 }
 
-static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, double grad_output,
-                                 void* grad_values, int grad_dtype, const ld_opts* opt, void* stream, ld_result* out) {
+// The gradient's forms (the pattern's analysis is cached, see PatternInfo):
+//  * paired (default, symmetric pattern): ceil(n/2) products with the product identities, which take
+//    B = B^T as Algorithm 1 does; the single-gather adjoint runs on B and each stored entry gets the
+//    derivative along symmetric perturbations (G_ij + G_ji) / 2;
+//  * plain (a pattern without its transpose, or opt->plain_recurrence): Algorithm 1's recurrence as
+//    written, n products, and the adjoint y_k = c_k v + 2 At^T y_{k+1} - y_{k+2} on B^T: the
+//    single-gather kernel on B^T applies B^T in its product and accumulates, at B^T's entry (j, i),
+//    the derivative with respect to B's entry (i, j), which an index map then carries back.  No
+//    symmetry is assumed: each stored entry gets dGamma/dB_ij on its own.
+static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, double grad_output,
+                     void* grad_values, int grad_dtype, const ld_opts* opt, void* stream, ld_result* out,
+                     bool allow_retry) {
   int rc = check_csr(B, "B");
   if (rc) return rc;
   rc = check_common(a, b, n, M);
@@ -1456,24 +1598,18 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
                                      tiles_of(B, grad_shape(B, ch.last, vec_f64, opt)) * ch.last);
   const GradStrides strides = choose_strides(B, n, M, vec_f64, opt);
   const size_t need = grad_workspace_strides(B, n, M, vec_f64, opt, strides);
+  std::shared_ptr<PatternInfo> pat;
+  if (d > 0) {
+    rc = get_pattern(B, s, pat);
+    if (rc) return rc;
+  }
+  const bool sym_pattern = !pat || pat->sym;
+  const bool pair_form = use_pairs(opt) && sym_pattern;
   Workspace ws;
   rc = get_workspace(opt, need, s, ws);
   if (rc) return rc;
   Carve cv;
   cv.base = static_cast<char*>(ws.ptr);
-  int64_t* perm = static_cast<int64_t*>(cv.take((size_t)B->nnz * 8));
-  int* missing = static_cast<int*>(cv.take(256));
-  // The pattern's symmetry decides the form: the product identities (and the symmetrised
-  // gradient) need B = B^T; a pattern without its transpose runs the plain recurrence.
-  LD_HIP(launch_fill_zero(missing, 256, s));
-  LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, B->nnz, perm, missing, s));
-  int miss = 1;
-  if (B->nnz > 0) {
-    LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
-    LD_HIP(hipStreamSynchronize(s));
-  }
-  const bool sym_pattern = miss == 0;
-  const bool pair_form = use_pairs(opt) && sym_pattern;
   const GradPlan g = plan_grad(n, pair_form, pair_form ? strides.pair : strides.plain);
   const bool pair = g.pair;
   const int nrows = partial_rows(n, pair);
@@ -1484,6 +1620,22 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   void* Ya = cv.take(vecb);
   void* Yb = cv.take(vecb);
   void* Gacc = cv.take((size_t)B->nnz * vb);
+  // the adjoint's matrix: B itself (paired form), or B^T (plain form)
+  void* val_t = pair ? nullptr : cv.take((size_t)B->nnz * val_bytes(valt));
+  uint64_t* hash_dev = static_cast<uint64_t*>(cv.take(256));
+  if (d > 0) LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, B->nnz, hash_dev, s));
+  const int64_t* adj_rp = B->row_ptr;
+  const int32_t* adj_col = B->col_idx;
+  const void* adj_val = B->values;
+  if (!pair && B->nnz > 0) {
+    const int64_t* src = sym_pattern ? pat->perm : pat->src_t;  // B^T's entry u is B's entry src[u]
+    LD_HIP(launch_gather_values(B->values, valt, src, B->nnz, val_t, s));
+    if (!sym_pattern) {
+      adj_rp = pat->rp_t;
+      adj_col = pat->col_t;
+    }
+    adj_val = val_t;
+  }
   double* gdiag_part = static_cast<double*>(cv.take((size_t)std::max<int64_t>(nt_max, 1) * 8));
   double* gdiag_tot = static_cast<double*>(cv.take(8));
   const int rows_alloc = std::max(nrows, 1);
@@ -1516,7 +1668,9 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   LD_HIP(launch_fill_zero(Gacc, (size_t)B->nnz * vb, s));
   LD_HIP(launch_fill_zero(gdiag_part, (size_t)std::max<int64_t>(nt_max, 1) * 8, s));
   LD_HIP(tm.mark(T_OTHER));
-  const bool sym = sym_pattern && sym_enabled();
+  // single-gather adjoint: on B^T always; on B when its pattern is symmetric (LD_GRAD_SYM=0 keeps
+  // the two-gather form there, for tests)
+  const bool sym = !pair || (sym_pattern && sym_enabled());
   std::vector<double> red((size_t)M * rows_alloc, 0.0);  // per-probe partial rows, all passes
 
   for (int pass = 0; pass < ch.count; ++pass) {
@@ -1599,9 +1753,9 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
       void* y1 = Ya;       // y_{j+1}
       void* y2 = nullptr;  // y_{j+2}
       AdjDesc A{};
-      A.row_ptr = B->row_ptr;
-      A.col = B->col_idx;
-      A.val = B->values;
+      A.row_ptr = adj_rp;
+      A.col = adj_col;
+      A.val = adj_val;
       A.Gacc = Gacc;
       A.gdiag_part = gdiag_part;
       A.seed = pseed;
@@ -1663,19 +1817,30 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   }
   const double scale = grad_output * (2.0 / (b - a)) / M;
   if (B->nnz > 0) {
-    // symmetric pattern: the derivative along symmetric perturbations, (G_ij + G_ji)/2
-    if (sym_pattern)
-      LD_HIP(launch_sym_scale(Gacc, vec_f64, perm, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
-    else
-      LD_HIP(launch_scale_grad(Gacc, vec_f64, B->nnz, scale, grad_values, grad_dtype == LD_F64, s));
+    const int of64 = grad_dtype == LD_F64;
+    if (pair)  // the derivative along symmetric perturbations, (G_ij + G_ji)/2
+      LD_HIP(launch_sym_scale(Gacc, vec_f64, pat->perm, B->nnz, scale, grad_values, of64, s));
+    else if (sym_pattern)  // B^T has B's pattern: entry (i, j) reads the accumulator of (j, i)
+      LD_HIP(launch_perm_scale(Gacc, vec_f64, pat->perm, B->nnz, scale, grad_values, of64, 0, s));
+    else  // B^T's entry u belongs to B's entry src_t[u]
+      LD_HIP(launch_perm_scale(Gacc, vec_f64, pat->src_t, B->nnz, scale, grad_values, of64, 1, s));
   }
   double gd = 0.0;
   if (nt_max > 0) {
     LD_HIP(launch_sum_doubles(gdiag_part, nt_max, gdiag_tot, s));
     LD_HIP(hipMemcpyAsync(&gd, gdiag_tot, 8, hipMemcpyDeviceToHost, s));
   }
+  uint64_t hash = 0;
+  if (d > 0) LD_HIP(hipMemcpyAsync(&hash, hash_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   LD_HIP(tm.mark(T_OTHER));
   LD_HIP(hipStreamSynchronize(s));
+  if (pat && hash != pat->hash) {
+    // the pattern at these addresses is not the one analysed: the caller analyses it again and
+    // repeats the call, once this call's buffers are released
+    drop_pattern(B);
+    if (!allow_retry) return fail(LD_EINVAL, "the pattern of B changed while the gradient ran");
+    return kRetryPattern;
+  }
   std::vector<double> mu((size_t)M * (n + 1), 0.0);
   assemble_moments(red, nrows, pair, n, M, d, mu);
   ld_result r{};
@@ -1685,6 +1850,13 @@ static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int
   tm.report(&r);
   *out = r;
   return r.flags ? LD_WBOUNDS : LD_OK;
+}
+
+static int logdet_cheb_grad_impl(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, double grad_output,
+                                 void* grad_values, int grad_dtype, const ld_opts* opt, void* stream, ld_result* out) {
+  const int rc = grad_body(B, a, b, n, M, seed, grad_output, grad_values, grad_dtype, opt, stream, out, true);
+  if (rc != kRetryPattern) return rc;
+  return grad_body(B, a, b, n, M, seed, grad_output, grad_values, grad_dtype, opt, stream, out, false);
 }
 
 static int logdet_cheb_batched_impl(int count, const ld_csr* Bs, const double* a, const double* b, const int* n, int M,
@@ -2031,6 +2203,10 @@ static int clear_cache_impl(void) {
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     g_batch.clear();
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_pat_mu);
+    g_pat.clear();
   }
   pool_release_all();
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -159,10 +159,25 @@ hipError_t launch_laplacian_minor(const int64_t* row_ptr, const int32_t* col, in
 
 hipError_t launch_probes(uint64_t seed, int M, int64_t rows, int8_t* out, hipStream_t s);
 
+// C^T in CSR form with ascending columns.  val/val_t may be null (pattern only); src_t (nullable)
+// receives, for every entry of C^T, the index of the entry of C it came from.
 hipError_t launch_transpose(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, int64_t d,
                             int64_t nnz, int64_t* row_ptr_t, int32_t* col_t, void* val_t, int64_t* cursor,
-                            void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
+                            void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s, int64_t* src_t = nullptr);
 size_t transpose_scratch_bytes(int64_t d);
+
+// out[u] = val[src[u]] for u < n (values of type valt): the values of C^T from its source map.
+hipError_t launch_gather_values(const void* val, int valt, const int64_t* src, int64_t n, void* out, hipStream_t s);
+
+// Gradient output through an index map: scatter = 0: out[u] = scale * a[idx[u]];
+// scatter = 1: out[idx[u]] = scale * a[u] (idx a permutation of [0, n)).
+hipError_t launch_perm_scale(const void* a, int a_f64, const int64_t* idx, int64_t n, double scale, void* out,
+                             int out_f64, int scatter, hipStream_t s);
+
+// *out (device) = an order-independent 64-bit hash of a CSR pattern (row_ptr[0..d], col[0..nnz)):
+// the sum mod 2^64 of a mixing function of (position, value) over both arrays.
+hipError_t launch_pattern_hash(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz, uint64_t* out,
+                               hipStream_t s);
 
 hipError_t launch_scale_grad(const void* Gacc, int acc_f64, int64_t nnz, double scale, void* out, int out_f64,
                              hipStream_t s);

@@ -862,26 +862,36 @@ __global__ void __launch_bounds__(256) scan_add_kernel(int64_t* out, int64_t n, 
     out[x] += sums[x / kScanTile];
 }
 
+// Row r of C scatters its entries into the rows of C^T at per-column cursors.  val_t and src_t are
+// nullable: without values only the pattern is built; src_t[pos] = t records which entry of C
+// landed at pos (the map from C^T's entries back to C's).
 template <int VALT>
 __global__ void __launch_bounds__(256) scatter_t_kernel(const int64_t* row_ptr, const int32_t* col, const void* val,
-                                                        int64_t d, int64_t* cursor, int32_t* col_t, void* val_t) {
+                                                        int64_t d, int64_t* cursor, int32_t* col_t, void* val_t,
+                                                        int64_t* src_t) {
   for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
     for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t) {
       const int c = col[t];
       const int64_t pos = (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(cursor + c), 1ull);
       col_t[pos] = (int32_t)r;
-      if constexpr (VALT == VAL_F64)
-        static_cast<double*>(val_t)[pos] = static_cast<const double*>(val)[t];
-      else if constexpr (VALT == VAL_F32)
-        static_cast<float*>(val_t)[pos] = static_cast<const float*>(val)[t];
-      else
-        static_cast<uint16_t*>(val_t)[pos] = static_cast<const uint16_t*>(val)[t];
+      if (src_t) src_t[pos] = t;
+      if (val_t) {
+        if constexpr (VALT == VAL_F64)
+          static_cast<double*>(val_t)[pos] = static_cast<const double*>(val)[t];
+        else if constexpr (VALT == VAL_F32)
+          static_cast<float*>(val_t)[pos] = static_cast<const float*>(val)[t];
+        else
+          static_cast<uint16_t*>(val_t)[pos] = static_cast<const uint16_t*>(val)[t];
+      }
     }
   }
 }
 
+// Sorts every row by column (the scatter's order within a row depends on timing); values and
+// source indices (both nullable) move with their columns, so the result is deterministic.
 template <int VALT>
-__global__ void __launch_bounds__(256) sort_rows_kernel(const int64_t* row_ptr, int64_t d, int32_t* col, void* val) {
+__global__ void __launch_bounds__(256) sort_rows_kernel(const int64_t* row_ptr, int64_t d, int32_t* col, void* val,
+                                                        int64_t* src) {
   typedef typename std::conditional<VALT == VAL_F64, double,
                                     typename std::conditional<VALT == VAL_F32, float, uint16_t>::type>::type T;
   T* v = static_cast<T*>(val);
@@ -889,15 +899,18 @@ __global__ void __launch_bounds__(256) sort_rows_kernel(const int64_t* row_ptr, 
     const int64_t s = row_ptr[r], e = row_ptr[r + 1];
     for (int64_t i = s + 1; i < e; ++i) {  // insertion sort: rows are short
       const int32_t kc = col[i];
-      const T kv = v[i];
+      const T kv = v ? v[i] : T(0);
+      const int64_t ks = src ? src[i] : 0;
       int64_t j = i - 1;
       while (j >= s && col[j] > kc) {
         col[j + 1] = col[j];
-        v[j + 1] = v[j];
+        if (v) v[j + 1] = v[j];
+        if (src) src[j + 1] = src[j];
         --j;
       }
       col[j + 1] = kc;
-      v[j + 1] = kv;
+      if (v) v[j + 1] = kv;
+      if (src) src[j + 1] = ks;
     }
   }
 }
@@ -1199,7 +1212,7 @@ size_t transpose_scratch_bytes(int64_t d) {
 
 hipError_t launch_transpose(const int64_t* row_ptr, const int32_t* col, const void* val, int valt, int64_t d,
                             int64_t nnz, int64_t* row_ptr_t, int32_t* col_t, void* val_t, int64_t* cursor,
-                            void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s) {
+                            void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s, int64_t* src_t) {
   const int64_t n = d + 1;
   const int64_t nt = (n + kScanTile - 1) / kScanTile;
   if (scan_tmp_bytes < transpose_scratch_bytes(d)) return hipErrorInvalidValue;
@@ -1215,15 +1228,17 @@ hipError_t launch_transpose(const int64_t* row_ptr, const int32_t* col, const vo
   if (e != hipSuccess) return e;
   const unsigned g = grid_for(d, 256);
   if (valt == VAL_F64) {
-    hipLaunchKernelGGL(scatter_t_kernel<VAL_F64>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t, val_t);
-    hipLaunchKernelGGL(sort_rows_kernel<VAL_F64>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t);
+    hipLaunchKernelGGL(scatter_t_kernel<VAL_F64>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t, val_t,
+                       src_t);
+    hipLaunchKernelGGL(sort_rows_kernel<VAL_F64>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t, src_t);
   } else if (valt == VAL_F32) {
-    hipLaunchKernelGGL(scatter_t_kernel<VAL_F32>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t, val_t);
-    hipLaunchKernelGGL(sort_rows_kernel<VAL_F32>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t);
+    hipLaunchKernelGGL(scatter_t_kernel<VAL_F32>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t, val_t,
+                       src_t);
+    hipLaunchKernelGGL(sort_rows_kernel<VAL_F32>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t, src_t);
   } else {
     hipLaunchKernelGGL(scatter_t_kernel<VAL_BF16>, dim3(g), dim3(256), 0, s, row_ptr, col, val, d, cursor, col_t,
-                       val_t);
-    hipLaunchKernelGGL(sort_rows_kernel<VAL_BF16>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t);
+                       val_t, src_t);
+    hipLaunchKernelGGL(sort_rows_kernel<VAL_BF16>, dim3(g), dim3(256), 0, s, row_ptr_t, d, col_t, val_t, src_t);
   }
   return hipGetLastError();
 }

@@ -1,7 +1,8 @@
 // Preparation kernels for gfx950 that run once per matrix, before the estimator's loop (Han,
 // Malioutov & Shin, arXiv 1503.06394): Gershgorin bounds for a whole batch of matrices in one
-// launch, the Lanczos steps of the spectral estimate (the bounds Section 3.2 asks for), and the
-// Laplacian minor used to count spanning trees (Section 3.3).
+// launch, the Lanczos steps of the spectral estimate (the bounds Section 3.2 asks for), the
+// Laplacian minor used to count spanning trees (Section 3.3), and the pattern analysis of the
+// gradient (values of B^T through a source map, outputs through an index map, a pattern hash).
 #include <algorithm>
 
 #include "ld_internal.h"
@@ -189,6 +190,94 @@ hipError_t launch_lanczos_update(double* w, const double* v, const double* u, co
 hipError_t launch_lanczos_scale(const double* x, const double* bb, int64_t n, double* y, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(lanczos_scale_kernel, dim3(lanczos_grid(n)), dim3(256), 0, s, x, bb, n, y);
+  return hipGetLastError();
+}
+
+// --- pattern analysis for the gradient ---
+
+template <typename T>
+__global__ void __launch_bounds__(256) gather_values_kernel(const T* val, const int64_t* src, int64_t n, T* out) {
+  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < n; u += (int64_t)gridDim.x * 256) out[u] = val[src[u]];
+}
+
+hipError_t launch_gather_values(const void* val, int valt, const int64_t* src, int64_t n, void* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = lanczos_grid(n);
+  if (valt == VAL_F64)
+    hipLaunchKernelGGL(gather_values_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<const double*>(val), src, n,
+                       static_cast<double*>(out));
+  else if (valt == VAL_F32)
+    hipLaunchKernelGGL(gather_values_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<const float*>(val), src, n,
+                       static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL(gather_values_kernel<uint16_t>, dim3(g), dim3(256), 0, s, static_cast<const uint16_t*>(val), src,
+                       n, static_cast<uint16_t*>(out));
+  return hipGetLastError();
+}
+
+template <typename TA, typename TO>
+__global__ void __launch_bounds__(256) perm_scale_kernel(const TA* a, const int64_t* idx, int64_t n, double scale,
+                                                         TO* out, int scatter) {
+  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < n; u += (int64_t)gridDim.x * 256) {
+    if (scatter)
+      out[idx[u]] = (TO)((double)a[u] * scale);
+    else
+      out[u] = (TO)((double)a[idx[u]] * scale);
+  }
+}
+
+hipError_t launch_perm_scale(const void* a, int a_f64, const int64_t* idx, int64_t n, double scale, void* out,
+                             int out_f64, int scatter, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = lanczos_grid(n);
+  if (a_f64 && out_f64)
+    hipLaunchKernelGGL((perm_scale_kernel<double, double>), dim3(g), dim3(256), 0, s, static_cast<const double*>(a), idx,
+                       n, scale, static_cast<double*>(out), scatter);
+  else if (a_f64)
+    hipLaunchKernelGGL((perm_scale_kernel<double, float>), dim3(g), dim3(256), 0, s, static_cast<const double*>(a), idx,
+                       n, scale, static_cast<float*>(out), scatter);
+  else if (out_f64)
+    hipLaunchKernelGGL((perm_scale_kernel<float, double>), dim3(g), dim3(256), 0, s, static_cast<const float*>(a), idx,
+                       n, scale, static_cast<double*>(out), scatter);
+  else
+    hipLaunchKernelGGL((perm_scale_kernel<float, float>), dim3(g), dim3(256), 0, s, static_cast<const float*>(a), idx, n,
+                       scale, static_cast<float*>(out), scatter);
+  return hipGetLastError();
+}
+
+// Order-independent pattern hash: every (position, value) pair of row_ptr and col goes through the
+// SplitMix64 finaliser (a generic 64-bit mixer here) with a different salt per array; the terms are
+// summed modulo 2^64 (per-workgroup sums, then one integer atomic each), so the result does not
+// depend on the order of the additions.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) pattern_hash_kernel(const int64_t* row_ptr, const int32_t* col, int64_t d,
+                                                           int64_t nnz, unsigned long long* out) {
+  uint64_t h = 0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r <= d; r += stride)
+    h += mix64(((uint64_t)r * 0x9E3779B97F4A7C15ull) ^ (uint64_t)row_ptr[r] ^ 0x5851F42D4C957F2Dull);
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nnz; t += stride)
+    h += mix64(((uint64_t)t * 0xD1B54A32D192ED03ull) ^ (uint64_t)(uint32_t)col[t]);
+  for (int o = 32; o >= 1; o >>= 1) h += (uint64_t)__shfl_xor((unsigned long long)h, o, 64);
+  __shared__ uint64_t sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)(sh[0] + sh[1] + sh[2] + sh[3]));
+}
+
+hipError_t launch_pattern_hash(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz, uint64_t* out,
+                               hipStream_t s) {
+  hipError_t e = launch_fill_zero(out, sizeof(uint64_t), s);
+  if (e != hipSuccess) return e;
+  const int64_t work = std::max<int64_t>(d + 1, nnz);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 2047) / 2048, 2048));
+  hipLaunchKernelGGL(pattern_hash_kernel, dim3(g), dim3(256), 0, s, row_ptr, col, d, nnz,
+                     reinterpret_cast<unsigned long long*>(out));
   return hipGetLastError();
 }
 

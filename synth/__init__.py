@@ -26,6 +26,7 @@ __all__ = [
     "grid_laplacian_3d",
     "random_sparse_spd",
     "random_nonsingular",
+    "lower_triangular_nonsymmetric",
     "random_batch",
     "diagonal_matrix",
     "graph_from_edges",
@@ -202,6 +203,24 @@ def random_nonsingular(d: int, per_row: int = 8, mseed: int = 6, diag_add: float
     row_ptr, col, val = _insert_diagonal(d, row_ptr, col, val, np.full(d, diag_add))
     return CSR(d, row_ptr, col, round_to(val, storage), storage,
                {"kind": "random_nonsingular", "per_row": per_row, "mseed": mseed, "diag_add": diag_add})
+
+
+def lower_triangular_nonsymmetric(d: int, per_row: int = 3, mseed: int = 5, diag_lo: float = 10.0,
+                                  diag_hi: float = 14.0, off_scale: float = 0.3, storage: str = "f64") -> CSR:
+    """Non-symmetric sparse matrix with a real spectrum: diagonal U[diag_lo, diag_hi] plus ``per_row``
+    strictly lower-triangular entries per row (columns uniform below the row, duplicates summed),
+    N(0, off_scale^2) values.  Its eigenvalues are its diagonal entries, and no stored off-diagonal
+    entry has its transpose stored, so its pattern is not symmetric."""
+    rng = np.random.Generator(np.random.PCG64(mseed))
+    rows = np.repeat(np.arange(d, dtype=np.int64), per_row)
+    hi = np.maximum(rows, 1)
+    cols = (rng.random(size=rows.shape[0]) * hi).astype(np.int64)
+    keep = rows > 0  # row 0 has no entry below the diagonal
+    vals = off_scale * rng.standard_normal(size=rows.shape[0])
+    row_ptr, col, val = _coo_to_csr(d, rows[keep], cols[keep], vals[keep])
+    row_ptr, col, val = _insert_diagonal(d, row_ptr, col, val, rng.uniform(diag_lo, diag_hi, size=d))
+    return CSR(d, row_ptr, col, round_to(val, storage), storage,
+               {"kind": "lower_triangular_nonsymmetric", "per_row": per_row, "mseed": mseed})
 
 
 def random_batch(count: int = 256, mseed0: int = 1000, d_min: int = 1000, d_max: int = 200_000,

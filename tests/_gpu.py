@@ -6,10 +6,30 @@ import sys
 import numpy as np
 
 
-# Relative errors of log det estimates use max(|reference|, FLOOR * d) as denominator: a log det
-# within 1e-3 d of zero is compared in absolute terms, because the FP64 rounding of the final
-# coefficient sum scales with d, not with |log det|.
-FLOOR = 1e-3
+U64 = 2.0 ** -53  # unit roundoff of FP64
+U32 = 2.0 ** -24  # unit roundoff of FP32
+
+
+def floor_for(a: float, b: float, n: int, d: int, tol: float, u: float = U64) -> float:
+    """Floor of the denominator of a relative parity check on a log det estimate: E / tol, with E the
+    rounding the two sides may commit in Gamma = sum_k c_k mu_k.  A moment |mu_k| <= d comes out of k
+    steps of the recurrence with about (k + 1) u d of rounding (u the unit roundoff of the recurrence)
+    and c_k weighs it, so E = 4 u d sum_k (k + 1) |c_k| (both sides, with a factor 2 of margin).  The
+    check |x - y| / max(|y|, E / tol) <= tol passes when |x - y| <= max(tol |y|, E): relative while
+    |Gamma| is above the rounding scale, absolute at that scale below it."""
+    from tests import _ref
+
+    c = _ref.cheb_coeffs(a, b, n)
+    k = np.arange(n + 1)
+    return 4.0 * u * d * float(np.sum((k + 1) * np.abs(c))) / tol
+
+
+def floor_taylor(a: float, b: float, n: int, d: int, tol: float, u: float = U64) -> float:
+    """floor_for for the Taylor comparator: its terms v^T A^k v / k have |A| <= q = b/(a + b), so a term
+    carries about (k + 1) u d q^k / k of rounding; E = 4 u d sum_{k=1..n} (k + 1) q^k / k."""
+    q = b / (a + b)
+    k = np.arange(1, n + 1)
+    return 4.0 * u * d * float(np.sum((k + 1) * q ** k / k)) / tol
 
 
 def say(msg: str) -> None:
@@ -26,6 +46,25 @@ def dev(B, dtype=None, shift=0.0):
 
 def rel(x, y, floor=0.0) -> float:
     return abs(x - y) / max(abs(y), floor)
+
+
+# Gradients are compared entry by entry: |g_t - o_t| <= tol * max(|o_t|, TAU * max_s |o_s|).  An entry
+# far below the largest is held to that absolute level instead of its own relative one, because its
+# value is a sum (over probes and degrees) of terms as large as those of the large entries, and its
+# rounding error scales with those terms, not with the sum.
+TAU = 1e-2
+
+
+def entrywise(g, ref, tau: float = TAU) -> float:
+    """max_t |g_t - ref_t| / max(|ref_t|, tau * max|ref|): the entrywise relative error with a floor."""
+    g = np.asarray(g, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    if ref.size == 0:
+        return 0.0
+    den = np.maximum(np.abs(ref), tau * max(float(np.max(np.abs(ref))), 1e-300))
+    err = float(np.max(np.abs(g - ref) / den))
+    print(f"[entrywise] {err:.3e} over {ref.size} entries", flush=True)
+    return err
 
 
 def normwise(x, y) -> float:
