@@ -1,14 +1,19 @@
 """Benchmark of the stochastic Chebyshev log-determinant hot path on one MI355X.
 
-A step is one pass of the whole path over the workload with inputs resident in HBM:
-Gershgorin bounds on the device, then the forward estimate and its gradient on the
-sparsity pattern (ld_logdet_cheb_grad: forward recurrence with checkpoints, recomputation,
-adjoint recurrence fused with the SDDMM).  The metric counts M * n * nnz matrix-vector
-nonzeros per logdet (the forward work of Algorithm 1) per second of fwd+grad time.
+A step is one pass of the whole path over the workload with inputs resident in HBM: the
+spectral interval (given, or Gershgorin bounds on the device), then the forward estimate and
+its gradient on the sparsity pattern (ld_logdet_cheb_grad: forward recurrence with
+checkpoints, adjoint recurrence fused with the SDDMM).
 
-Default workload: random sparse symmetric diagonally dominant matrix, d = 1,000,000, about
-11 stored entries per row (Section 5.1 recipe with diagonal = sum |offdiag| + 1), FP32
-values and recurrence, M = 64 probes in one block, degree n = 50.
+Default workload: the 2-D Dirichlet grid Laplacian 4096 x 4096 (d = 16,777,216, 83,869,696
+stored entries) + 0.01 I, values stored in BF16 (exact) with the 0.01 shift kept in FP64, FP32
+recurrence, M = 32 probes, degree n = 100, bounds [0.01, 8.01]: the largest configuration,
+in the paper's tens-of-millions regime (Section 5.1).
+
+`value` counts the sparse matrix-vector nonzeros of the products the method executes per
+second of fwd+grad time: M * nnz per product, ceil(n/2) forward products (Chebyshev product
+identities) plus ceil(n/2) - 1 adjoint products, recomputation from checkpoints excluded.
+The count with the paper's n products per logdet is reported beside it.
 
 Prints ONE JSON line.  Runs on one GPU only.
 """
@@ -96,8 +101,9 @@ def workload(name: str):
                          "matrix of the main workload, extreme Ritz values")
     if name == "grid4096":
         B = synth.grid_laplacian_2d(4096, "bf16")
-        return dict(B=B, shift=0.01, a=0.01, b=8.01, n=100, M=32, seed=5, grad=False,
-                    desc="2D Dirichlet grid 4096x4096 + 0.01 I, BF16 values, FP32 recurrence, M=32, n=100")
+        return dict(B=B, shift=0.01, a=0.01, b=8.01, n=100, M=32, seed=5, grad=True,
+                    desc="2D Dirichlet grid 4096x4096 (d=16.8M) + 0.01 I, BF16 values (shift 0.01 in FP64), "
+                         "FP32 recurrence, M=32, n=100, bounds [0.01, 8.01]: fwd+grad")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -105,21 +111,31 @@ def workload(name: str):
 # algorithmic bytes of the dominant kernels (per launch)
 # ----------------------------------------------------------------------------------------
 
+def csr_bytes(d: int, nnz: int, val_bytes: int) -> int:
+    """The CSR matrix once: values, int32 columns and 4-byte row pointers (the survey's count; the
+    library's int64 row pointers add (d + 1) * 4 bytes, reported in `moved_bytes_per_launch`)."""
+    return nnz * (val_bytes + 4) + (d + 1) * 4
+
+
 def step_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int) -> int:
-    """Compulsory bytes of one recurrence step: the CSR matrix once (values, int32 columns, int64
-    row pointers), W_k read once, W_{k-1} read, W_{k+1} written.  Algorithm 2 splits a degree into
-    T = C W_k (C, W_k gathered, T written) and W_{k+1} = alpha C^T T + beta W_k - W_{k-1} (C^T, T
-    gathered, W_k and W_{k-1} read, W_{k+1} written): 2 + 4 vectors over two launches, the same
-    three per launch on average."""
-    return nnz * (val_bytes + 4) + (d + 1) * 8 + 3 * d * M * vec_bytes
+    """Algorithmic bytes of one recurrence step: the CSR matrix once, W_k read once, W_{k-1} read,
+    W_{k+1} written.  Algorithm 2 splits a degree into T = C W_k (C, W_k gathered, T written) and
+    W_{k+1} = alpha C^T T + beta W_k - W_{k-1} (C^T, T gathered, W_k and W_{k-1} read, W_{k+1}
+    written): 2 + 4 vectors over two launches, the same three per launch on average."""
+    return csr_bytes(d, nnz, val_bytes) + 3 * d * M * vec_bytes
 
 
-def adjoint_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int, pair: bool) -> int:
-    """Compulsory bytes of one adjoint step: the CSR matrix, y_{j+1} and w_j read once each, y_{j+2}
-    read, y_j written, the nnz gradient accumulators read and written, and with the product
-    identities the seed's w_{j-1} and w_{j+1}."""
-    vectors = 6 if pair else 4
-    return nnz * (val_bytes + 4) + (d + 1) * 8 + vectors * d * M * vec_bytes + 2 * nnz * acc_bytes
+def adjoint_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int) -> int:
+    """Algorithmic bytes of one adjoint step, the method's own work: the SpMM y_j = c_j v + 2 At y_{j+1}
+    - y_{j+2} (the CSR matrix, y_{j+1} read once, y_{j+2} read, y_j written), w_j read once for the
+    SDDMM, and the gradient accumulators read and written (2 * acc_bytes per stored entry)."""
+    return csr_bytes(d, nnz, val_bytes) + 4 * d * M * vec_bytes + 2 * nnz * acc_bytes
+
+
+def adjoint_moved_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int) -> int:
+    """What the paired-form adjoint kernel must move besides: its seed reads w_{j-1} and w_{j+1}
+    (the product identities' derivative), and int64 row pointers."""
+    return adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, acc_bytes) + 2 * d * M * vec_bytes + (d + 1) * 4
 
 
 def traffic_from_profiles(kernel_tag: str, workload_name: str):
@@ -143,52 +159,71 @@ def traffic_from_profiles(kernel_tag: str, workload_name: str):
 # CPU baseline: the oracle on a bounded sample
 # ----------------------------------------------------------------------------------------
 
-def host_cpu() -> str:
-    """Model name of the host CPU (from /proc/cpuinfo) and the cores this process may use."""
-    model = "unknown"
+def host_cpu() -> dict:
+    """The host CPU: model name and clock (/proc/cpuinfo, cpufreq), logical CPUs on the machine and
+    the CPUs this process may run on."""
+    model, mhz = "unknown", None
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
+                if line.startswith("model name") and model == "unknown":
                     model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
+                elif line.startswith("cpu MHz") and mhz is None:
+                    mhz = float(line.split(":", 1)[1])
+    except (OSError, ValueError):
         pass
-    return f"{model}, {len(os.sched_getaffinity(0))} cores available"
+    max_mhz = None
+    try:
+        with open("/sys/devices/system/cpu/cpu0/cpufreq/cpuinfo_max_freq") as f:
+            max_mhz = int(f.read().strip()) / 1000.0
+    except (OSError, ValueError):
+        pass
+    return {"model": model, "mhz_now": mhz, "mhz_max": max_mhz, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(W: dict, a: float, b: float, gpu_probe_values) -> tuple:
+    """The oracle as it stands, single-threaded FP64 C, on a bounded sample of the workload: whole
+    probes on the full matrix, one at a time, until about 12 s of work.  The oracle's gradient keeps
+    every w_k and y_k (2n + 3 vectors of d doubles), so at large d the sample runs at a reduced
+    degree (at most 4 GB of vectors); the rate is per executed sparse product, the unit of `value`
+    (the oracle applies B once per degree forward and once per degree backward)."""
     import numpy as np
 
     import oracle
 
     oracle.build()
     B, n, M = W["B"], W["n"], W["M"]
-    # one probe at a time (probe ids 0, 1, ...) until about 10 s of single-core work
+    ns = n
+    if W["grad"]:
+        ns = max(2, min(n, int(4e9 / (16.0 * (B.d + 1)) - 2)))
     secs, done = 0.0, 0
-    while done < M and (secs < 10.0 or done == 0):
+    while done < M and (secs < 12.0 or done == 0):
         t0 = time.perf_counter()
         if W.get("nonsingular"):
-            oracle.logabsdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]))
+            oracle.logabsdet(B, a, b, ns, 1, seed=W["seed"], ids=np.array([done]))
         elif W["grad"]:
-            oracle.logdet_grad(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
+            oracle.logdet_grad(B, a, b, ns, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
         else:
-            oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
+            oracle.logdet(B, a, b, ns, 1, seed=W["seed"], ids=np.array([done]), shift=W["shift"])
         secs += time.perf_counter() - t0
         done += 1
-    if W.get("nonsingular"):
-        r = oracle.logabsdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]))
-    else:
-        r = oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]), shift=W["shift"])
-    work = done * n * B.nnz * (2 if W.get("nonsingular") else 1)
+    products = (2 * ns - 1) if W["grad"] else ns * (2 if W.get("nonsingular") else 1)
     kind = "fwd+grad" if W["grad"] else "fwd"
-    base = {"value": work / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle", "host_cpu": host_cpu(),
-            "sample": f"{kind} of probes 0..{done - 1} of {M} on the full matrix (degree {n}), single-threaded "
-                      f"FP64 C oracle, {secs:.1f} s"}
+    base = {"value": done * products * B.nnz / secs, "unit": "matvec-nnz/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu(),
+            "sample": f"{kind} of probes 0..{done - 1} of {M} on the full matrix at degree {ns} (workload degree "
+                      f"{n}), single-threaded FP64 C oracle, {secs:.1f} s; {products} sparse products per probe"}
     parity = None
     if gpu_probe_values is not None:
+        t0 = time.perf_counter()
+        if W.get("nonsingular"):
+            r = oracle.logabsdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]))
+        else:
+            r = oracle.logdet(B, a, b, n, 1, seed=W["seed"], ids=np.array([0]), shift=W["shift"])
+        log(f"oracle probe 0 at degree {n}: {time.perf_counter() - t0:.1f} s")
         ref = float(r["s"][0])
-        parity = abs(float(gpu_probe_values[0]) - ref) / max(abs(ref), 1e-3 * B.d)
+        parity = abs(float(gpu_probe_values[0]) - ref) / abs(ref)
     return base, parity
 
 
@@ -201,7 +236,7 @@ def main() -> None:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="random1m",
+    ap.add_argument("--workload", default="grid4096",
                     choices=["random1m", "grid32", "gmrf128", "grid4096", "batch256", "nonsingular1m", "gmrf5000",
                              "trees1m", "taylor4096", "lanczos1m",
                              "sec51_3e7"])
@@ -304,8 +339,12 @@ def main() -> None:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    work = M * n * nnz * (2 if nonsingular else 1)  # Algorithm 2 applies C and C^T per degree
-    value = work / (ms_per_step / 1e3)
+    # sparse products of the method per step: ceil(n/2) forward products with the product identities
+    # (Algorithm 2: two per step, C and C^T), plus ceil(n/2) - 1 adjoint products with the gradient
+    m_fwd = (n + 1) // 2
+    products = m_fwd * (2 if nonsingular else 1) + (max(m_fwd - 1, 0) if do_grad else 0)
+    value = M * nnz * products / (ms_per_step / 1e3)
+    work = M * n * nnz * (2 if nonsingular else 1)  # the paper's count: n products per logdet
 
     # forward-only throughput on the same inputs (context)
     a, b = bounds()
@@ -327,18 +366,22 @@ def main() -> None:
 
     # dominant kernel: the larger of the summed step and adjoint kernel times
     sb = step_bytes(d, nnz, M, val_bytes, vec_bytes)
-    ab_ = adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes, True)
+    ab_ = adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes)
     if adj_ms > step_ms and adj_n > 0:
         tag, avg_ms, bytes_ = "adjoint", adj_ms / adj_n, ab_
+        moved = adjoint_moved_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes)
     else:
         tag, avg_ms, bytes_ = "step", step_ms / max(step_n, 1), sb
+        moved = sb + (d + 1) * 4
     achieved = bytes_ / (avg_ms / 1e3) / 1e9
     traffic = traffic_from_profiles(tag, args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": f"{tag} kernel",
-            "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_}
+            "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_,
+            "moved_bytes_per_launch": moved, "moved_GBps": round(moved / (avg_ms / 1e3) / 1e9, 1)}
     if traffic is not None:
         roof["traffic_GBps"] = round(traffic / (avg_ms / 1e3) / 1e9, 1)  # counted bytes at the live launch time
+        roof["traffic_over_algorithmic"] = round(traffic / bytes_, 3)
     extra = {
         "step_kernel": {"avg_ms": round(step_ms / max(step_n, 1), 5), "launches_per_step": step_n // args.steps,
                         "algorithmic_GBps": round(sb / (step_ms / max(step_n, 1) / 1e3) / 1e9, 1)},
@@ -347,7 +390,10 @@ def main() -> None:
         extra["adjoint_kernel"] = {"avg_ms": round(adj_ms / adj_n, 5), "launches_per_step": adj_n // args.steps,
                                    "algorithmic_GBps": round(ab_ / (adj_ms / adj_n / 1e3) / 1e9, 1)}
     if fwd_ms is not None:
-        extra["forward_only"] = {"ms": round(fwd_ms, 3), "matvec_nnz_per_s": work / (fwd_ms / 1e3)}
+        extra["forward_only"] = {"ms": round(fwd_ms, 3),
+                                 "matvec_nnz_per_s": M * nnz * m_fwd * (2 if nonsingular else 1) / (fwd_ms / 1e3)}
+    extra["paper_equivalent_matvec_nnz_per_s"] = work / (ms_per_step / 1e3)
+    extra["products_per_step"] = products
     # sparse products the kernels actually executed (product identities: ceil(n/2) per forward; every
     # adjoint launch runs the SDDMM and all but the last of a call also the SpMM), per second of step time
     executed = nnz * M * (step_n + (2 * adj_n - args.steps if adj_n else 0))

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests._gpu import FLOOR, dev, rel, say
+from tests._gpu import U32, U64, dev, floor_for, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -53,9 +53,10 @@ def test_largest_probe_block(ld, oracle_lib):
     say("M = 4096")
     r = ld.ld_logdet_cheb(dev(B), a, b, 12, 4096, 5, want_probes=True)
     o = oracle_lib.logdet(B, a, b, 12, 4096, seed=5)
-    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-4
+    fl = floor_for(a, b, 12, B.d, 1e-4, U32)
+    assert rel(r["logdet"], o["gamma"], fl) <= 1e-4
     for j in (0, 63, 64, 2047, 4095):
-        assert rel(r["s"][j], o["s"][j], FLOOR * B.d) <= 1e-4, j
+        assert rel(r["s"][j], o["s"][j], fl) <= 1e-4, j
     with pytest.raises(ld.LogdetChebError):
         ld.ld_logdet_cheb(dev(B), a, b, 12, 4097, 5)
 
@@ -68,7 +69,7 @@ def test_high_degree_fp64(ld, oracle_lib, plain):
     say(f"n = 2000 plain={plain}")
     r = ld.ld_logdet_cheb(dev(B), a, b, 2000, 8, 6, plain=plain)
     o = oracle_lib.logdet(B, a, b, 2000, 8, seed=6)
-    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10
+    assert rel(r["logdet"], o["gamma"], floor_for(a, b, 2000, B.d, 1e-10, U64)) <= 1e-10
 
 
 def test_argument_errors_before_any_kernel(ld):
@@ -111,7 +112,7 @@ def test_row_longer_than_the_lds_slice(ld, oracle_lib, plain):
     say(f"long row: forward and gradient plain={plain}")
     r = ld.ld_logdet_cheb(dev(B), a, b, 20, 16, 4, plain=plain)
     o = oracle_lib.logdet(B, a, b, 20, 16, seed=4)
-    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-10
+    assert rel(r["logdet"], o["gamma"], floor_for(a, b, 20, B.d, 1e-10, U64)) <= 1e-10
     rg, g = ld.ld_logdet_cheb_grad(dev(B), a, b, 20, 16, 4, plain=plain)
     og = oracle_lib.logdet_grad(B, a, b, 20, 16, seed=4)
     gg = g.cpu().numpy()
@@ -187,6 +188,7 @@ def test_high_degree_fp32(ld, oracle_lib, plain):
     say(f"n = 400 FP32 plain={plain}")
     r = ld.ld_logdet_cheb(dev(B), a, b, 400, 16, 8, plain=plain, want_probes=True)
     o = oracle_lib.logdet(B, a, b, 400, 16, seed=8)
-    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-4
+    fl = floor_for(a, b, 400, B.d, 1e-4, U32)
+    assert rel(r["logdet"], o["gamma"], fl) <= 1e-4
     for j in range(16):
-        assert rel(r["s"][j], o["s"][j], FLOOR * B.d) <= 1e-4, j
+        assert rel(r["s"][j], o["s"][j], fl) <= 1e-4, j

@@ -13,7 +13,7 @@ import pytest
 
 import synth
 from tests import _ref
-from tests._gpu import FLOOR, b_form_moments, dev, normwise, rel, say
+from tests._gpu import U32, U64, b_form_moments, dev, floor_for, normwise, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -32,10 +32,12 @@ def ld():
     return pkg
 
 
-def _compare(r, o, tol, d, label):
-    # relative error with the floor FLOOR * d, so that an estimate of log det = 0 is not divided by ~0
-    assert rel(r["logdet"], o["gamma"], FLOOR * d) <= tol, (label, r["logdet"], o["gamma"])
-    assert np.max(np.abs(np.asarray(r["s"]) - o["s"])) <= tol * max(np.max(np.abs(o["s"])), FLOOR * d), label
+def _compare(r, o, tol, d, label, a, b, n):
+    # relative error whose denominator is floored at the rounding scale of the estimate (floor_for), so
+    # that an estimate of log det near 0 is not divided by ~0
+    fl = floor_for(a, b, n, d, tol, U64 if tol == TOL64 else U32)
+    assert rel(r["logdet"], o["gamma"], fl) <= tol, (label, r["logdet"], o["gamma"])
+    assert np.max(np.abs(np.asarray(r["s"]) - o["s"])) <= tol * max(np.max(np.abs(o["s"])), fl), label
     if "moments" in r and "moments" in o:
         mo = b_form_moments(o["moments"])
         assert np.max(np.abs(r["moments"] - mo)) <= tol * d, label
@@ -79,7 +81,7 @@ def test_cfg0_fp64_parity(ld, oracle_lib, plain):
     r = ld.ld_logdet_cheb(dev(B, shift=0.1), 0.1, 8.1, 30, 50, 1, want_moments=True, want_probes=True,
                           plain=plain)
     o = oracle_lib.logdet(B, 0.1, 8.1, 30, 50, seed=1, shift=0.1, want_moments=True)
-    _compare(r, o, TOL64, B.d, "cfg0")
+    _compare(r, o, TOL64, B.d, "cfg0", 0.1, 8.1, 30)
     assert r["status"] == 0 and r["flags"] == 0
     # and the estimate is within its standard error of the exact value (Cholesky, eigen-sum)
     assert abs(r["logdet"] - 1259.922427278947) < 4 * r["std_err"]
@@ -104,7 +106,7 @@ def test_fp32_path_parity(ld, oracle_lib, case, plain):
     say(f"fp32 parity {name} plain={plain}")
     r = ld.ld_logdet_cheb(dev(B, shift=shift), a, b, n, M, 11, want_moments=True, want_probes=True, plain=plain)
     o = oracle_lib.logdet(B, a, b, n, M, seed=11, shift=shift, want_moments=True)
-    _compare(r, o, TOL32, B.d, name)
+    _compare(r, o, TOL32, B.d, name, a, b, n)
 
 
 def test_fp64_vectors_with_fp32_values(ld, oracle_lib):
@@ -113,7 +115,7 @@ def test_fp64_vectors_with_fp32_values(ld, oracle_lib):
     say("fp64 vectors, f32 values")
     r = ld.ld_logdet_cheb(dev(B), a, b, 25, 16, 3, vec_f64=True, want_probes=True)
     o = oracle_lib.logdet(B, a, b, 25, 16, seed=3)
-    _compare(r, o, TOL64, B.d, "f64vec")
+    _compare(r, o, TOL64, B.d, "f64vec", a, b, 25)
 
 
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 7, 10, 24, 33, 56, 64, 130, 300])
@@ -126,7 +128,7 @@ def test_probe_counts_and_tiles(ld, oracle_lib, M, vec64):
     say(f"M={M} vec64={vec64}")
     r = ld.ld_logdet_cheb(dev(B), a, b, 13, M, 5, vec_f64=vec64, want_moments=True, want_probes=True)
     o = oracle_lib.logdet(B, a, b, 13, M, seed=5, want_moments=True)
-    _compare(r, o, TOL64 if vec64 else TOL32, B.d, f"M={M}")
+    _compare(r, o, TOL64 if vec64 else TOL32, B.d, f"M={M}", a, b, 13)
 
 
 @pytest.mark.parametrize("plain", [False, True])
@@ -137,7 +139,7 @@ def test_low_degrees(ld, oracle_lib, n, plain):
     say(f"n={n} plain={plain}")
     r = ld.ld_logdet_cheb(dev(B, shift=0.2), 0.2, 8.2, n, 6, 4, want_moments=True, want_probes=True, plain=plain)
     o = oracle_lib.logdet(B, 0.2, 8.2, n, 6, seed=4, shift=0.2, want_moments=True)
-    _compare(r, o, TOL64, B.d, f"n={n}")
+    _compare(r, o, TOL64, B.d, f"n={n}", 0.2, 8.2, n)
     if n == 0:
         assert rel(r["logdet"], B.d * math.log(4.2)) <= 1e-15
 
@@ -151,7 +153,7 @@ def test_tiny_and_ragged(ld, oracle_lib, d, tile):
     say(f"d={d} tile={tile}")
     r = ld.ld_logdet_cheb(dev(B), a, b, 9, 5, 2, tile=tile, want_probes=True, want_moments=True)
     o = oracle_lib.logdet(B, a, b, 9, 5, seed=2, want_moments=True)
-    _compare(r, o, TOL64, B.d, f"d={d}")
+    _compare(r, o, TOL64, B.d, f"d={d}", a, b, 9)
 
 
 def test_rows_without_stored_diagonal(ld, oracle_lib):
@@ -171,7 +173,7 @@ def test_rows_without_stored_diagonal(ld, oracle_lib):
         say(f"no-diagonal rows vec64={vec64}")
         r = ld.ld_logdet_cheb(dev(Cx, shift=shift), a, b, 20, 8, 6, vec_f64=vec64, want_probes=True)
         o = oracle_lib.logdet(Cx, a, b, 20, 8, seed=6, shift=shift)
-        _compare(r, o, TOL64 if vec64 else TOL32, C.d, "nodiag")
+        _compare(r, o, TOL64 if vec64 else TOL32, C.d, "nodiag", a, b, 20)
 
 
 def test_diagonal_matrix_exact(ld):
@@ -236,7 +238,7 @@ def test_autotuned_large_matrix(ld, oracle_lib):
     say("autotuned d=1e5")
     r = ld.ld_logdet_cheb(D, a, b, 10, 32, 21, want_probes=True)
     o = oracle_lib.logdet(B, a, b, 10, 32, seed=21)
-    _compare(r, o, TOL32, B.d, "autotune")
+    _compare(r, o, TOL32, B.d, "autotune", a, b, 10)
 
 
 def test_python_convenience_gershgorin_default(ld, oracle_lib):

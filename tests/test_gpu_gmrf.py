@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests._gpu import FLOOR, dev, rel, say
+from tests._gpu import U32, dev, floor_for, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -77,7 +77,7 @@ def test_loglik_curve_parity(ld, oracle_lib, field, method):
             o = oracle_lib.logdet(J, a, b, n, M, seed=seed)
         else:
             o = oracle_lib.logabsdet(J, a, b, n, M, seed=seed)
-        assert rel(r["logdet"], o["gamma"], FLOOR * J.d) <= 1e-4, rho
+        assert rel(r["logdet"], o["gamma"], floor_for(a, b, n, J.d, 1e-4, U32) if method == 1 else floor_for(a * a, b * b, n, J.d, 1e-4, U32)) <= 1e-4, rho
         rows = J.row_of_entry()
         q = float(np.sum(x[rows] * J.val * x[J.col.astype(np.int64)]))
         assert rel(r["quad"], q) < 1e-12, rho

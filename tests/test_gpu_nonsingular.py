@@ -6,7 +6,7 @@ import pytest
 import scipy.sparse as sp
 
 import synth
-from tests._gpu import FLOOR, dev, rel, say
+from tests._gpu import U32, U64, dev, floor_for, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def test_alg2_parity(ld, oracle_lib, storage, tol, given_t, plain):
     say(f"alg2 {storage} given_t={given_t} plain={plain}")
     r = ld.ld_logabsdet_cheb(D, Ct, smin, smax, n, M, 6, want_probes=True, plain=plain)
     o = oracle_lib.logabsdet(C, smin, smax, n, M, seed=6)
-    assert rel(r["logdet"], o["gamma"], FLOOR * C.d) <= tol, (r["logdet"], o["gamma"])
+    assert rel(r["logdet"], o["gamma"], floor_for(smin ** 2, smax ** 2, n, C.d, tol, U64 if tol < 1e-6 else U32)) <= tol, (r["logdet"], o["gamma"])
     assert np.max(np.abs(r["s"] - o["s"])) <= tol * np.max(np.abs(o["s"]))
     assert r["status"] == 0
 

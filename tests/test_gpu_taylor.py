@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests._gpu import FLOOR, dev, rel, say
+from tests._gpu import U32, U64, dev, floor_taylor, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +39,9 @@ def test_taylor_parity(ld, oracle_lib, name, make, shift, n, M, tol):
     say(f"taylor {name} d={B.d} n={n} M={M}")
     r = ld.ld_logdet_taylor(dev(B, shift=shift), a, b, n, M, 7, want_probes=True, want_moments=True)
     o = oracle_lib.logdet_taylor(B, a, b, n, M, seed=7, shift=shift)
-    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= tol
+    assert rel(r["logdet"], o["gamma"], floor_taylor(a, b, n, B.d, tol, U64 if tol < 1e-6 else U32)) <= tol
     for j in range(M):
-        assert rel(r["s"][j], o["s"][j], FLOOR * B.d) <= tol, j
+        assert rel(r["s"][j], o["s"][j], floor_taylor(a, b, n, B.d, tol, U64 if tol < 1e-6 else U32)) <= tol, j
     assert np.all(r["moments"][:, 0] == B.d)
     assert np.all(np.abs(r["moments"]) <= B.d * (1 + 1e-6))
 
@@ -55,7 +55,7 @@ def test_taylor_low_degree(ld, oracle_lib, n):
     o = oracle_lib.logdet_taylor(B, a, b, n, 8, seed=3)
     if n == 0:
         assert r["logdet"] == B.d * math.log(a + b)
-    assert rel(r["logdet"], o["gamma"], FLOOR * B.d) <= 1e-12
+    assert rel(r["logdet"], o["gamma"], floor_taylor(a, b, n, B.d, 1e-12)) <= 1e-12
 
 
 def test_chebyshev_beats_taylor_on_grid(ld):

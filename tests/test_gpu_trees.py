@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests._gpu import FLOOR, dev, rel, say
+from tests._gpu import U32, U64, dev, floor_for, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -83,9 +83,9 @@ def test_log_spanning_trees_parity(ld, oracle_lib, method, f64):
     r = ld.ld_log_spanning_trees(dev(G), 1234, n, M, seed, method=method, vec_f64=f64, want_probes=True)
     o = oracle_lib.log_spanning_trees(G, 1234, n, M, seed=seed, method=method)
     tol = 1e-10 if f64 else 1e-4
-    assert rel(r["logdet"], o["gamma"], FLOOR * G.d) <= tol
+    assert rel(r["logdet"], o["gamma"], floor_for(1.0, (2.0 * o["delta_max"] - 1.0) ** (2 if method == 1 else 1), n, G.d, tol, U64 if f64 else U32)) <= tol
     for j in range(M):
-        assert rel(r["s"][j], o["s"][j], FLOOR * G.d) <= tol, j
+        assert rel(r["s"][j], o["s"][j], floor_for(1.0, (2.0 * o["delta_max"] - 1.0) ** (2 if method == 1 else 1), n, G.d, tol, U64 if f64 else U32)) <= tol, j
 
 
 def test_log_spanning_trees_star_is_zero(ld):
