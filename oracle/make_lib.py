@@ -27,7 +27,7 @@ def lib_name(sanitize: bool) -> str:
 def build(verbose: bool = False, sanitize: bool = False) -> str:
     src = os.path.join(_HERE, "ldo.c")
     out = lib_name(sanitize)
-    tmp = out + ".tmp"
+    tmp = f"{out}.tmp{os.getpid()}"  # per process: parallel test workers may build at once
     opt = SAN_FLAGS if sanitize else ["-O2"]
     cmd = ["gcc", "-std=c99", *opt, "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
            "-Wall", "-Wextra", "-o", tmp, src, "-lm"]

@@ -1,6 +1,7 @@
 """Helpers shared by the GPU parity tests: device upload and comparison with the oracle."""
 from __future__ import annotations
 
+import math
 import sys
 
 import numpy as np
@@ -12,16 +13,25 @@ U32 = 2.0 ** -24  # unit roundoff of FP32
 
 def floor_for(a: float, b: float, n: int, d: int, tol: float, u: float = U64) -> float:
     """Floor of the denominator of a relative parity check on a log det estimate: E / tol, with E the
-    rounding the two sides may commit in Gamma = sum_k c_k mu_k.  A moment |mu_k| <= d comes out of k
-    steps of the recurrence with about (k + 1) u d of rounding (u the unit roundoff of the recurrence)
-    and c_k weighs it, so E = 4 u d sum_k (k + 1) |c_k| (both sides, with a factor 2 of margin).  The
-    check |x - y| / max(|y|, E / tol) <= tol passes when |x - y| <= max(tol |y|, E): relative while
-    |Gamma| is above the rounding scale, absolute at that scale below it."""
+    rounding the two sides may commit in Gamma = sum_k c_k mu_k.  Two sources:
+      * a moment |mu_k| <= d comes out of k steps of the recurrence with about (k + 1) u d of
+        rounding (u the unit roundoff of the recurrence) and c_k weighs it: 2 u d sum_k (k + 1) |c_k|
+        per side;
+      * each side computes the c_k itself, in FP64, as a sum of n + 1 terms (2/(n+1)) f(x_j) cos(.)
+        with |f| <= F = max(|log a|, |log b|): |dc_k| <= 2 (n + 1) u64 F, which |mu_k| <= d carries
+        into Gamma as 2 (n + 1)^2 u64 d F per side.
+    E = 2 x (both), with a factor 2 of margin on the first.  The check |x - y| / max(|y|, E / tol) <= tol
+    passes when |x - y| <= max(tol |y|, E): relative while |Gamma| is above the rounding scale,
+    absolute at that scale below it (at 1e-10 the floor is ~1e-12 d for the configurations' degrees,
+    far below their |Gamma| / d >= 1)."""
     from tests import _ref
 
     c = _ref.cheb_coeffs(a, b, n)
     k = np.arange(n + 1)
-    return 4.0 * u * d * float(np.sum((k + 1) * np.abs(c))) / tol
+    F = max(abs(math.log(a)), abs(math.log(b)))
+    rec = 4.0 * u * d * float(np.sum((k + 1) * np.abs(c)))
+    coef = 4.0 * (n + 1) ** 2 * U64 * d * F
+    return (rec + coef) / tol
 
 
 def floor_taylor(a: float, b: float, n: int, d: int, tol: float, u: float = U64) -> float:
