@@ -112,6 +112,20 @@ typedef struct {
 int ld_logdet_cheb(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
                    const ld_opts *opt, void *stream, ld_result *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ld_logdet_cheb with the same arguments, results and
+ * errors, whose workspace is a fixed device array of the library, LD_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per GPU, held by each GPU the library runs on until the process ends.  The call makes
+ * no hipMalloc, hipFree or other allocating call: the kernel shape is the planner's default (no
+ * autotuning) and opt->timing is ignored.  opt->workspace must be NULL (LD_EINVAL otherwise).  A
+ * problem whose ld_workspace_bytes(B, n, M, 0, ...) exceeds the array gets LD_EWORKSPACE, before
+ * any work.  Every call on a GPU shares that GPU's array and leaves its contents behind (nothing in
+ * it needs clearing: each step writes every partial it later reads): calls that overlap on one
+ * GPU, from several threads or on several streams, race and must be serialised by the caller. */
+#define LD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int ld_logdet_cheb_noalloc(const ld_csr *B, double a, double b, int n, int M, uint64_t seed,
+                           const ld_opts *opt, void *stream, ld_result *out);
+
 /* Algorithm 2: estimate log|det C| for a non-singular C with singular values in
  * [smin, smax], via log|det C| = (1/2) log det(C^T C).  The recurrence applies C^T (C w)
  * with two sparse products per step.  Ct (nullable) is C^T in CSR form with the same

@@ -18,7 +18,7 @@ from dataclasses import dataclass, field
 import torch
 
 __all__ = [
-    "LogdetChebError", "DeviceCSR", "lib", "ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad",
+    "LogdetChebError", "DeviceCSR", "lib", "ld_logdet_cheb", "ld_logdet_cheb_noalloc", "ld_logabsdet_cheb", "ld_logdet_cheb_grad",
     "ld_logdet_cheb_batched", "ld_gershgorin", "ld_probes", "ld_transpose", "ld_workspace_bytes", "ld_copy",
     "ld_version", "ld_clear_cache", "ld_spectral_estimate", "ld_laplacian_minor", "ld_log_spanning_trees",
     "ld_logdet_taylor", "ld_quadratic_form", "ld_gershgorin_batched",
@@ -75,6 +75,7 @@ def lib():
         P, D, I, I64, U64, SZ = (ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
                                  ctypes.c_size_t)
         L.ld_logdet_cheb.argtypes = [P, D, D, I, I, U64, P, P, P]
+        L.ld_logdet_cheb_noalloc.argtypes = [P, D, D, I, I, U64, P, P, P]
         L.ld_logabsdet_cheb.argtypes = [P, P, D, D, I, I, U64, P, P, P]
         L.ld_logdet_cheb_grad.argtypes = [P, D, D, I, I, U64, D, P, I, P, P, P]
         L.ld_logdet_cheb_batched.argtypes = [I, P, P, P, P, I, U64, P, P, P]
@@ -94,7 +95,7 @@ def lib():
         L.ld_clear_cache.argtypes = []
         L.ld_last_error.restype = ctypes.c_char_p
         L.ld_version.restype = ctypes.c_char_p
-        for f in ("ld_logdet_cheb", "ld_logabsdet_cheb", "ld_logdet_cheb_grad", "ld_logdet_cheb_batched",
+        for f in ("ld_logdet_cheb", "ld_logdet_cheb_noalloc", "ld_logabsdet_cheb", "ld_logdet_cheb_grad", "ld_logdet_cheb_batched",
                   "ld_gershgorin", "ld_probes", "ld_transpose", "ld_copy", "ld_clear_cache", "ld_laplacian_minor",
                   "ld_log_spanning_trees", "ld_logdet_taylor", "ld_quadratic_form", "ld_gershgorin_batched"):
             getattr(L, f).restype = I
@@ -193,6 +194,27 @@ def ld_logdet_cheb(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, 
     cb = B.c()
     rc = _check(lib().ld_logdet_cheb(ctypes.byref(cb), float(a), float(b), int(n), int(M), int(seed) & (2**64 - 1),
                                      ctypes.byref(o), _stream_ptr(stream), ctypes.byref(r)), "ld_logdet_cheb")
+    out = _result(r, rc)
+    if mom is not None:
+        out["moments"] = mom
+    if pv is not None:
+        out["s"] = pv
+    return out
+
+
+def ld_logdet_cheb_noalloc(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, *, vec_f64=None, tile=0,
+                           probe_tile=0, want_moments=False, want_probes=False, plain=False, stream=None) -> dict:
+    """ld_logdet_cheb on the library's fixed scratch array: no device allocation (64 MiB limit)."""
+    import numpy as np
+
+    mom = np.zeros((M, n + 1)) if want_moments else None
+    pv = np.zeros(M) if want_probes else None
+    o = _opts(vec_f64, tile, False, None, moments=mom, probes=pv, probe_tile=probe_tile, plain=plain)
+    r = _Result()
+    cb = B.c()
+    rc = _check(lib().ld_logdet_cheb_noalloc(ctypes.byref(cb), float(a), float(b), int(n), int(M),
+                                             int(seed) & (2**64 - 1), ctypes.byref(o), _stream_ptr(stream),
+                                             ctypes.byref(r)), "ld_logdet_cheb_noalloc")
     out = _result(r, rc)
     if mom is not None:
         out["moments"] = mom

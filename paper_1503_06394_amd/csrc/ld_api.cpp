@@ -585,8 +585,10 @@ size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, const 
 }
 
 // Shared body of ld_logdet_cheb and ld_logabsdet_cheb.
+// fixed_plan: no autotuning and no timing events (the planner's default shape), for callers that
+// must not allocate; the workspace is then always opt->workspace.
 int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double b, int n, int M_out, uint64_t seed,
-                const ld_opts* opt, hipStream_t s, ld_result* out) {
+                const ld_opts* opt, hipStream_t s, ld_result* out, bool fixed_plan = false) {
   const int valt = valt_of(B->dtype);
   const int vec_f64 = vec_f64_of(opt, valt);
   const int64_t d = B->rows;
@@ -625,7 +627,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       Ct.values = valt_;
     }
   }
-  const bool tune = (!opt || opt->tile == 0) && autotune_enabled() && d >= 65536;
+  const bool tune = !fixed_plan && (!opt || opt->tile == 0) && autotune_enabled() && d >= 65536;
   double* part_base =
       static_cast<double*>(cv.take((size_t)std::max(nrows, 1) * max_tiles(B, vec_f64, M, opt) * M * 8));
   double* red_out = static_cast<double*>(cv.take((size_t)M * std::max(nrows, 1) * 8));
@@ -661,7 +663,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
   const int64_t kstride = p.ntiles * M;
 
   StepTimer tm;
-  tm.on = opt && opt->timing;
+  tm.on = !fixed_plan && opt && opt->timing;
   tm.s = s;
 
   StepLaunch L{};
@@ -1284,6 +1286,42 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
 // C ABI
 // ======================================================================================
 
+// ------------------------------------------------------------------------------------
+// Forward without allocation: the workspace is a fixed device array of the library
+// ------------------------------------------------------------------------------------
+
+namespace {
+
+// Device memory of ld_logdet_cheb_noalloc: one copy per GPU the library runs on, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the device array:
+// every host use goes through the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[LD_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> device address of its copy of `scratch`
+
+// Address of the current device's `scratch`, looked up once per device (with it current).
+int scratch_address(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *ptr = it->second;
+    return LD_OK;
+  }
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+  if (!p || reinterpret_cast<uintptr_t>(p) % kAlign) return fail(LD_EHIP, "scratch has no aligned device address");
+  g_scratch_addr[dev] = p;
+  *ptr = p;
+  return LD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ld_last_error(void) { return g_err; }
@@ -1310,6 +1348,33 @@ static int logdet_cheb_impl(const ld_csr* B, double a, double b, int n, int M, u
   if (!out) return fail(LD_EINVAL, "out is NULL");
   ld_result r{};
   rc = run_forward(B, nullptr, false, a, b, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
+  if (rc < 0) return rc;
+  *out = r;
+  return rc;
+}
+
+static int logdet_cheb_noalloc_impl(const ld_csr* B, double a, double b, int n, int M, uint64_t seed,
+                                    const ld_opts* opt, void* stream, ld_result* out) {
+  int rc = check_csr(B, "B");
+  if (rc) return rc;
+  rc = check_common(a, b, n, M);
+  if (rc) return rc;
+  if (!out) return fail(LD_EINVAL, "out is NULL");
+  if (opt && opt->workspace) return fail(LD_EINVAL, "ld_logdet_cheb_noalloc takes no workspace (opt->workspace)");
+  ld_opts o{};
+  if (opt) o = *opt;
+  const int vec_f64 = vec_f64_of(&o, valt_of(B->dtype));
+  const size_t need = fwd_workspace(B, n, M, vec_f64, false, &o);
+  if (need > (size_t)LD_NOALLOC_SCRATCH_BYTES)
+    return fail(LD_EWORKSPACE, "ld_logdet_cheb_noalloc needs %zu bytes of scratch; its limit is %zu bytes", need,
+                (size_t)LD_NOALLOC_SCRATCH_BYTES);
+  void* base = nullptr;
+  rc = scratch_address(&base);
+  if (rc) return rc;
+  o.workspace = base;
+  o.workspace_bytes = LD_NOALLOC_SCRATCH_BYTES;
+  ld_result r{};
+  rc = run_forward(B, nullptr, false, a, b, n, M, seed, &o, static_cast<hipStream_t>(stream), &r, true);
   if (rc < 0) return rc;
   *out = r;
   return rc;
@@ -2227,6 +2292,11 @@ size_t ld_workspace_bytes(const ld_csr* B, int n, int M, int mode, int vec_f64) 
 int ld_logdet_cheb(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
                    void* stream, ld_result* out) {
   return guarded<int>([&] { return logdet_cheb_impl(B, a, b, n, M, seed, opt, stream, out); });
+}
+
+int ld_logdet_cheb_noalloc(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,
+                           void* stream, ld_result* out) {
+  return guarded<int>([&] { return logdet_cheb_noalloc_impl(B, a, b, n, M, seed, opt, stream, out); });
 }
 
 int ld_logdet_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt,

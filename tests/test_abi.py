@@ -95,3 +95,23 @@ def test_product_package_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text and "ldo_" not in text, f
+
+
+def test_noalloc_refusals_happen_on_the_host(built_lib):
+    """ld_logdet_cheb_noalloc refuses a caller workspace (LD_EINVAL) and a problem beyond its fixed
+    scratch array (LD_EWORKSPACE) before any HIP call; the array pointers here are never read."""
+    import paper_1503_06394_amd as pkg
+
+    L = pkg.lib()
+    r = pkg._Result()
+    fake = 0x1000
+    big = pkg._CSR(1_000_000, 1_000_000, 5_000_000, fake, fake, fake, 1, 0, 0.0)
+    assert L.ld_logdet_cheb_noalloc(ctypes.byref(big), 0.5, 2.0, 10, 64, 0, None, None, ctypes.byref(r)) == -3
+    assert b"scratch" in L.ld_last_error()
+    o = pkg._Opts()
+    o.workspace = fake
+    o.workspace_bytes = 1 << 20
+    small = pkg._CSR(100, 100, 100, fake, fake, fake, 1, 0, 0.0)
+    assert L.ld_logdet_cheb_noalloc(ctypes.byref(small), 0.5, 2.0, 10, 8, 0, ctypes.byref(o), None,
+                                    ctypes.byref(r)) == -1
+    assert b"workspace" in L.ld_last_error()
