@@ -132,10 +132,13 @@ def adjoint_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_
     return csr_bytes(d, nnz, val_bytes) + 4 * d * M * vec_bytes + 2 * nnz * acc_bytes
 
 
-def adjoint_moved_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int) -> int:
-    """What the paired-form adjoint kernel must move besides: its seed reads w_{j-1} and w_{j+1}
-    (the product identities' derivative), and int64 row pointers."""
-    return adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, acc_bytes) + 2 * d * M * vec_bytes + (d + 1) * 4
+def adjoint_moved_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int,
+                        form: str | None) -> int:
+    """What the adjoint kernel moves besides, by the form that ran: the explicit seed of the
+    product-identity form reads w_{j-1} and w_{j+1} as well; the shifted form (and the plain
+    recurrence) move no extra vector block; int64 row pointers in every form."""
+    extra = 2 * d * M * vec_bytes if form in ("explicit_single", "explicit_two") else 0
+    return adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, acc_bytes) + extra + (d + 1) * 4
 
 
 def traffic_from_profiles(kernel_tag: str, workload_name: str):
@@ -369,7 +372,7 @@ def main() -> None:
     ab_ = adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes)
     if adj_ms > step_ms and adj_n > 0:
         tag, avg_ms, bytes_ = "adjoint", adj_ms / adj_n, ab_
-        moved = adjoint_moved_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes)
+        moved = adjoint_moved_bytes(d, nnz, M, val_bytes, vec_bytes, vec_bytes, r.get("adjoint_form"))
     else:
         tag, avg_ms, bytes_ = "step", step_ms / max(step_n, 1), sb
         moved = sb + (d + 1) * 4
@@ -379,6 +382,8 @@ def main() -> None:
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": f"{tag} kernel",
             "avg_launch_ms": round(avg_ms, 5), "algorithmic_bytes_per_launch": bytes_,
             "moved_bytes_per_launch": moved, "moved_GBps": round(moved / (avg_ms / 1e3) / 1e9, 1)}
+    if tag == "adjoint":
+        roof["adjoint_form"] = r.get("adjoint_form")
     if traffic is not None:
         roof["traffic_GBps"] = round(traffic / (avg_ms / 1e3) / 1e9, 1)  # counted bytes at the live launch time
         roof["traffic_over_algorithmic"] = round(traffic / bytes_, 3)

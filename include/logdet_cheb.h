@@ -78,7 +78,21 @@ typedef struct {
     int32_t adjoint_launches;
     int32_t n, M;
     uint32_t flags;         /* bit 0: LD_WBOUNDS seen */
+    int32_t adjoint_form;   /* gradient entry point: how its adjoint ran (LD_ADJ_*); 0 elsewhere */
 } ld_result;
+
+/* ld_result.adjoint_form.  The product-identity forward (symmetric pattern) has two adjoints:
+ * the explicit one streams w_{k-1}, w_k, w_{k+1} for its seed and gathers one row of y_{k+1} per
+ * stored entry; the shifted one carries y_k + eps_k w_{k-1} instead, which cancels the w_{k-1}
+ * and w_{k+1} terms, and reads rows of both y_{k+1} and w_k per entry: two vector blocks less per
+ * step.  The shifted form runs by default on stencil patterns, from vector tiles staged in LDS;
+ * elsewhere the explicit form runs (LD_GRAD_FORM=shifted|explicit in the environment forces one). */
+#define LD_ADJ_EXPLICIT_SINGLE 1 /* explicit seed, one gather per entry (transposed-entry trick) */
+#define LD_ADJ_EXPLICIT_TWO 2    /* explicit seed, two gathers per entry */
+#define LD_ADJ_SHIFTED 3         /* shifted form, two gathers per entry from global memory */
+#define LD_ADJ_PLAIN 4           /* plain recurrence: single-gather adjoint on B^T */
+#define LD_ADJ_SHIFTED_STAGED 5  /* shifted form on vector tiles staged in LDS (stencil patterns:
+                                    the rows a tile reaches are its own and a fixed offset list) */
 
 typedef struct {
     void *workspace;          /* device scratch, 256-byte aligned (LD_EINVAL otherwise), or NULL:

@@ -32,6 +32,9 @@ LD_WBOUNDS = 1
 _DTYPE = {torch.float64: LD_F64, torch.float32: LD_F32, torch.bfloat16: LD_BF16}
 
 
+_ADJ_FORMS = {0: None, 1: "explicit_single", 2: "explicit_two", 3: "shifted", 4: "plain", 5: "shifted_staged"}
+
+
 class LogdetChebError(RuntimeError):
     pass
 
@@ -50,6 +53,7 @@ class _Result(ctypes.Structure):
         ("grad_shift", ctypes.c_double), ("kernel_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double),
         ("kernel_launches", ctypes.c_int32), ("adjoint_launches", ctypes.c_int32),
         ("n", ctypes.c_int32), ("M", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("adjoint_form", ctypes.c_int32),
     ]
 
 
@@ -178,7 +182,7 @@ def _result(r: _Result, rc: int) -> dict:
     return {"logdet": r.logdet, "std_err": r.std_err, "poly_bound": r.poly_bound, "grad_shift": r.grad_shift,
             "kernel_ms": r.kernel_ms, "kernel_launches": r.kernel_launches, "adjoint_ms": r.adjoint_ms,
             "adjoint_launches": r.adjoint_launches, "n": r.n, "M": r.M,
-            "flags": r.flags, "status": rc}
+            "flags": r.flags, "adjoint_form": _ADJ_FORMS.get(r.adjoint_form), "status": rc}
 
 
 def ld_logdet_cheb(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, *, vec_f64=None, tile=0,

@@ -18,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -328,6 +329,16 @@ std::map<TuneKey, Shape> g_tune;
 bool sym_enabled() {
   const char* e = std::getenv("LD_GRAD_SYM");
   return !(e && e[0] == '0');
+}
+
+// Form of the paired adjoint: LD_GRAD_FORM=shifted or =explicit forces one (for tests); otherwise
+// -1 (chosen from the pattern).
+int grad_form_override() {
+  const char* e = std::getenv("LD_GRAD_FORM");
+  if (!e) return -1;
+  if (std::strcmp(e, "shifted") == 0) return 1;
+  if (std::strcmp(e, "explicit") == 0) return 0;
+  return -1;
 }
 
 // LD_AUTOTUNE=0 keeps the default tile height and probe layout (no timing of candidates).
@@ -932,8 +943,30 @@ int64_t tiles_of(const ld_csr* B, const Shape& sh) {
 //         device and compares once its results are back (no extra synchronisation); a pattern
 //         rewritten in place at the same addresses is then analysed afresh and the call repeated.
 // Only the first call on a pattern synchronises to learn its symmetry.
+// Stencil plan of a pattern for staged tiles of `tr` rows (see StencilDesc), with the per-call
+// buffers of the padded layout (values, accumulators); `mu` serialises the calls that use them.
+struct StencilPlan {
+  int tr = 0, K = 0, nofs = 0, nruns = 0;
+  int run_base[kStencilRuns] = {}, run_delta[kStencilRuns] = {};
+  int64_t ntiles = 0, slots = 0;  // tiles, entry slots (ntiles * tr * K)
+  uint16_t* lcol = nullptr;
+  int32_t* emap = nullptr;
+  int64_t* dslot = nullptr;  // [d] slot of each row's diagonal entry
+  void* ent = nullptr;       // 16 bytes per slot: room for any packed entry
+  void* hacc = nullptr;      // 8 bytes per slot: room for either accumulator type
+  std::mutex mu;
+  ~StencilPlan() {
+    for (void* p : {(void*)lcol, (void*)emap, (void*)dslot, ent, hacc})
+      if (p) (void)hipFree(p);
+  }
+};
+
 struct PatternInfo {
   bool sym = false;
+  std::mutex stencil_mu;
+  std::map<std::pair<int, int>, std::shared_ptr<StencilPlan>> stencil;  // (tr, offset capacity) -> plan, or null:
+                                                                        // not a stencil pattern for that tile
+  uint64_t dist_hist[kDistBins] = {};  // entries per bit length of |i - j| (launch_distance_hist)
   int64_t* perm = nullptr;
   int64_t* rp_t = nullptr;
   int32_t* col_t = nullptr;
@@ -989,18 +1022,22 @@ struct DevTmp {
 
 int analyze_pattern(const ld_csr* B, hipStream_t s, PatternInfo& P) {
   const int64_t d = B->rows, nnz = B->nnz;
-  DevTmp scratch;  // [0]: missing flag (int), [8]: hash (uint64)
-  LD_HIP(hipMalloc(&scratch.p, 256));
+  DevTmp scratch;  // [0]: missing flag (int), [8]: hash (uint64), [64]: distance histogram
+  LD_HIP(hipMalloc(&scratch.p, 512));
   int* missing = static_cast<int*>(scratch.p);
   uint64_t* hash = reinterpret_cast<uint64_t*>(static_cast<char*>(scratch.p) + 8);
+  unsigned long long* hist = reinterpret_cast<unsigned long long*>(static_cast<char*>(scratch.p) + 64);
+  static_assert(64 + kDistBins * 8 <= 512, "pattern analysis scratch");
   int rc = dev_alloc(&P.perm, (size_t)nnz, "the transposed-entry index");
   if (rc) return rc;
-  LD_HIP(launch_fill_zero(missing, sizeof(int), s));
+  LD_HIP(launch_fill_zero(scratch.p, 512, s));
   LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, nnz, P.perm, missing, s));
   LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, nnz, hash, s));
+  LD_HIP(launch_distance_hist(B->row_ptr, B->col_idx, d, nnz, hist, s));
   int miss = 0;
   LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
   LD_HIP(hipMemcpyAsync(&P.hash, hash, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipMemcpyAsync(P.dist_hist, hist, sizeof(P.dist_hist), hipMemcpyDeviceToHost, s));
   LD_HIP(hipStreamSynchronize(s));
   P.sym = miss == 0;
   if (P.sym) return LD_OK;
@@ -1055,13 +1092,225 @@ void drop_pattern(const ld_csr* B) {
   g_pat.erase(key);
 }
 
+// Builds the stencil plan on the host from a copy of the pattern, or leaves `out` null when the
+// pattern is not one for tiles of `tr` rows: more than `cap` distinct offsets (column - tile's first
+// row) outside the tile over all tiles, or more than kStencilRuns runs of them, rows longer than
+// kStencilK, a row without its diagonal, or a padded layout more than 1.5 times the stored entries.  Tiles are independent, so ranges of them are scanned on several
+// host threads.
+int build_stencil_plan(const ld_csr* B, hipStream_t s, int tr, int cap, std::shared_ptr<StencilPlan>& out) {
+  out.reset();
+  const int64_t d = B->rows, nnz = B->nnz;
+  if (d <= 0 || nnz <= 0 || nnz > (int64_t)INT32_MAX) return LD_OK;
+  std::vector<int64_t> rp((size_t)d + 1);
+  std::vector<int32_t> col((size_t)nnz);
+  LD_HIP(hipMemcpyAsync(rp.data(), B->row_ptr, (size_t)(d + 1) * 8, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipMemcpyAsync(col.data(), B->col_idx, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  int K = 0;
+  for (int64_t r = 0; r < d; ++r) K = std::max<int64_t>(K, rp[(size_t)r + 1] - rp[(size_t)r]);
+  const int64_t nt = (d + tr - 1) / tr;
+  if (K < 1 || K > kStencilK) return LD_OK;
+  if (K != 5 && K != 7) K = kStencilK;  // the kernel's padded widths
+  std::vector<int64_t> ds((size_t)d, -1);
+  if ((double)nt * tr * K > 1.5 * (double)nnz) return LD_OK;
+  // distinct outside offsets, per thread, then merged
+  const int nthr = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                                 (nt + 4095) / 4096}));
+  std::vector<std::vector<int64_t>> offs((size_t)nthr);
+  std::vector<char> over((size_t)nthr, 0);
+  auto scan = [&](int w) {
+    const int64_t t0 = nt * w / nthr, t1 = nt * (w + 1) / nthr;
+    std::vector<int64_t>& o = offs[(size_t)w];
+    for (int64_t t = t0; t < t1 && !over[(size_t)w]; ++t) {
+      const int64_t r0 = t * tr, r1 = std::min<int64_t>(d, r0 + tr);
+      for (int64_t e = rp[(size_t)r0]; e < rp[(size_t)r1]; ++e) {
+        const int64_t c = col[(size_t)e];
+        if (c < r0 || c >= r1) o.push_back(c - r0);
+      }
+      if ((t & 63) == 63 || t + 1 == t1) {
+        std::sort(o.begin(), o.end());
+        o.erase(std::unique(o.begin(), o.end()), o.end());
+        if ((int64_t)o.size() > cap) over[(size_t)w] = 1;
+      }
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int w = 1; w < nthr; ++w) th.emplace_back(scan, w);
+    scan(0);
+    for (auto& x : th) x.join();
+  }
+  std::vector<int64_t> ofs;
+  for (int w = 0; w < nthr; ++w) {
+    if (over[(size_t)w]) return LD_OK;
+    ofs.insert(ofs.end(), offs[(size_t)w].begin(), offs[(size_t)w].end());
+  }
+  std::sort(ofs.begin(), ofs.end());
+  ofs.erase(std::unique(ofs.begin(), ofs.end()), ofs.end());
+  if ((int64_t)ofs.size() > cap) return LD_OK;
+  // the list as runs of consecutive offsets, passed to the kernel by value
+  std::vector<std::pair<int64_t, int64_t>> runs;
+  for (int64_t o : ofs) {
+    if (!runs.empty() && runs.back().first + runs.back().second == o)
+      ++runs.back().second;
+    else
+      runs.push_back({o, 1});
+  }
+  if ((int)runs.size() > kStencilRuns) return LD_OK;
+  // a halo beyond three tiles' worth of rows (3-D lattices: four) stages more than the entries save
+  // (measured on the 128^3 GMRF: 0.66 ms per step staged against 0.40 ms explicit)
+  if ((int64_t)ofs.size() > 3 * (int64_t)tr) return LD_OK;
+  for (auto& r : runs)
+    if (r.first < INT32_MIN / 2 || r.first > INT32_MAX / 2) return LD_OK;
+  // padded layout: slot (t * tr + lr) * K + k
+  const int64_t slots = nt * tr * K;
+  std::vector<uint16_t> lc((size_t)slots, 0);
+  std::vector<int32_t> em((size_t)slots, -1);
+  auto fill = [&](int w) {
+    const int64_t t0 = nt * w / nthr, t1 = nt * (w + 1) / nthr;
+    for (int64_t t = t0; t < t1; ++t) {
+      const int64_t r0 = t * tr, r1 = std::min<int64_t>(d, r0 + tr);
+      for (int64_t r = r0; r < r1; ++r) {
+        int64_t k = 0;
+        for (int64_t e = rp[(size_t)r]; e < rp[(size_t)r + 1]; ++e, ++k) {
+          const int64_t c = col[(size_t)e];
+          const size_t slot = (size_t)(r * K + k);
+          em[slot] = (int32_t)e;
+          if (c == r) ds[(size_t)r] = (int64_t)slot;
+          lc[slot] = (c >= r0 && c < r1)
+                         ? (uint16_t)(c - r0)
+                         : (uint16_t)(tr + (std::lower_bound(ofs.begin(), ofs.end(), c - r0) - ofs.begin()));
+        }
+      }
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int w = 1; w < nthr; ++w) th.emplace_back(fill, w);
+    fill(0);
+    for (auto& x : th) x.join();
+  }
+  for (int64_t r = 0; r < d; ++r)
+    if (ds[(size_t)r] < 0) return LD_OK;  // the shift's derivative is read off the diagonal entries
+  auto P = std::make_shared<StencilPlan>();
+  P->tr = tr;
+  P->K = K;
+  P->nofs = (int)ofs.size();
+  P->nruns = (int)runs.size();
+  int base = 0;
+  for (int i = 0; i < P->nruns; ++i) {
+    P->run_base[i] = base;
+    P->run_delta[i] = (int)runs[(size_t)i].first - base;  // halo index j of run i has offset j + delta
+    base += (int)runs[(size_t)i].second;
+  }
+  P->ntiles = nt;
+  P->slots = slots;
+  int rc;
+  if ((rc = dev_alloc(&P->lcol, (size_t)slots, "the stencil plan")) || (rc = dev_alloc(&P->emap, (size_t)slots, "the stencil plan")) ||
+      (rc = dev_alloc(&P->dslot, (size_t)d, "the stencil plan")))
+    return rc;
+  {
+    uint4* v = nullptr;
+    if ((rc = dev_alloc(&v, (size_t)slots, "the stencil plan"))) return rc;
+    P->ent = v;
+    double* h = nullptr;
+    if ((rc = dev_alloc(&h, (size_t)slots, "the stencil plan"))) return rc;
+    P->hacc = h;
+  }
+  LD_HIP(hipMemcpyAsync(P->dslot, ds.data(), (size_t)d * 8, hipMemcpyHostToDevice, s));
+  LD_HIP(hipMemcpyAsync(P->lcol, lc.data(), (size_t)slots * 2, hipMemcpyHostToDevice, s));
+  LD_HIP(hipMemcpyAsync(P->emap, em.data(), (size_t)slots * 4, hipMemcpyHostToDevice, s));
+  LD_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  out = P;
+  return LD_OK;
+}
+
+// Staged tiles only pay on patterns whose entries stay near their rows; a pattern is taken for a
+// stencil plan only when at most 1 % of its entries reach farther from their row than a 4 MiB window
+// of vector rows (one XCD's L2), which keeps scattered patterns from a pointless host scan.
+constexpr size_t kLocalWindowBytes = 4u << 20;
+
+bool local_pattern(const PatternInfo& P, int64_t nnz, size_t row_bytes) {
+  const uint64_t window = kLocalWindowBytes / std::max<size_t>(row_bytes, 1);
+  uint64_t far = 0;
+  for (int b = 1; b < kDistBins; ++b)  // bin b holds distances in [2^(b-1), 2^b - 1]
+    if (((1ull << b) - 1) > window) far += P.dist_hist[b];
+  return far * 100 <= (uint64_t)std::max<int64_t>(nnz, 0);
+}
+
+// The stencil plans whose per-call buffers a gradient call uses, locked in the order its passes
+// need them (every call takes its full-size passes' plan before its last pass's), and released
+// only once the call's stream has drained.
+struct StencilHold {
+  hipStream_t s = nullptr;
+  std::vector<StencilPlan*> held;
+  std::vector<std::unique_lock<std::mutex>> locks;
+  void take(StencilPlan* p) {
+    if (std::find(held.begin(), held.end(), p) != held.end()) return;
+    held.push_back(p);
+    locks.emplace_back(p->mu);
+  }
+  ~StencilHold() {
+    if (!locks.empty()) (void)hipStreamSynchronize(s);
+  }
+};
+
+// LD_STENCIL=0 keeps the shifted adjoint on global gathers (for tests).
+bool stencil_enabled() {
+  const char* e = std::getenv("LD_STENCIL");
+  return !(e && e[0] == '0');
+}
+
+// Staged tile of a gradient pass's shape: rows and offset capacity (0 rows: no staged form).
+std::pair<int, int> stencil_shape(const Shape& sh, size_t vb) {
+  const int tr = stencil_tile_rows(sh.lpr_log2);
+  if (tr > kStencilRows) return {0, 0};
+  const size_t slot_bytes = 2 * (size_t)((1 << sh.lpr_log2) * sh.vpl) * vb;
+  const int slots = (int)(kStencilLdsBytes / slot_bytes);
+  if (slots <= tr) return {0, 0};
+  return {tr, slots - tr};
+}
+
+// The cached stencil plan of a pattern for a pass shape (built on first use); null when the pattern
+// is not a stencil pattern for that tile.
+int get_stencil(PatternInfo& P, const ld_csr* B, hipStream_t s, const Shape& sh, size_t vb,
+                std::shared_ptr<StencilPlan>& out) {
+  out.reset();
+  const std::pair<int, int> ss = stencil_shape(sh, vb);
+  if (ss.first == 0 || B->rows <= 0) return LD_OK;
+  std::lock_guard<std::mutex> lk(P.stencil_mu);
+  auto it = P.stencil.find(ss);
+  if (it != P.stencil.end()) {
+    out = it->second;
+    return LD_OK;
+  }
+  std::shared_ptr<StencilPlan> S;
+  const int rc = build_stencil_plan(B, s, ss.first, ss.second, S);
+  if (rc) return rc;
+  P.stencil[ss] = S;
+  out = S;
+  return LD_OK;
+}
+
+// Diagonal partials any adjoint launch of a gradient call may write: one per tile of the pass
+// shapes, and at least the 256 of the staged steps' diagonal sum.
+int64_t grad_diag_tiles(const ld_csr* B, int M, int vec_f64, const ld_opts* opt) {
+  const GradChunks ch = grad_chunks(M, vec_f64);
+  int64_t nt = 0;
+  for (int mp : {ch.size, ch.last}) {
+    const Shape sh = grad_shape(B, mp, vec_f64, opt);
+    nt = std::max(nt, tiles_of(B, sh));
+  }
+  return std::max<int64_t>(nt, 256);  // the staged steps' diagonal sum writes 256 partials
+}
+
 size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_opts* opt, int stride, bool pair) {
   const size_t vb = vec_f64 ? 8 : 4;
   const GradPlan g = plan_grad(n, pair, stride);
   const GradChunks ch = grad_chunks(M, vec_f64);
   const int64_t nt_full = tiles_of(B, grad_shape(B, ch.size, vec_f64, opt));
   const int64_t nt_last = tiles_of(B, grad_shape(B, ch.last, vec_f64, opt));
-  const int64_t ntiles = std::max(nt_full, nt_last);
+  const int64_t ntiles = grad_diag_tiles(B, M, vec_f64, opt);
   const int64_t part_cols = std::max(nt_full * ch.size, nt_last * ch.last);  // per partial row
   const int rows = std::max(partial_rows(n, g.pair), 1);
   Carve c;
@@ -1657,8 +1906,7 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
   // the probes run in passes of ch.size (the last one ch.last); the gradient accumulators and
   // the per-probe moments collect over the passes
   const GradChunks ch = grad_chunks(M, vec_f64);
-  const int64_t nt_max =
-      std::max(tiles_of(B, grad_shape(B, ch.size, vec_f64, opt)), tiles_of(B, grad_shape(B, ch.last, vec_f64, opt)));
+  const int64_t nt_max = grad_diag_tiles(B, M, vec_f64, opt);
   const int64_t part_cols = std::max(tiles_of(B, grad_shape(B, ch.size, vec_f64, opt)) * ch.size,
                                      tiles_of(B, grad_shape(B, ch.last, vec_f64, opt)) * ch.last);
   const GradStrides strides = choose_strides(B, n, M, vec_f64, opt);
@@ -1733,10 +1981,33 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
   LD_HIP(launch_fill_zero(Gacc, (size_t)B->nnz * vb, s));
   LD_HIP(launch_fill_zero(gdiag_part, (size_t)std::max<int64_t>(nt_max, 1) * 8, s));
   LD_HIP(tm.mark(T_OTHER));
-  // single-gather adjoint: on B^T always; on B when its pattern is symmetric (LD_GRAD_SYM=0 keeps
-  // the two-gather form there, for tests)
-  const bool sym = !pair || (sym_pattern && sym_enabled());
+  // Adjoint form.  Plain: single-gather on B^T.  Paired (symmetric pattern): the shifted two-gather
+  // form for local patterns (two vector blocks less per step), otherwise the single-gather form with
+  // the explicit seed (LD_GRAD_SYM=0 keeps the two-gather form there, for tests).
+  // The shifted form is taken on its own only with staged tiles (its two gathers per entry from
+  // global memory are slower than the explicit form's one): when the pattern is a stencil pattern
+  // for the passes' tiles.
+  const int form = grad_form_override();
+  const bool stencil_on = stencil_enabled();
+  bool shifted = pair && form == 1;
+  if (pair && form < 0 && pat && stencil_on && local_pattern(*pat, B->nnz, (size_t)ch.size * vb)) {
+    std::shared_ptr<StencilPlan> sp0;
+    rc = get_stencil(*pat, B, s, grad_shape(B, ch.size, vec_f64, opt), vb, sp0);
+    if (rc) return rc;
+    shifted = sp0 != nullptr;
+  }
+  const bool sym = !pair || (!shifted && sym_pattern && sym_enabled());
+  // Shifted adjoint: Y holds yh_j = y_j + eps_j w_{j-1}, with eps_j = eps_{j+2} + al[j] - al[j-1]
+  // (eps_{top+1} = eps_{top+2} = 0), which cancels every w_{j-1} term of the seed, and step j runs
+  // its product on z = yh_{j+1} + kap_j w_j, kap_j = al[j] - eps_{j+1} + eps_{j+2}, using
+  // w_{j+1} = 2 At w_j - w_{j-1}:  yh_j = 2 At z - yh_{j+2} + 2 be[j-1] w_j,  yh_top = 2 be[top-1] w_top.
+  std::vector<double> eps(g.top + 3, 0.0);
+  if (shifted)
+    for (int j = g.top; j >= 1; --j) eps[j] = eps[j + 2] + (j < (int)al.size() ? al[j] : 0.0) - al[j - 1];
   std::vector<double> red((size_t)M * rows_alloc, 0.0);  // per-probe partial rows, all passes
+  StencilHold sp_hold;
+  sp_hold.s = s;
+  int staged_passes = 0;  // passes whose adjoint ran on staged stencil tiles
 
   for (int pass = 0; pass < ch.count; ++pass) {
     const int probe0 = pass * ch.size;  // a multiple of 64 whenever there is more than one pass
@@ -1745,6 +2016,26 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
     const Shape sh = grad_shape(B, Mp, vec_f64, opt);
     const int64_t ntiles = tiles_of(B, sh);
     const int64_t kstride = ntiles * Mp;
+    std::shared_ptr<StencilPlan> sp;  // staged tiles of this pass's shifted adjoint
+    if (shifted && stencil_on && pat) {
+      rc = get_stencil(*pat, B, s, sh, vb, sp);
+      if (rc) return rc;
+    }
+    StencilDesc sd{};
+    if (sp) {
+      ++staged_passes;
+      sp_hold.take(sp.get());  // its per-call buffers, until this call's stream has drained
+      sd = StencilDesc{};
+      sd.ent = sp->ent;
+      sd.hacc = sp->hacc;
+      sd.K = sp->K;
+      sd.nofs = sp->nofs;
+      sd.nruns = sp->nruns;
+      std::copy(sp->run_base, sp->run_base + kStencilRuns, sd.run_base);
+      std::copy(sp->run_delta, sp->run_delta + kStencilRuns, sd.run_delta);
+      LD_HIP(launch_stencil_pack(B->values, valt, sp->emap, sp->lcol, sp->slots, sp->ent, s));
+      LD_HIP(launch_fill_zero(sp->hacc, (size_t)sp->slots * vb, s));
+    }
     StepLaunch L{};
     L.nmat = 1;
     L.ntiles = ntiles;
@@ -1809,6 +2100,9 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
       // y_top: c_n V (plain) or al[top-1] W_{top-1} + 2 be[top-1] W_top (pairs; W_0 = V)
       if (!pair) {
         LD_HIP(launch_seed(Ya, vec_f64, nullptr, nullptr, nullptr, c[n], 0.0, 0.0, 0.0, pseed, d, Mp, s));
+      } else if (shifted) {
+        const int t = g.top;
+        LD_HIP(launch_seed(Ya, vec_f64, ckpt(t), nullptr, nullptr, 0.0, 2.0 * be[t - 1], 0.0, 0.0, pseed, d, Mp, s));
       } else {
         const int t = g.top;
         LD_HIP(launch_seed(Ya, vec_f64, ckpt(t), t - 1 >= 1 ? ckpt(t - 1) : nullptr, nullptr,
@@ -1850,10 +2144,17 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
           A.out = o;
           A.W = segW[j - lo + 1];
           A.gw = 2.0;
+          A.ck = A.ce = 0.0;
           if (!pair) {
             A.cv = c[j];
             A.cw = A.cwm = A.cwp = 0.0;
             A.Wm = A.Wp = nullptr;
+          } else if (shifted) {
+            A.cw = 2.0 * be[j - 1];
+            A.cv = A.cwm = A.cwp = 0.0;
+            A.Wm = A.Wp = nullptr;
+            A.ck = al[j] - eps[j + 1] + eps[j + 2];
+            A.ce = eps[j + 1];
           } else {
             A.cw = 2.0 * be[j - 1];
             A.cv = j - 1 == 0 ? al[j - 1] : 0.0;  // W_0 = V
@@ -1862,11 +2163,18 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
             A.Wp = segW[j - lo + 2];
             A.cwp = al[j];
           }
-          LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, true, false, y2 != nullptr, sym, s));
+          if (sp)
+            LD_HIP(launch_adjoint_stencil(A, sd, Mp, sh, vec_f64, valt, y2 != nullptr, s));
+          else
+            LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, true, false, y2 != nullptr, sym, s));
           LD_HIP(tm.mark(T_ADJ));
           y2 = y1;
           y1 = o;
         }
+      }
+      if (sp) {  // the staged steps' accumulators: the shift's derivative off the diagonal, then entry order
+        LD_HIP(launch_stencil_diag_sum(sp->hacc, vec_f64, sp->dslot, d, gdiag_part, s));
+        LD_HIP(launch_stencil_unpack(sp->hacc, vec_f64, sp->emap, sp->slots, Gacc, s));
       }
       // the y_1 w_0^T term, w_0 = v
       A.Y1 = y1;
@@ -1875,6 +2183,8 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
       A.W = nullptr;
       A.Wm = A.Wp = nullptr;
       A.cv = A.cw = A.cwm = A.cwp = 0.0;
+      A.ck = 0.0;
+      A.ce = shifted ? eps[1] : 0.0;  // y_1 = yh_1 - eps_1 w_0
       A.gw = 1.0;
       LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, false, true, false, sym, s));
       LD_HIP(tm.mark(T_ADJ));
@@ -1912,6 +2222,10 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
   combine(mu, c, n, M, d, 1.0, &r, opt);
   r.poly_bound = lemma_bound(a, b, n, d);
   r.grad_shift = scale * gd;
+  r.adjoint_form = !pair      ? LD_ADJ_PLAIN
+                   : shifted  ? (staged_passes == ch.count ? LD_ADJ_SHIFTED_STAGED : LD_ADJ_SHIFTED)
+                   : sym      ? LD_ADJ_EXPLICIT_SINGLE
+                              : LD_ADJ_EXPLICIT_TWO;
   tm.report(&r);
   *out = r;
   return r.flags ? LD_WBOUNDS : LD_OK;

@@ -87,6 +87,11 @@ hipError_t launch_step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int
 //   gdiag_part[tile] += gw * sum_p y1[r,p] * W[r,p]
 //   with spmm the new vector also takes the seed  cw * W[r,:] + cwm * Wm[r,:] + cwp * Wp[r,:]
 //   (Wm, Wp nullable): the direct derivative of the estimate with respect to w_k.
+// Two-gather form only (sym off), the shifted adjoint: Y1 holds yh = y + ce * W (yh_{k+1} =
+// y_{k+1} + eps_{k+1} w_k), and the product runs on z = Y1 + ck * W:
+//   out[r,:] = ag * sum_t val[t] z[col[t],:] + bd * z[r,:] + cp * Y2[r,:] + cw * W[r,:] + ...
+//   G[t] += gw * sum_p (Y1[r,p] - ce * W[r,p]) * W[col[t],p]
+// (ck = ce = 0 is the plain two-gather form).
 struct AdjDesc {
   const int64_t* row_ptr;
   const int32_t* col;
@@ -100,9 +105,50 @@ struct AdjDesc {
   void* Gacc;      // nnz accumulators (float for FP32 vectors, double for FP64)
   double* gdiag_part;  // [tiles] doubles
   double ag, bd, cp, cv, gw, cw, cwm, cwp;
+  double ck, ce;  // shifted adjoint (two-gather form): z = Y1 + ck W in the product, y = Y1 - ce W in G
   uint64_t seed;
   int64_t d;
 };
+
+// Vector tiles staged in LDS (the shifted adjoint on stencil patterns).  Tiles are one row pass of
+// a block, TR = 4 * 64 / LPR consecutive rows.  A pattern is a stencil pattern for TR when the rows
+// that tile t's entries reach outside the tile are always among r0 + ofs[j] for one short list of
+// offsets (grids and lattices in their natural order) and every row stores its diagonal: the block
+// then copies the rows of y_{k+1} and w_k for its own rows and r0 + ofs[j] (those inside [0, d))
+// into LDS, and every entry reads its operands from there.  Entries are kept in a padded layout, K
+// slots per row in tile order (slot (tile * TR + lr) * K + k), so that no address in the kernel
+// depends on a load: the packed entries (LDS slot of the column -- own row r0 + c at c, offset
+// ofs[j] at TR + j -- with its value) and the gradient accumulators live in that layout, and emap
+// carries a slot back to its stored entry (-1: padding).
+constexpr int kStencilRuns = 8;   // the offset list as at most this many runs of consecutive offsets
+struct StencilDesc {
+  const void* ent;  // [ntiles * TR * K] packed entries: BF16 values: uint32 (value bits << 16 | slot);
+                    // FP32: (slot, value bits) as 2 x uint32; FP64: (slot, 0, value) as 16 bytes
+  void* hacc;       // [ntiles * TR * K] gradient accumulators (vector type) per entry slot
+  int K, nofs, nruns;
+  int run_base[kStencilRuns];   // first LDS halo index of each run (prefix sums of the run lengths)
+  int run_delta[kStencilRuns];  // offset of halo index j in run q: j + run_delta[q]
+};
+constexpr int kStencilRows = 64;  // largest staged tile
+constexpr int kStencilK = 8;      // most entries per row (K of 5 and 7, the 2-D and 3-D grids, run exactly)
+constexpr int kStencilLdsBytes = 48 << 10;  // LDS for the two staged vector tiles (y_{k+1}, w_k)
+inline int stencil_tile_rows(int lpr_log2) { return 4 * (64 >> lpr_log2); }
+inline size_t stencil_entry_bytes(int valt) { return valt == VAL_BF16 ? 4 : (valt == VAL_F32 ? 8 : 16); }
+
+// The shifted adjoint step (spmm, ck/ce, no Wm/Wp) on staged stencil tiles; the SDDMM accumulates
+// into S.hacc (the diagonal entries' accumulators carry the shift's derivative; no gdiag partials).
+hipError_t launch_adjoint_stencil(const AdjDesc& A, const StencilDesc& S, int M, const Shape& sh, int vec_f64,
+                                  int valt, bool y2, hipStream_t s);
+// ent[i] = packed (lcol[i], emap[i] >= 0 ? val[emap[i]] : 0), i < n.
+hipError_t launch_stencil_pack(const void* val, int valt, const int32_t* emap, const uint16_t* lcol, int64_t n,
+                               void* ent, hipStream_t s);
+// acc[emap[i]] += hacc[i] for emap[i] >= 0 (every stored entry appears once), i < n.
+hipError_t launch_stencil_unpack(const void* hacc, int vec_f64, const int32_t* emap, int64_t n, void* acc,
+                                 hipStream_t s);
+// part[b] += fixed-order partial sums of hacc[dslot[i]] over rows i (blocks b < 256): the staged
+// steps' share of d Gamma / d shift.
+hipError_t launch_stencil_diag_sum(const void* hacc, int vec_f64, const int64_t* dslot, int64_t d, double* part,
+                                   hipStream_t s);
 
 // out[r,:] = cv * V[r,:] + cw * W[r,:] + cwm * Wm[r,:] + cwp * Wp[r,:] (W, Wm, Wp nullable):
 // the adjoint's starting vector.
@@ -116,6 +162,12 @@ hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64,
 // perm[t] = index of the stored entry (col[t], row(t)); *missing |= 1 if some is absent.
 hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz, int64_t* perm,
                                   int* missing, hipStream_t s);
+
+// hist[b] += count of stored entries (i, j) with bit_length(|i - j|) = b, b < kDistBins (hist zeroed
+// by the caller; d <= 2^31 keeps b <= 32).
+constexpr int kDistBins = 33;
+hipError_t launch_distance_hist(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz,
+                                unsigned long long* hist, hipStream_t s);
 
 // out[t] = scale * (a[t] + a[perm[t]]) / 2
 hipError_t launch_sym_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,

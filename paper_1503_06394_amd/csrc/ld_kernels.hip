@@ -149,6 +149,10 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
 constexpr int kBlock = 256;  // 4 waves of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kUnroll = LD_UNROLL;  // nonzeros whose gathers are in flight together per row group
+#ifndef LD_UNROLL_STEP
+#define LD_UNROLL_STEP LD_UNROLL
+#endif
+constexpr int kUnrollStep = LD_UNROLL_STEP;  // the same for the recurrence step
 
 // ------------------------------------------------------------------------------------
 // fused recurrence step
@@ -262,12 +266,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = wk[i] = VT(0);
     bool hd = false;
-    for (int64_t t = s; t < e; t += kUnroll) {
-      int cc[kUnroll];
-      VT aa[kUnroll];
-      bool ok[kUnroll];
+    for (int64_t t = s; t < e; t += kUnrollStep) {
+      int cc[kUnrollStep];
+      VT aa[kUnrollStep];
+      bool ok[kUnrollStep];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < kUnrollStep; ++u) {
         ok[u] = t + u < e;
         int cu = 0;
         MV vu = MV(0);
@@ -290,9 +294,9 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
         aa[u] = a;
         cc[u] = cu;
       }
-      VT gg[kUnroll][VPL];
+      VT gg[kUnrollStep][VPL];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < kUnrollStep; ++u) {
         if (ok[u]) {
           if constexpr (GSRC == SRC_BUF)
             vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
@@ -304,12 +308,12 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
         }
       }
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < kUnrollStep; ++u)
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
       if constexpr (MU == MU_PAIR && DSRC == SRC_SAME) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+        for (int u = 0; u < kUnrollStep; ++u)
           if (ok[u] && cc[u] == row)
 #pragma unroll
             for (int i = 0; i < VPL; ++i) wk[i] = gg[u][i];
@@ -432,6 +436,7 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
   if (!pact) p0 = 0;
 
   const VT ag = (VT)A.ag, bd = (VT)A.bd, cp = (VT)A.cp, cv = (VT)A.cv, gw = (VT)A.gw;
+  const VT ck = (VT)A.ck, ce = (VT)A.ce;  // shifted adjoint (two-gather form); zero otherwise
   const VT* __restrict__ Y1 = static_cast<const VT*>(A.Y1);
   const VT* Y2p = static_cast<const VT*>(A.Y2);
   VT* out = static_cast<VT*>(A.out);
@@ -469,6 +474,11 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
 #pragma unroll
       for (int i = 0; i < VPL; ++i) yown[i] = wown[i] = VT(0);
     }
+    // y_{k+1} of the row (Y1 less the shift ce * w_k) for the SDDMM and the diagonal term; the
+    // single-gather form has no shift and keeps no copy (its register budget is tight)
+    VT ysd[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) ysd[i] = SYM ? VT(0) : fma(-ce, wown[i], yown[i]);
     VT acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = VT(0);
@@ -527,12 +537,17 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
         }
         if constexpr (SPMM) {
           const VT a = ag * (VT)vv[u];
+          if constexpr (SYM) {
 #pragma unroll
-          for (int i = 0; i < VPL; ++i) acc[i] = fma(a, yg[i], acc[i]);
+            for (int i = 0; i < VPL; ++i) acc[i] = fma(a, yg[i], acc[i]);
+          } else {  // product on z = Y1 + ck w_k
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) acc[i] = fma(a, fma(ck, wg[i], yg[i]), acc[i]);
+          }
         }
         VT dp = VT(0);
 #pragma unroll
-        for (int i = 0; i < VPL; ++i) dp = SYM ? fma(yg[i], wown[i], dp) : fma(yown[i], wg[i], dp);
+        for (int i = 0; i < VPL; ++i) dp = SYM ? fma(yg[i], wown[i], dp) : fma(ysd[i], wg[i], dp);
         dot[u] = dp;
       }
       if (wide) {
@@ -564,7 +579,7 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
     if (has) {
       double dd = 0.0;
 #pragma unroll
-      for (int i = 0; i < VPL; ++i) dd += (double)yown[i] * (double)wown[i];
+      for (int i = 0; i < VPL; ++i) dd += (double)(SYM ? yown[i] : ysd[i]) * (double)wown[i];
       gdiag += (double)A.gw * dd;
       if constexpr (SPMM) {
         VT vv[VPL];
@@ -572,7 +587,7 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
         const VT cw = (VT)A.cw;
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
-          VT o = fma(bd, yown[i], acc[i]);
+          VT o = fma(bd, SYM ? yown[i] : fma(ck, wown[i], yown[i]), acc[i]);
           o = fma(cw, wown[i], o);
           acc[i] = fma(cv, vv[i], o);
         }
@@ -604,6 +619,244 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
     for (int w = 0; w < kWaves; ++w) sum += sg[w];
     A.gdiag_part[tile] += sum;
   }
+}
+
+// ------------------------------------------------------------------------------------
+// shifted adjoint step on vector tiles staged in LDS (stencil patterns)
+// ------------------------------------------------------------------------------------
+
+// DPP lane exchange within a row of 16 lanes (a VALU operand modifier: no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, typename VT>
+__device__ __forceinline__ VT dpp_x(VT v) {
+  if constexpr (sizeof(VT) == 4)
+    return dpp_f32<CTRL>(v);
+  else
+    return dpp_f64<CTRL>(v);
+}
+
+// Sum over the LPR consecutive lanes of a row group (LPR a power of two), every lane receiving
+// the total: exchanges within quads, then the mirrored half-row and row, then (LPR >= 32) shuffles.
+template <typename VT>
+__device__ __forceinline__ VT row_sum(VT v, int LPR) {
+  if (LPR >= 2) v += dpp_x<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (LPR >= 4) v += dpp_x<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (LPR >= 8) v += dpp_x<0x141>(v);  // row_half_mirror: lane i of 8 <- lane 7 - i
+  if (LPR >= 16) v += dpp_x<0x140>(v); // row_mirror: lane i of 16 <- lane 15 - i
+  for (int o = 16; o < LPR; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Packed entry of the stencil layout: LDS slot of the column and the value.
+template <int VALT>
+struct StencilEnt;
+template <>
+struct StencilEnt<VAL_BF16> {
+  typedef uint32_t T;  // value bits << 16 | slot
+  __device__ static void get(const void* p, int64_t i, int& lc, float& v) {
+    const uint32_t w = static_cast<const uint32_t*>(p)[i];
+    lc = (int)(w & 0xFFFFu);
+    v = __uint_as_float(w & 0xFFFF0000u);
+  }
+};
+template <>
+struct StencilEnt<VAL_F32> {
+  typedef uint2 T;  // (slot, value bits)
+  __device__ static void get(const void* p, int64_t i, int& lc, float& v) {
+    const uint2 w = static_cast<const uint2*>(p)[i];
+    lc = (int)w.x;
+    v = __uint_as_float(w.y);
+  }
+};
+template <>
+struct StencilEnt<VAL_F64> {
+  typedef uint4 T;  // (slot, 0, value bits low, high)
+  __device__ static void get(const void* p, int64_t i, int& lc, double& v) {
+    const uint4 w = static_cast<const uint4*>(p)[i];
+    lc = (int)w.x;
+    v = __hiloint2double((int)w.w, (int)w.z);
+  }
+};
+
+// The shifted adjoint gathers rows of both y_{k+1} and w_k at every stored entry.  On a stencil
+// pattern the rows a tile's entries reach are its own rows and r0 + ofs[j] for a short offset list
+// (a few runs, passed by value), so the block copies those rows of both operands into LDS once, all
+// loads in flight together and none depending on another, and every entry reads them from there: a
+// vector row crosses the cache hierarchy (TR + nofs) / TR times per step instead of once per entry
+// that reaches it.  After the barrier each row loads its KK packed entry slots and accumulators
+// (arithmetic addresses in the padded layout), forms the product on z = y_{k+1} + ck w_k and the
+// SDDMM dots, sums each dot over the row's lanes with DPP exchanges, and writes the accumulators
+// back.  The diagonal entries' accumulators carry d Gamma / d shift, summed after the steps.
+template <typename VT, int VALT, int VPL, bool Y2, int KK>
+__global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, StencilDesc S, int M, int lpr_log2,
+                                                                 int64_t ntiles) {
+  typedef typename Val<VALT>::T MV;
+  const int64_t tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int LPR = 1 << lpr_log2;
+  const int RPW = 64 >> lpr_log2;
+  const int TR = kWaves * RPW;  // rows of the tile: one per lane group
+  const int sub = lane & (LPR - 1);
+  const int grp = lane >> lpr_log2;
+  const int tp = LPR * VPL;  // elements per staged row
+  const int64_t row0 = tile * TR;
+  const int nown = (int)min((int64_t)TR, A.d - row0);
+  int p0 = sub * VPL;
+  const bool pact = p0 < M;
+  if (!pact) p0 = 0;
+  const VT* __restrict__ Y1 = static_cast<const VT*>(A.Y1);
+  const VT* __restrict__ W = static_cast<const VT*>(A.W);
+
+  extern __shared__ __align__(16) unsigned char ld_stencil_smem[];
+  VT* Ys = reinterpret_cast<VT*>(ld_stencil_smem);
+  VT* Ws = Ys + (TR + S.nofs) * tp;
+
+  const int lr = wave * RPW + grp;
+  const bool has = lr < nown;
+  const int64_t row = row0 + (has ? lr : 0);
+  const int64_t roff = row * (int64_t)M + p0;
+
+  // ---- staging: own rows and the offset rows, every load independent of the others ----
+  VT yown[VPL], wown[VPL], x2[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) yown[i] = wown[i] = x2[i] = VT(0);
+  if (has && pact) {
+    vload<VT, VPL>(Y1 + roff, yown);
+    vload<VT, VPL>(W + roff, wown);
+    if constexpr (Y2) vload_nt<VT, VPL>(static_cast<const VT*>(A.Y2) + roff, x2);
+  }
+  for (int j = lr; j < S.nofs; j += TR) {
+    int off = j + S.run_delta[0];  // run q holds halo indices [run_base[q], run_base[q + 1])
+#pragma unroll
+    for (int q = 1; q < kStencilRuns; ++q)
+      if (q < S.nruns && j >= S.run_base[q]) off = j + S.run_delta[q];
+    const int64_t r = row0 + off;
+    VT y[VPL], w[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) y[i] = w[i] = VT(0);
+    if (r >= 0 && r < A.d && pact) {
+      vload<VT, VPL>(Y1 + r * M + p0, y);
+      vload<VT, VPL>(W + r * M + p0, w);
+    }
+    vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, y);
+    vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, w);
+  }
+  vstore<VT, VPL>(Ys + lr * tp + sub * VPL, yown);
+  vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
+
+  // the row's entry slots, issued before the barrier (their addresses do not depend on it); rows
+  // past the end read the tile's first row's slots (valid memory, results dropped), so that the KK
+  // consecutive loads carry no predicate and merge into wide ones
+  const int64_t e0 = (tile * TR + (has ? lr : 0)) * (int64_t)KK;
+  VT* __restrict__ hacc = static_cast<VT*>(S.hacc) + e0;
+  int lc[KK];
+  VT va[KK], h[KK];
+#pragma unroll
+  for (int k = 0; k < KK; ++k) {
+    MV v;
+    StencilEnt<VALT>::get(S.ent, e0 + k, lc[k], v);
+    va[k] = (VT)v;
+    h[k] = hacc[k];
+  }
+  __syncthreads();
+
+  const VT ag = (VT)A.ag, ck = (VT)A.ck, ce = (VT)A.ce, gw = (VT)A.gw;
+  VT ysd[VPL], acc[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    ysd[i] = fma(-ce, wown[i], yown[i]);
+    acc[i] = VT(0);
+  }
+#pragma unroll
+  for (int k = 0; k < KK; ++k) {
+    VT yg[VPL], wg[VPL];
+    vload<VT, VPL>(Ys + lc[k] * tp + sub * VPL, yg);
+    vload<VT, VPL>(Ws + lc[k] * tp + sub * VPL, wg);
+    const VT a = ag * va[k];
+    VT dp = VT(0);
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      acc[i] = fma(a, fma(ck, wg[i], yg[i]), acc[i]);
+      dp = fma(ysd[i], wg[i], dp);
+    }
+    h[k] = fma(gw, row_sum<VT>(dp, LPR), h[k]);
+  }
+  if (!has) return;
+  // every lane of the row holds the sums: lane 0 writes the KK slots back (padding too: never read out)
+  if (sub == 0)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) hacc[k] = h[k];
+  const VT bd = (VT)A.bd, cp = (VT)A.cp, cw = (VT)A.cw;
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) {
+    VT o = fma(bd, fma(ck, wown[i], yown[i]), acc[i]);
+    o = fma(cw, wown[i], o);
+    acc[i] = Y2 ? fma(cp, x2[i], o) : o;
+  }
+  if (A.cv != 0.0) {  // the probe term (absent in the shifted form's steps)
+    VT pv[VPL];
+    probe_signs<VT, VPL>(A.seed, row, p0, pv);
+    const VT cv = (VT)A.cv;
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) acc[i] = fma(cv, pv[i], acc[i]);
+  }
+  if (pact) vstore_nt<VT, VPL>(static_cast<VT*>(A.out) + roff, acc);
+}
+
+template <int VALT>
+__global__ void __launch_bounds__(256) stencil_pack_kernel(const void* val, const int32_t* emap, const uint16_t* lcol,
+                                                           int64_t n, void* ent) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int32_t e = emap[i];
+    const uint32_t lc = lcol[i];
+    if constexpr (VALT == VAL_BF16) {
+      const uint32_t vb = e >= 0 ? static_cast<const uint16_t*>(val)[e] : 0u;
+      static_cast<uint32_t*>(ent)[i] = (vb << 16) | lc;
+    } else if constexpr (VALT == VAL_F32) {
+      const float v = e >= 0 ? static_cast<const float*>(val)[e] : 0.f;
+      static_cast<uint2*>(ent)[i] = make_uint2(lc, __float_as_uint(v));
+    } else {
+      const double v = e >= 0 ? static_cast<const double*>(val)[e] : 0.0;
+      static_cast<uint4*>(ent)[i] = make_uint4(lc, 0u, (uint32_t)__double2loint(v), (uint32_t)__double2hiint(v));
+    }
+  }
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(256) stencil_unpack_kernel(const VT* hacc, const int32_t* emap, int64_t n, VT* acc) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int32_t e = emap[i];
+    if (e >= 0) acc[e] += hacc[i];
+  }
+}
+
+// 256 blocks, block b: rows [b * chunk, (b + 1) * chunk), threads strided, then a fixed-order tree.
+template <typename VT>
+__global__ void __launch_bounds__(256) stencil_diag_sum_kernel(const VT* hacc, const int64_t* dslot, int64_t d,
+                                                               double* part) {
+  __shared__ double red[256];
+  const int64_t chunk = (d + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(d, r0 + chunk);
+  double sum = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) sum += (double)hacc[dslot[i]];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] += red[0];
 }
 
 // perm[t] = index of the entry (col[t], row(t)); flag set when some transposed entry is missing.
@@ -639,6 +892,27 @@ __global__ void __launch_bounds__(256) transpose_index_kernel(const int64_t* row
     perm[t] = found;
     if (found < 0) atomicOr(missing, 1);
   }
+}
+
+// hist[b] += number of stored entries (i, j) with bit_length(|i - j|) = b (b = 0: the diagonal):
+// how far from its row each entry reaches, which decides the adjoint's form.  Block-local counts
+// in LDS, one atomic per bin per block (integer atomics: the result does not depend on order).
+__global__ void __launch_bounds__(256) distance_hist_kernel(const int64_t* row_ptr, const int32_t* col, int64_t d,
+                                                            int64_t nnz, unsigned long long* hist) {
+  __shared__ unsigned int h[kDistBins];
+  for (int i = threadIdx.x; i < kDistBins; i += 256) h[i] = 0u;
+  __syncthreads();
+  // rows of this block's share of entries: walk rows in a grid-stride loop
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
+    for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t) {
+      const int64_t dist = col[t] > r ? col[t] - r : r - col[t];
+      const int b = dist == 0 ? 0 : 64 - __clzll((unsigned long long)dist);
+      atomicAdd(&h[b], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kDistBins; i += 256)
+    if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
 // out[t] = scale * (a[t] + a[perm[t]]) / 2: the derivative along symmetric perturbations from
@@ -1124,11 +1398,97 @@ hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64,
   return hipErrorInvalidValue;
 }
 
+template <typename VT, int VALT>
+static hipError_t adj_stencil_by_vpl(const AdjDesc& A, const StencilDesc& S, int M, const Shape& sh, bool y2,
+                                     hipStream_t s) {
+  const int tr = stencil_tile_rows(sh.lpr_log2);
+  const int64_t ntiles = (A.d + tr - 1) / tr;
+  const int64_t per = (ntiles + 7) / 8;
+  const dim3 grid((unsigned)(per * 8));
+  const size_t lds = 2 * (size_t)(tr + S.nofs) * (size_t)((1 << sh.lpr_log2) * sh.vpl) * sizeof(VT);
+  if (tr > kStencilRows || lds > (size_t)kStencilLdsBytes) return hipErrorInvalidValue;
+  // K = 5 and 7 (2-D and 3-D grids) run exactly; other K up to kStencilK are planned as 8
+#define LD_STEN(V_, Y_, K_)                                                                                      \
+  if (sh.vpl == V_ && y2 == Y_ && S.K == K_) {                                                                   \
+    hipLaunchKernelGGL((adjoint_stencil_kernel<VT, VALT, V_, Y_, K_>), grid, dim3(kBlock), lds, s, A, S, M,      \
+                       sh.lpr_log2, ntiles);                                                                    \
+    return hipGetLastError();                                                                                   \
+  }
+#define LD_STEN_K(V_, Y_) LD_STEN(V_, Y_, 5) LD_STEN(V_, Y_, 7) LD_STEN(V_, Y_, 8)
+  LD_STEN_K(1, true)
+  LD_STEN_K(1, false)
+  LD_STEN_K(2, true)
+  LD_STEN_K(2, false)
+  LD_STEN_K(4, true)
+  LD_STEN_K(4, false)
+#undef LD_STEN_K
+#undef LD_STEN
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_stencil(const AdjDesc& A, const StencilDesc& S, int M, const Shape& sh, int vec_f64,
+                                  int valt, bool y2, hipStream_t s) {
+  if (A.d <= 0) return hipSuccess;
+  if (vec_f64) {
+    if (valt == VAL_F64) return adj_stencil_by_vpl<double, VAL_F64>(A, S, M, sh, y2, s);
+    if (valt == VAL_F32) return adj_stencil_by_vpl<double, VAL_F32>(A, S, M, sh, y2, s);
+    if (valt == VAL_BF16) return adj_stencil_by_vpl<double, VAL_BF16>(A, S, M, sh, y2, s);
+  } else {
+    if (valt == VAL_F64) return adj_stencil_by_vpl<float, VAL_F64>(A, S, M, sh, y2, s);
+    if (valt == VAL_F32) return adj_stencil_by_vpl<float, VAL_F32>(A, S, M, sh, y2, s);
+    if (valt == VAL_BF16) return adj_stencil_by_vpl<float, VAL_BF16>(A, S, M, sh, y2, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stencil_pack(const void* val, int valt, const int32_t* emap, const uint16_t* lcol, int64_t n,
+                               void* ent, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = grid_for(n, 256);
+  if (valt == VAL_F64)
+    hipLaunchKernelGGL(stencil_pack_kernel<VAL_F64>, dim3(g), dim3(256), 0, s, val, emap, lcol, n, ent);
+  else if (valt == VAL_F32)
+    hipLaunchKernelGGL(stencil_pack_kernel<VAL_F32>, dim3(g), dim3(256), 0, s, val, emap, lcol, n, ent);
+  else
+    hipLaunchKernelGGL(stencil_pack_kernel<VAL_BF16>, dim3(g), dim3(256), 0, s, val, emap, lcol, n, ent);
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_unpack(const void* hacc, int vec_f64, const int32_t* emap, int64_t n, void* acc,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = grid_for(n, 256);
+  if (vec_f64)
+    hipLaunchKernelGGL(stencil_unpack_kernel<double>, dim3(g), dim3(256), 0, s, (const double*)hacc, emap, n,
+                       (double*)acc);
+  else
+    hipLaunchKernelGGL(stencil_unpack_kernel<float>, dim3(g), dim3(256), 0, s, (const float*)hacc, emap, n,
+                       (float*)acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_diag_sum(const void* hacc, int vec_f64, const int64_t* dslot, int64_t d, double* part,
+                                   hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  if (vec_f64)
+    hipLaunchKernelGGL(stencil_diag_sum_kernel<double>, dim3(256), dim3(256), 0, s, (const double*)hacc, dslot, d, part);
+  else
+    hipLaunchKernelGGL(stencil_diag_sum_kernel<float>, dim3(256), dim3(256), 0, s, (const float*)hacc, dslot, d, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz, int64_t* perm,
                                   int* missing, hipStream_t s) {
   if (d <= 0 || nnz <= 0) return hipSuccess;
   hipLaunchKernelGGL(transpose_index_kernel, dim3(grid_for(nnz, 256, 1u << 20)), dim3(256), 0, s, row_ptr, col, d,
                      nnz, perm, missing);
+  return hipGetLastError();
+}
+
+hipError_t launch_distance_hist(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz,
+                                unsigned long long* hist, hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  hipLaunchKernelGGL(distance_hist_kernel, dim3(grid_for(d, 256, 8192u)), dim3(256), 0, s, row_ptr, col, d, nnz, hist);
   return hipGetLastError();
 }
 

@@ -31,8 +31,10 @@ def test_adjoint_bytes_model():
     alg = bench.adjoint_bytes(d, nnz, M, 4, 4, 4)
     assert abs(alg / 1e9 - 1.204) < 1e-3
     assert alg == (nnz * 8 + (d + 1) * 4 + 3 * d * M * 4) + d * M * 4 + 8 * nnz
-    moved = bench.adjoint_moved_bytes(d, nnz, M, 4, 4, 4)
+    moved = bench.adjoint_moved_bytes(d, nnz, M, 4, 4, 4, "explicit_single")
     assert moved - alg == 2 * d * M * 4 + (d + 1) * 4
+    # the shifted form moves no extra vector block, only the int64 row pointers' extra half
+    assert bench.adjoint_moved_bytes(d, nnz, M, 4, 4, 4, "shifted") - alg == (d + 1) * 4
 
 
 def test_traffic_needs_the_profiled_kernel_source(tmp_path, monkeypatch):

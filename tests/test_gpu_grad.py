@@ -24,19 +24,44 @@ def ld():
     return pkg
 
 
-@pytest.mark.parametrize("plain", [False, True])
+# Adjoint forms: the product-identity form with the explicit seed (single gather per entry) or the
+# shifted one (two gathers, two vector blocks less per step) on vector tiles staged in LDS or on
+# global gathers, and the plain recurrence.
+FORMS = ["explicit", "shifted", "shifted_global", "plain"]
+# what may run: the shifted form runs on staged tiles where the pattern is a stencil pattern for the
+# pass's tile, on global gathers elsewhere
+RAN = {"explicit": ("explicit_single",), "shifted": ("shifted", "shifted_staged"), "shifted_global": ("shifted",),
+       "plain": ("plain",)}
+
+
+def _use_form(monkeypatch, form: str) -> bool:
+    """Select the adjoint form; returns the `plain` argument."""
+    monkeypatch.delenv("LD_STENCIL", raising=False)
+    if form == "plain":
+        monkeypatch.delenv("LD_GRAD_FORM", raising=False)
+        return True
+    if form == "shifted_global":
+        monkeypatch.setenv("LD_STENCIL", "0")
+        form = "shifted"
+    monkeypatch.setenv("LD_GRAD_FORM", form)
+    return False
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 30])
 @pytest.mark.parametrize("stride", [0, 1, 2, 3, 5, 100])
-def test_grad_fp64_parity(ld, oracle_lib, n, stride, plain):
+def test_grad_fp64_parity(ld, oracle_lib, n, stride, form, monkeypatch):
     """Gradient along symmetric perturbations, per stored entry, against the oracle's reverse mode:
-    both the product-identity form and the plain recurrence, every checkpoint stride."""
+    both product-identity forms and the plain recurrence, every checkpoint stride."""
+    plain = _use_form(monkeypatch, form)
     B = synth.random_sparse_spd(2000, 4, 17, 1.0, "f64")
     a, b = oracle_lib.gershgorin(B)
     M, seed, shift, go = 16, 9, 0.25, 1.7
-    say(f"grad fp64 n={n} stride={stride} plain={plain}")
+    say(f"grad fp64 n={n} stride={stride} form={form}")
     r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a + shift, b + shift, n, M, seed, go, ckpt_stride=stride,
                                   plain=plain)
     o = oracle_lib.logdet_grad(B, a + shift, b + shift, n, M, seed=seed, shift=shift)
+    assert r["adjoint_form"] in RAN[form]
     assert entrywise(g.cpu().numpy(), go * o["grad"]) <= 1e-10
     assert rel(r["grad_shift"], go * o["grad_shift"]) <= 1e-10
     assert rel(r["logdet"], o["gamma"]) <= 1e-10
@@ -58,20 +83,125 @@ def test_grad_rows_without_diagonal(ld, oracle_lib):
     assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-10
 
 
-@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("M", [1, 3, 32, 64])
-def test_grad_fp32_gmrf_parity(ld, oracle_lib, M, plain):
+def test_grad_fp32_gmrf_parity(ld, oracle_lib, M, form, monkeypatch):
     """3-D GMRF precision Q = tau (kappa^2 I + L) in FP32 with the kappa^2 shift kept in FP64."""
+    plain = _use_form(monkeypatch, form)
     N, tau, kappa, n = 10, 1.0, 0.3, 60
     L = synth.grid_laplacian_3d(N, "f32")
     shift = tau * kappa ** 2
     a, b = tau * kappa ** 2, tau * (kappa ** 2 + 12.0)
-    say(f"grad fp32 gmrf M={M} plain={plain}")
+    say(f"grad fp32 gmrf M={M} form={form}")
     r, g = ld.ld_logdet_cheb_grad(dev(L, shift=shift), a, b, n, M, 3, plain=plain)
+    assert r["adjoint_form"] in RAN[form]
     o = oracle_lib.logdet_grad(L, a, b, n, M, seed=3, shift=shift)
     assert entrywise(g.cpu().numpy(), o["grad"]) <= 1e-4
     assert rel(r["grad_shift"], o["grad_shift"]) <= 1e-4
     assert rel(r["logdet"], o["gamma"]) <= 1e-4
+
+
+def _grid2d_rect(n1: int, n2: int, storage: str, drop_diag_every: int = 0):
+    """Dirichlet 5-point Laplacian on an n1 x n2 grid (node (i, j) = i n2 + j); optionally every
+    drop_diag_every-th row without its stored diagonal (the shift carries it)."""
+    d = n1 * n2
+    idx = np.arange(d)
+    i, j = idx // n2, idx % n2
+    rows, cols, vals = [], [], []
+    for o, m in ((-n2, i > 0), (-1, j > 0), (0, np.ones(d, bool)), (1, j < n2 - 1), (n2, i < n1 - 1)):
+        if o == 0 and drop_diag_every:
+            m = idx % drop_diag_every != 0
+        rows.append(idx[m]), cols.append(idx[m] + o), vals.append(np.full(int(m.sum()), 4.0 if o == 0 else -1.0))
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((c, r))
+    rp = np.zeros(d + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=d), out=rp[1:])
+    return synth.CSR(d, rp, c[order].astype(np.int32), synth.round_to(v[order], storage), storage)
+
+
+def _hex2d(n1: int, n2: int, storage: str):
+    """7-point (triangular-lattice) Laplacian on an n1 x n2 grid: neighbours (i, j +- 1), (i +- 1, j)
+    and (i - 1, j + 1), (i + 1, j - 1); diagonal 6, -1 per in-grid neighbour."""
+    d = n1 * n2
+    idx = np.arange(d)
+    i, j = idx // n2, idx % n2
+    rows, cols, vals = [], [], []
+    for di, dj in ((-1, 0), (-1, 1), (0, -1), (0, 0), (0, 1), (1, -1), (1, 0)):
+        m = (i + di >= 0) & (i + di < n1) & (j + dj >= 0) & (j + dj < n2)
+        rows.append(idx[m]), cols.append(idx[m] + di * n2 + dj)
+        vals.append(np.full(int(m.sum()), 6.0 if (di, dj) == (0, 0) else -1.0))
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((c, r))
+    rp = np.zeros(d + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=d), out=rp[1:])
+    return synth.CSR(d, rp, c[order].astype(np.int32), synth.round_to(v[order], storage), storage)
+
+
+def _banded(d: int, half: int, storage: str, seed: int):
+    """Symmetric band matrix (|i - j| <= half) with random off-diagonals and a dominant diagonal."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((d, d))
+    for k in range(1, half + 1):
+        v = rng.uniform(-1.0, 1.0, d - k)
+        A[np.arange(d - k), np.arange(k, d)] = v
+        A[np.arange(k, d), np.arange(d - k)] = v
+    A[np.arange(d), np.arange(d)] = np.abs(A).sum(axis=1) + 1.0
+    r, c = np.nonzero(A)
+    rp = np.zeros(d + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=d), out=rp[1:])
+    return synth.CSR(d, rp, c.astype(np.int32), synth.round_to(A[r, c], storage), storage)
+
+
+STENCIL_CASES = {
+    # name: (builder, shift, M, degree, staged by default)
+    "grid2d_ragged_f64": (lambda: _grid2d_rect(37, 41, "f64"), 0.3, 16, 24, True),
+    "grid2d_f32_M32": (lambda: _grid2d_rect(64, 64, "f32"), 0.05, 32, 40, True),
+    "grid3d_f32_M64": (lambda: synth.grid_laplacian_3d(12, "f32"), 0.2, 64, 30, False),  # halo of 4 tiles
+    "hex2d_f64_K7": (lambda: _hex2d(33, 29, "f64"), 0.1, 16, 22, True),
+    "band3_f64_M8": (lambda: _banded(1500, 3, "f64", 4), 0.0, 8, 20, True),
+    "grid2d_nodiag_f64": (lambda: _grid2d_rect(30, 33, "f64", drop_diag_every=3), 4.5, 16, 18, False),  # no diagonal
+    "grid2d_passes_f32_M200": (lambda: _grid2d_rect(40, 40, "f32"), 0.1, 200, 16, True),
+    "band5_k11_f64": (lambda: _banded(900, 5, "f64", 6), 0.0, 16, 14, False),  # 11 entries per row
+}
+
+
+@pytest.mark.parametrize("case", sorted(STENCIL_CASES))
+def test_grad_stencil_patterns(ld, oracle_lib, case, monkeypatch):
+    """Patterns whose tiles reach a fixed offset list (grids in natural order, bands): by default the
+    shifted adjoint runs on vector tiles staged in LDS.  Entry by entry against the oracle, with
+    ragged last tiles and several probe passes; rows without a stored diagonal and rows too long for
+    the staged layout fall back to the explicit form."""
+    monkeypatch.delenv("LD_GRAD_FORM", raising=False)
+    monkeypatch.delenv("LD_STENCIL", raising=False)
+    build, shift, M, n, staged = STENCIL_CASES[case]
+    B = build()
+    a, b = oracle_lib.gershgorin(B, shift)
+    tol = 1e-10 if B.storage == "f64" else 1e-4
+    say(f"grad stencil pattern {case} d={B.d} nnz={B.nnz} M={M} n={n}")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a, b, n, M, 7)
+    assert r["adjoint_form"] == ("shifted_staged" if staged else "explicit_single"), r["adjoint_form"]
+    o = oracle_lib.logdet_grad(B, a, b, n, M, seed=7, shift=shift)
+    assert entrywise(g.cpu().numpy(), o["grad"]) <= tol
+    assert rel(r["grad_shift"], o["grad_shift"]) <= tol
+    assert rel(r["logdet"], o["gamma"]) <= tol
+
+
+def test_grad_stencil_repeat_bit_identical(ld, oracle_lib):
+    """A second call on the same stencil pattern reuses the cached plan and its buffers and gives the
+    same gradient bit for bit; another pattern in between does not disturb it."""
+    import torch
+
+    B = _grid2d_rect(50, 70, "f32")
+    C = _banded(1200, 2, "f32", 9)
+    DB, DC = dev(B, shift=0.2), dev(C)
+    a, b = oracle_lib.gershgorin(B, 0.2)
+    ac, bc = oracle_lib.gershgorin(C)
+    say("grad stencil repeat")
+    r1, g1 = ld.ld_logdet_cheb_grad(DB, a, b, 22, 32, 3)
+    rc_, gc = ld.ld_logdet_cheb_grad(DC, ac, bc, 22, 32, 3)
+    r2, g2 = ld.ld_logdet_cheb_grad(DB, a, b, 22, 32, 3)
+    assert r1["adjoint_form"] == r2["adjoint_form"] == rc_["adjoint_form"] == "shifted_staged"
+    assert torch.equal(g1, g2) and r1["logdet"] == r2["logdet"] and r1["grad_shift"] == r2["grad_shift"]
 
 
 def _pattern_case(kind: str):
@@ -98,11 +228,13 @@ def _pattern_case(kind: str):
     return synth.CSR(B.d, B.row_ptr, B.col[order], B.val[order], "f64"), 0.0
 
 
+@pytest.mark.parametrize("form", ["explicit", "shifted", "shifted_global"])
 @pytest.mark.parametrize("kind", ["hub", "empty_rows", "unsorted"])
-def test_grad_pattern_layouts(ld, oracle_lib, kind):
+def test_grad_pattern_layouts(ld, oracle_lib, kind, form, monkeypatch):
+    _use_form(monkeypatch, form)
     C, shift = _pattern_case(kind)
     a, b = oracle_lib.gershgorin(C, shift)
-    say(f"grad pattern layout {kind} d={C.d} nnz={C.nnz}")
+    say(f"grad pattern layout {kind} d={C.d} nnz={C.nnz} form={form}")
     r, g = ld.ld_logdet_cheb_grad(dev(C, shift=shift), a, b, 15, 8, 3)
     o = oracle_lib.logdet_grad(C, a, b, 15, 8, seed=3, shift=shift)
     assert entrywise(g.cpu().numpy(), o["grad"]) <= 1e-10
@@ -163,10 +295,12 @@ def test_autograd_function_and_gmrf_chain_rule(ld, oracle_lib):
 
 
 def test_grad_two_gather_path_matches(ld, oracle_lib, monkeypatch):
-    """LD_GRAD_SYM=0 forces the general (two-gather) adjoint on a symmetric pattern."""
+    """LD_GRAD_SYM=0 forces the general (two-gather) adjoint with the explicit seed on a symmetric
+    pattern."""
     B = synth.random_sparse_spd(1500, 4, 23, 1.0, "f64")
     a, b = oracle_lib.gershgorin(B)
     monkeypatch.setenv("LD_GRAD_SYM", "0")
+    monkeypatch.setenv("LD_GRAD_FORM", "explicit")
     say("grad two-gather path fp64")
     r, g = ld.ld_logdet_cheb_grad(dev(B, shift=0.1), a + 0.1, b + 0.1, 20, 12, 4)
     o = oracle_lib.logdet_grad(B, a + 0.1, b + 0.1, 20, 12, seed=4, shift=0.1)
