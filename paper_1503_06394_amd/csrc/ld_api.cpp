@@ -2062,6 +2062,8 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
         D.mu_part2 = pair ? part + (int64_t)(2 * k + 1) * kstride : nullptr;
       }
       L.d0 = D;
+      if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu))
+        return launch_step_stencil(L, sd, valt, psrc, mu, s);
       return launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu, s);
     };
 

@@ -814,6 +814,146 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   if (pact) vstore_nt<VT, VPL>(static_cast<VT*>(A.out) + roff, acc);
 }
 
+// Recurrence step on stencil tiles: the step kernel's W_{k+1} = alpha B W_k + beta W_k + cp P with its
+// moment partials, where W_k's rows reach each entry from LDS.  A block covers one row tile of the
+// pass shape (so that its moment partials keep the step kernel's [tile][M] layout) as a sequence of
+// stencil tiles of one row pass each: stage the own and offset rows of W_k, barrier, one row per
+// lane group, barrier.  FP32 vectors, FP32 or BF16 values, a single probe tile.
+template <int VALT, int VPL, int PSRC, int MU, int KK>
+__global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, StencilDesc S) {
+  typedef float VT;
+  typedef typename Val<VALT>::T MV;
+  const int64_t tile = xcd_tile(L.ntiles);
+  if (tile >= L.ntiles) return;
+  const StepDesc& D = L.d0;
+  const int64_t row0 = tile * L.tile_rows;
+  const int64_t row_end = min(D.d, row0 + L.tile_rows);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lg = L.shape.lpr_log2;
+  const int LPR = 1 << lg;
+  const int RPW = 64 >> lg;
+  const int TR = kWaves * RPW;
+  const int sub = lane & (LPR - 1);
+  const int grp = lane >> lg;
+  const int M = L.M;
+  const int tp = LPR * VPL;
+  int p0 = sub * VPL;
+  const bool pact = p0 < M;
+  if (!pact) p0 = 0;
+  const VT ag = (VT)D.ag, bd = (VT)D.bd, cp = (VT)D.cp;
+  const VT* __restrict__ G = static_cast<const VT*>(D.G);
+  const VT* P = static_cast<const VT*>(D.P);
+  VT* out = static_cast<VT*>(D.out);
+
+  extern __shared__ __align__(16) unsigned char ld_step_smem[];
+  VT* Ws = reinterpret_cast<VT*>(ld_step_smem);
+  const int lr = wave * RPW + grp;
+
+  VT mu[VPL], mu2[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) mu[i] = mu2[i] = VT(0);
+
+  for (int64_t sr0 = row0; sr0 < row_end; sr0 += TR) {
+    const int nown = (int)min((int64_t)TR, row_end - sr0);
+    const bool has = lr < nown;
+    const int64_t row = sr0 + (has ? lr : 0);
+    const int64_t roff = row * (int64_t)M + p0;
+    VT wown[VPL], pv[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) wown[i] = pv[i] = VT(0);
+    if (has && pact) vload<VT, VPL>(G + roff, wown);
+    if constexpr (PSRC == SRC_BUF) {
+      if (has && pact) vload_nt<VT, VPL>(P + roff, pv);
+    } else if constexpr (PSRC == SRC_HASH) {
+      probe_signs<VT, VPL>(D.seed, row, p0, pv);
+    }
+    for (int j = lr; j < S.nofs; j += TR) {
+      int off = j + S.run_delta[0];
+#pragma unroll
+      for (int q = 1; q < kStencilRuns; ++q)
+        if (q < S.nruns && j >= S.run_base[q]) off = j + S.run_delta[q];
+      const int64_t r = sr0 + off;
+      VT w[VPL];
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) w[i] = VT(0);
+      if (r >= 0 && r < D.d && pact) vload<VT, VPL>(G + r * M + p0, w);
+      vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, w);
+    }
+    vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
+    const int64_t e0 = row * (int64_t)KK;  // slot (tile * TR + lr) * KK of the padded layout
+    int lc[KK];
+    VT va[KK];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+      MV v;
+      StencilEnt<VALT>::get(S.ent, e0 + k, lc[k], v);
+      va[k] = (VT)v;
+    }
+    __syncthreads();
+    VT acc[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) acc[i] = bd * wown[i];
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+      VT g[VPL];
+      vload<VT, VPL>(Ws + lc[k] * tp + sub * VPL, g);
+      const VT a = ag * va[k];
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) acc[i] = fma(a, g[i], acc[i]);
+    }
+    if constexpr (PSRC != SRC_NONE) {
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
+    }
+    if (has && pact) {
+      vstore_nt<VT, VPL>(out + roff, acc);
+      if constexpr (MU == MU_PAIR) {
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+          mu[i] = fma(acc[i], wown[i], mu[i]);
+          mu2[i] = fma(acc[i], acc[i], mu2[i]);
+        }
+      }
+    }
+    __syncthreads();  // the next stencil tile overwrites the staged rows
+  }
+
+  if constexpr (MU == MU_PAIR) {
+    // fixed-order reduction as in the step kernel: wave butterfly, then waves summed in order
+    double m1[VPL], m2[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+      m1[i] = (double)mu[i];
+      m2[i] = (double)mu2[i];
+    }
+    for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) {
+        m1[i] += __shfl_xor(m1[i], o, 64);
+        m2[i] += __shfl_xor(m2[i], o, 64);
+      }
+    double* red = reinterpret_cast<double*>(ld_step_smem);  // [2][kWaves][256] (the launch sizes it)
+    if (grp == 0)
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) {
+        red[wave * 256 + sub * VPL + i] = m1[i];
+        red[(kWaves + wave) * 256 + sub * VPL + i] = m2[i];
+      }
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+      double* dst = (q == 0 ? D.mu_part : D.mu_part2) + (tile - D.tile0) * (int64_t)M;
+      for (int j = threadIdx.x; j < tp; j += kBlock)
+        if (j < M) {
+          double sum = 0.0;
+#pragma unroll
+          for (int w = 0; w < kWaves; ++w) sum += red[(q * kWaves + w) * 256 + j];
+          dst[j] = sum;
+        }
+    }
+  }
+}
+
 template <int VALT>
 __global__ void __launch_bounds__(256) stencil_pack_kernel(const void* val, const int32_t* emap, const uint16_t* lcol,
                                                            int64_t n, void* ent) {
@@ -1438,6 +1578,49 @@ hipError_t launch_adjoint_stencil(const AdjDesc& A, const StencilDesc& S, int M,
     if (valt == VAL_F32) return adj_stencil_by_vpl<float, VAL_F32>(A, S, M, sh, y2, s);
     if (valt == VAL_BF16) return adj_stencil_by_vpl<float, VAL_BF16>(A, S, M, sh, y2, s);
   }
+  return hipErrorInvalidValue;
+}
+
+template <int VALT, int VPL>
+static hipError_t step_stencil_by_flags(const StepLaunch& L, const StencilDesc& S, int psrc, int mu, size_t lds,
+                                        dim3 grid, hipStream_t s) {
+#define LD_SS(P_, MU_, K_)                                                                                       \
+  if (psrc == P_ && mu == MU_ && S.K == K_) {                                                                   \
+    hipLaunchKernelGGL((step_stencil_kernel<VALT, VPL, P_, MU_, K_>), grid, dim3(kBlock), lds, s, L, S);       \
+    return hipGetLastError();                                                                                   \
+  }
+#define LD_SS_K(P_, MU_) LD_SS(P_, MU_, 5) LD_SS(P_, MU_, 7) LD_SS(P_, MU_, 8)
+  LD_SS_K(SRC_BUF, MU_PAIR)
+  LD_SS_K(SRC_HASH, MU_PAIR)
+  LD_SS_K(SRC_BUF, MU_NONE)
+  LD_SS_K(SRC_HASH, MU_NONE)
+#undef LD_SS_K
+#undef LD_SS
+  return hipErrorInvalidValue;
+}
+
+bool step_stencil_supported(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu) {
+  return !vec_f64 && valt != VAL_F64 && gsrc == SRC_BUF && dsrc == SRC_SAME && (psrc == SRC_BUF || psrc == SRC_HASH) &&
+         (mu == MU_PAIR || mu == MU_NONE) && L.descs == nullptr && L.shape.probe_tiles == 1 &&
+         (L.shape.vpl == 2 || L.shape.vpl == 4) && L.tile_rows % stencil_tile_rows(L.shape.lpr_log2) == 0 &&
+         stencil_tile_rows(L.shape.lpr_log2) <= kStencilRows;
+}
+
+hipError_t launch_step_stencil(const StepLaunch& L, const StencilDesc& S, int valt, int psrc, int mu, hipStream_t s) {
+  if (L.ntiles <= 0) return hipSuccess;
+  const int tr = stencil_tile_rows(L.shape.lpr_log2);
+  const size_t tp = (size_t)(1 << L.shape.lpr_log2) * L.shape.vpl;
+  const size_t lds = std::max((size_t)(tr + S.nofs) * tp * sizeof(float),
+                              mu == MU_PAIR ? (size_t)2 * kWaves * 256 * sizeof(double) : (size_t)0);
+  if (lds > (size_t)kStencilLdsBytes) return hipErrorInvalidValue;
+  const int64_t per = (L.ntiles + 7) / 8;
+  const dim3 grid((unsigned)(per * 8));
+  if (valt == VAL_BF16)
+    return L.shape.vpl == 4 ? step_stencil_by_flags<VAL_BF16, 4>(L, S, psrc, mu, lds, grid, s)
+                            : step_stencil_by_flags<VAL_BF16, 2>(L, S, psrc, mu, lds, grid, s);
+  if (valt == VAL_F32)
+    return L.shape.vpl == 4 ? step_stencil_by_flags<VAL_F32, 4>(L, S, psrc, mu, lds, grid, s)
+                            : step_stencil_by_flags<VAL_F32, 2>(L, S, psrc, mu, lds, grid, s);
   return hipErrorInvalidValue;
 }
 
