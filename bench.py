@@ -134,11 +134,17 @@ def adjoint_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_
 
 def adjoint_moved_bytes(d: int, nnz: int, M: int, val_bytes: int, vec_bytes: int, acc_bytes: int,
                         form: str | None) -> int:
-    """What the adjoint kernel moves besides, by the form that ran: the explicit seed of the
-    product-identity form reads w_{j-1} and w_{j+1} as well; the shifted form (and the plain
-    recurrence) move no extra vector block; int64 row pointers in every form."""
+    """What the adjoint kernel moves, by the form that ran: the explicit seed of the product-identity
+    form reads w_{j-1} and w_{j+1} as well (and int64 row pointers); the shifted form on staged
+    stencil tiles reads four vector blocks and, in place of the CSR matrix, one packed entry (slot and
+    value: 4 bytes for BF16 values, 8 for FP32) per stored entry, plus its accumulators (padding slots
+    of the layout, under 0.3 % of the entries on the grids, not counted)."""
+    alg = adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, acc_bytes)
+    if form == "shifted_staged":
+        ent = {2: 4, 4: 8, 8: 16}[val_bytes]
+        return alg - csr_bytes(d, nnz, val_bytes) + nnz * ent
     extra = 2 * d * M * vec_bytes if form in ("explicit_single", "explicit_two") else 0
-    return adjoint_bytes(d, nnz, M, val_bytes, vec_bytes, acc_bytes) + extra + (d + 1) * 4
+    return alg + extra + (d + 1) * 4
 
 
 def traffic_from_profiles(kernel_tag: str, workload_name: str):
@@ -384,6 +390,9 @@ def main() -> None:
             "moved_bytes_per_launch": moved, "moved_GBps": round(moved / (avg_ms / 1e3) / 1e9, 1)}
     if tag == "adjoint":
         roof["adjoint_form"] = r.get("adjoint_form")
+        roof["kernel"] = {"shifted_staged": "adjoint_stencil_kernel (shifted adjoint, LDS-staged stencil tiles)",
+                          "explicit_single": "adjoint_kernel (explicit seed, single gather)"}.get(
+                              r.get("adjoint_form"), "adjoint kernel")
     if traffic is not None:
         roof["traffic_GBps"] = round(traffic / (avg_ms / 1e3) / 1e9, 1)  # counted bytes at the live launch time
         roof["traffic_over_algorithmic"] = round(traffic / bytes_, 3)
@@ -400,8 +409,9 @@ def main() -> None:
     extra["paper_equivalent_matvec_nnz_per_s"] = work / (ms_per_step / 1e3)
     extra["products_per_step"] = products
     # sparse products the kernels actually executed (product identities: ceil(n/2) per forward; every
-    # adjoint launch runs the SDDMM and all but the last of a call also the SpMM), per second of step time
-    executed = nnz * M * (step_n + (2 * adj_n - args.steps if adj_n else 0))
+    # timed adjoint step runs the SpMM and the SDDMM, and each call closes with one more SDDMM),
+    # per second of step time
+    executed = nnz * M * (step_n + (2 * adj_n + args.steps if adj_n else 0))
     extra["executed_spmm_sddmm_nnz_ops_per_s"] = executed / args.steps / (ms_per_step / 1e3)
 
     cpu = None

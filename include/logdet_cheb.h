@@ -73,7 +73,8 @@ typedef struct {
     double poly_bound;      /* Lemma 7 bound on |log det - tr p_n| for delta = a / (a + b) */
     double grad_shift;      /* d Gamma / d diag_shift (gradient entry point only) */
     double kernel_ms;       /* with ld_opts.timing: summed duration of the recurrence-step kernels */
-    double adjoint_ms;      /* with ld_opts.timing: summed duration of the adjoint kernels (gradient) */
+    double adjoint_ms;      /* with ld_opts.timing: summed duration of the adjoint steps (gradient;
+                               product + SDDMM launches, not the closing SDDMM of y_1 w_0^T) */
     int32_t kernel_launches;/* with ld_opts.timing: number of recurrence-step kernels timed */
     int32_t adjoint_launches;
     int32_t n, M;

@@ -2189,7 +2189,7 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
       A.ce = shifted ? eps[1] : 0.0;  // y_1 = yh_1 - eps_1 w_0
       A.gw = 1.0;
       LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, false, true, false, sym, s));
-      LD_HIP(tm.mark(T_ADJ));
+      LD_HIP(tm.mark(T_OTHER));  // an SDDMM without the product: not timed with the adjoint steps
     }
   }
   const double scale = grad_output * (2.0 / (b - a)) / M;

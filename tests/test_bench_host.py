@@ -35,6 +35,9 @@ def test_adjoint_bytes_model():
     assert moved - alg == 2 * d * M * 4 + (d + 1) * 4
     # the shifted form moves no extra vector block, only the int64 row pointers' extra half
     assert bench.adjoint_moved_bytes(d, nnz, M, 4, 4, 4, "shifted") - alg == (d + 1) * 4
+    # staged stencil tiles: packed entries (8 bytes with FP32 values) in place of the CSR matrix
+    staged = bench.adjoint_moved_bytes(d, nnz, M, 4, 4, 4, "shifted_staged")
+    assert staged == alg - (nnz * 8 + (d + 1) * 4) + nnz * 8
 
 
 def test_traffic_needs_the_profiled_kernel_source(tmp_path, monkeypatch):
