@@ -61,12 +61,13 @@ def lib():
         L.ldo_logdet.argtypes = [P, D, D, D, I, I, P, P, P, P]
         L.ldo_logabsdet.argtypes = [P, D, D, I, I, P, P, P]
         L.ldo_logdet_grad.argtypes = [P, D, D, D, I, I, P, P, P, P]
+        L.ldo_logdet_dir.argtypes = [P, D, D, D, I, I, P, P, D, P]
         L.ldo_gershgorin.argtypes = [P, D, P, P]
         L.ldo_logdet_taylor.argtypes = [P, D, D, D, I, I, P, P, P]
         L.ldo_lemma_bound.argtypes = [D, I, I64]
         L.ldo_lemma_bound.restype = D
         for f in ("ldo_cheb_coeffs_alg1", "ldo_probe_sign", "ldo_logdet", "ldo_logabsdet",
-                  "ldo_logdet_grad", "ldo_gershgorin", "ldo_logdet_taylor"):
+                  "ldo_logdet_grad", "ldo_logdet_dir", "ldo_gershgorin", "ldo_logdet_taylor"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -196,6 +197,23 @@ def logdet_grad(B, a: float, b: float, n: int, m: int, seed: int = 0, V=None, id
     if rc:
         raise ValueError(f"ldo_logdet_grad failed ({rc})")
     return {"gamma": g.value, "grad": grad, "grad_shift": gs.value}
+
+
+def logdet_dir(B, a: float, b: float, n: int, m: int, e_val, e_shift: float = 0.0, seed: int = 0, V=None, ids=None,
+               shift: float = 0.0) -> float:
+    """Directional derivative of the ``logdet`` estimate along B -> B + h E (forward mode): E has the
+    values ``e_val`` on B's pattern and ``e_shift`` on the diagonal."""
+    k = _Keep(B)
+    pr, keep = _probes(seed, V, ids, B.d, m)
+    e = np.ascontiguousarray(e_val, dtype=np.float64)
+    if e.shape != (B.nnz,):
+        raise ValueError("e_val must hold one value per stored entry")
+    out = ctypes.c_double(0.0)
+    rc = lib().ldo_logdet_dir(ctypes.byref(k.s), float(shift), float(a), float(b), int(n), int(m),
+                              ctypes.byref(pr), _ptr(e), float(e_shift), ctypes.byref(out))
+    if rc:
+        raise ValueError(f"ldo_logdet_dir failed ({rc})")
+    return out.value
 
 
 def gershgorin(B, shift: float = 0.0) -> tuple:

@@ -486,6 +486,86 @@ done:
     return rc;
 }
 
+/* Directional derivative of the ldo_logdet estimate along B -> B + h E, where E has the values
+ * e_val on B's pattern and e_shift on the diagonal, at fixed a, b and probes: forward-mode
+ * differentiation of Algorithm 1's recurrence.  With X = (I - 2 (B + shift I)/(a + b))/(1 - 2 delta)
+ * its tangent is dX = -2 (E + e_shift I)/((a + b)(1 - 2 delta)), and
+ *     dw_0 = 0,  dw_1 = dX v,  dw_k = 2 (dX w_{k-1} + X dw_{k-1}) - dw_{k-2},
+ *     d s = sum_k c_k v^T dw_k,  d Gamma = (1/m) sum_probes d s.
+ * Three sparse products per degree and five vectors per probe, whatever the degree. */
+int ldo_logdet_dir(const ldo_csr *B, double shift, double a, double b, int n, int m,
+                   const ldo_probes *probes, const double *e_val, double e_shift, double *dgamma)
+{
+    if (check_csr(B) || !(a > 0.0) || !(b > a) || !isfinite(b) || n < 0 || m < 1 || !probes || !e_val ||
+        !dgamma)
+        return -1;
+    const int64_t d = B->d;
+    pd_ctx ctx = {B, shift, 1.0 / (a + b)};
+    const double delta = a / (a + b);
+    ldo_csr E = *B;
+    E.val = e_val;
+    const double dxs = -2.0 / ((a + b) * (1.0 - 2.0 * delta)); /* dX = dxs (E + e_shift I) */
+    double *c = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    double *v = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *w0 = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *w1 = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *t0 = (double *)malloc(sizeof(double) * (size_t)(d + 1)); /* tangents dw_{k-2}, dw_{k-1} */
+    double *t1 = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *xw = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *xt = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *ew = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    int rc = 0;
+    if (!c || !v || !w0 || !w1 || !t0 || !t1 || !xw || !xt || !ew || !tmp) {
+        rc = -2;
+        goto done;
+    }
+    ldo_cheb_coeffs_alg1(delta, n, c);
+    double D = 0.0;
+    for (int i = 0; i < m; ++i) {
+        get_probe(probes, i, d, v);
+        double ds = 0.0; /* c_0 v^T dw_0 = 0 */
+        if (n >= 1) {
+            memcpy(w0, v, sizeof(double) * (size_t)d); /* w_0 */
+            apply_X(d, pd_matvec, &ctx, delta, v, tmp, w1); /* w_1 = X v */
+            csr_mv(&E, v, ew);
+            for (int64_t r = 0; r < d; ++r) {
+                t0[r] = 0.0;                                    /* dw_0 */
+                t1[r] = dxs * (ew[r] + e_shift * v[r]);         /* dw_1 = dX v */
+            }
+            ds += c[1] * dot(d, v, t1);
+            for (int k = 2; k <= n; ++k) {
+                apply_X(d, pd_matvec, &ctx, delta, w1, tmp, xw); /* X w_{k-1} */
+                apply_X(d, pd_matvec, &ctx, delta, t1, tmp, xt); /* X dw_{k-1} */
+                csr_mv(&E, w1, ew);                              /* E w_{k-1} */
+                for (int64_t r = 0; r < d; ++r) {
+                    const double wk = 2.0 * xw[r] - w0[r];
+                    const double tk = 2.0 * (dxs * (ew[r] + e_shift * w1[r]) + xt[r]) - t0[r];
+                    w0[r] = w1[r];
+                    w1[r] = wk;
+                    t0[r] = t1[r];
+                    t1[r] = tk;
+                }
+                ds += c[k] * dot(d, v, t1);
+            }
+        }
+        D += ds / m;
+    }
+    *dgamma = D;
+done:
+    free(c);
+    free(v);
+    free(w0);
+    free(w1);
+    free(t0);
+    free(t1);
+    free(xw);
+    free(xt);
+    free(ew);
+    free(tmp);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Spectral interval and stated bounds                                        */
 /* ------------------------------------------------------------------------- */

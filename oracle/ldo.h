@@ -103,6 +103,13 @@ int ldo_logabsdet(const ldo_csr *C, double smin, double smax, int n, int m,
 int ldo_logdet_grad(const ldo_csr *B, double shift, double a, double b, int n, int m,
                     const ldo_probes *probes, double *grad, double *grad_shift, double *gamma);
 
+/* Directional derivative of the ldo_logdet estimate along B -> B + h E (E: values e_val on B's
+ * pattern, nnz of them, plus e_shift on the diagonal), at fixed a, b and probes, by forward-mode
+ * differentiation of Algorithm 1's recurrence (no stored vectors: usable at any size).
+ * Equals sum_t grad[t] e_val[t] + grad_shift e_shift of ldo_logdet_grad. */
+int ldo_logdet_dir(const ldo_csr *B, double shift, double a, double b, int n, int m,
+                   const ldo_probes *probes, const double *e_val, double e_shift, double *dgamma);
+
 /* Gershgorin interval of B + shift I: a = min_i (B_ii + shift - sum_{j!=i} |B_ij|),
  * b = max_i (B_ii + shift + sum_{j!=i} |B_ij|). */
 int ldo_gershgorin(const ldo_csr *B, double shift, double *a, double *b);

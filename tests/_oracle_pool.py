@@ -17,6 +17,7 @@ def _matrix(spec):
 
         kind, args = spec[0], spec[1:]
         _cache[spec] = {"random_sparse_spd": synth.random_sparse_spd,
+                        "grid_laplacian_2d": synth.grid_laplacian_2d,
                         "grid_laplacian_3d": synth.grid_laplacian_3d}[kind](*args)
     return _cache[spec]
 
@@ -50,3 +51,37 @@ def mean_gradient(spec, a, b, n, M, seed, idx, workers, shift=0.0):
     with ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
         parts = list(ex.map(grad_samples, jobs))
     return sum(p[0] for p in parts) / M, sum(p[1] for p in parts) / M
+
+
+def direction(B, dseed: int):
+    """A symmetric direction through every stored entry: e = (rho_i + rho_j)/2 on off-diagonal entries
+    (i, j), -rho_i / 2 on diagonal ones, rho ~ U[0.5, 1.5] per row from ``dseed``, and e_shift = 0.25."""
+    rho = np.random.default_rng(dseed).uniform(0.5, 1.5, B.d)
+    rows = np.repeat(np.arange(B.d), np.diff(B.row_ptr))
+    e = 0.5 * (rho[rows] + rho[B.col])
+    diag = rows == B.col
+    e[diag] = -0.5 * rho[rows[diag]]
+    return e, 0.25
+
+
+def dir_samples(job):
+    """job = (matrix spec, shift, a, b, n, seed, probe ids, direction seed): the sum over the given probes
+    of the oracle's directional derivative of the single-probe estimate along ``direction``."""
+    import oracle
+
+    spec, shift, a, b, n, seed, probes, dseed = job
+    B = _matrix(spec)
+    e, es = direction(B, dseed)
+    return sum(oracle.logdet_dir(B, a, b, n, 1, e, es, seed=seed, ids=np.array([j]), shift=shift) for j in probes)
+
+
+def mean_dir(spec, a, b, n, M, seed, dseed, workers, shift=0.0):
+    """Mean over probes 0..M-1 of the oracle's directional derivative along direction(B, dseed)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    chunks = [list(range(M))[w::workers] for w in range(workers)]
+    jobs = [(spec, shift, a, b, n, seed, c, dseed) for c in chunks if c]
+    with ProcessPoolExecutor(max_workers=len(jobs), mp_context=mp.get_context("spawn")) as ex:
+        parts = list(ex.map(dir_samples, jobs))
+    return sum(parts) / M

@@ -220,3 +220,32 @@ def test_gmrf_128_gradient_bench_configuration(ld, oracle_lib):
     og, ogs = mean_gradient(spec, a, b, n, M, seed, idx, workers, shift=shift)
     assert entrywise(gg, og) <= TOL32
     assert rel(r["grad_shift"], ogs) <= TOL32
+
+
+@pytest.mark.timeout(900)
+def test_grid_4096_gradient_bench_configuration(ld, oracle_lib):
+    """The bench's default fwd+grad call (4096^2 grid + 0.01 I, BF16 values with the shift in FP64,
+    M = 32, n = 100, FP32 gradient: the staged stencil kernels) against the oracle along one symmetric
+    direction through every stored entry and the shift: sum_t g_t e_t + grad_shift e_shift against the
+    oracle's forward-mode derivative of the same 32-probe estimate, computed in CPU worker processes
+    (the oracle's reverse mode would store 2n + 3 vectors of d doubles per probe).  Relative 1e-4."""
+    import os
+
+    import torch
+
+    from tests._oracle_pool import direction, mean_dir
+
+    spec = ("grid_laplacian_2d", 4096, "bf16")
+    B = synth.grid_laplacian_2d(4096, "bf16")
+    shift, a, b, n, M, seed, dseed = 0.01, 0.01, 8.01, 100, 32, 5, 17
+    say("full size grid4096 gradient: GPU")
+    r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a, b, n, M, seed, 1.0, grad_dtype=torch.float32)
+    assert r["adjoint_form"] == "shifted_staged", r["adjoint_form"]
+    e, es = direction(B, dseed)
+    gpu = float(np.dot(g.double().cpu().numpy(), e) + r["grad_shift"] * es)
+    del g
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    say(f"full size grid4096 gradient: oracle directional derivative, {M} probes over {workers} worker processes")
+    ora = mean_dir(spec, a, b, n, M, seed, dseed, workers, shift=shift)
+    print(f"[grid4096 grad] gpu {gpu:.9e} oracle {ora:.9e} rel {abs(gpu - ora) / abs(ora):.2e}", flush=True)
+    assert rel(gpu, ora) <= TOL32
