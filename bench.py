@@ -516,6 +516,7 @@ def bench_batch(args, W, copy_gbps) -> None:
     alg = sum(steps[i] * (mats[i].nnz * 8 + (mats[i].d + 1) * 8 + 3 * mats[i].d * M * vec_bytes)
               for i in range(len(mats)))
     achieved = alg / (gms / 1e3) / 1e9
+    traffic = traffic_from_profiles("step", args.workload)  # counted bytes of one whole graph replay
     cpu = None
     if not args.no_cpu_baseline:
         order = np.argsort([B.d for B in mats])
@@ -541,12 +542,14 @@ def bench_batch(args, W, copy_gbps) -> None:
                    "sum_nnz": sum(B.nnz for B in mats), "M": M, "step": "gershgorin bounds + batched forward graph",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "batched graph",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": "batched graph",
                      "graph_ms": round(gms, 4), "algorithmic_bytes_per_launch": alg},
         "cpu_baseline": cpu,
         "accuracy": {"oracle_parity_rel_median_member": parity, "parity_tolerance": 1e-4,
                      "std_err_rel_first": abs(res[0]["std_err"] / res[0]["logdet"])},
     }
+    if traffic is not None:
+        out["roofline"]["traffic_over_algorithmic"] = round(traffic / alg, 3)
     if copy_gbps is not None:
         out["copy_kernel_GBps"] = round(copy_gbps, 1)
         out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbps, 4)

@@ -1415,13 +1415,29 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
   }
   E.kmax = rmax;
   E.pair = pair;
-  std::vector<int64_t> tile_begin(count + 1, 0);
-  for (int i = 0; i < count; ++i) tile_begin[i + 1] = tile_begin[i] + (Bs[i].rows + sh.tile_rows - 1) / sh.tile_rows;
-  const int64_t ntiles = tile_begin[count];
+  // Tiles in order of decreasing step count (stable): the members still active at step k are then
+  // a prefix of the tile list, and node k dispatches only that prefix (active_tiles[k]) instead of
+  // every member's tiles with the finished ones returning at once.
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return steps_for(n[x], pair) > steps_for(n[y], pair); });
+  std::vector<int64_t> tile_begin(count), tile_range(2 * (size_t)count);
+  int64_t ntiles = 0;
+  for (int i : order) {
+    tile_begin[i] = ntiles;
+    ntiles += (Bs[i].rows + sh.tile_rows - 1) / sh.tile_rows;
+    tile_range[2 * (size_t)i] = tile_begin[i];
+    tile_range[2 * (size_t)i + 1] = ntiles;
+  }
+  std::vector<int64_t> active_tiles(std::max(kmax, 1), 0);
+  for (int k = 0; k < kmax; ++k)
+    for (int i : order)
+      if (steps_for(n[i], pair) > k) active_tiles[k] = tile_range[2 * (size_t)i + 1];
   std::vector<int32_t> tile_mat(ntiles);
   std::vector<int64_t> tile_row0(ntiles);
   for (int i = 0; i < count; ++i)
-    for (int64_t t = tile_begin[i]; t < tile_begin[i + 1]; ++t) {
+    for (int64_t t = tile_range[2 * (size_t)i]; t < tile_range[2 * (size_t)i + 1]; ++t) {
       tile_mat[t] = i;
       tile_row0[t] = (t - tile_begin[i]) * sh.tile_rows;
     }
@@ -1446,8 +1462,8 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
   const size_t off_tm = c.off - (size_t)ntiles * 4;
   c.take((size_t)ntiles * 8);
   const size_t off_tr = c.off - (size_t)ntiles * 8;
-  c.take((size_t)(count + 1) * 8);
-  const size_t off_tb = c.off - (size_t)(count + 1) * 8;
+  c.take((size_t)count * 16);
+  const size_t off_tb = c.off - (size_t)count * 16;
   c.take((size_t)count * 4);
   const size_t off_n = c.off - (size_t)count * 4;
   hipError_t e = hipMalloc(&E.mem, align_up(c.off));
@@ -1498,7 +1514,7 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
   LD_HIP(hipMemcpy(descs, hd.data(), hd.size() * sizeof(StepDesc), hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(d_tm, tile_mat.data(), tile_mat.size() * 4, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(d_tr, tile_row0.data(), tile_row0.size() * 8, hipMemcpyHostToDevice));
-  LD_HIP(hipMemcpy(d_tb, tile_begin.data(), tile_begin.size() * 8, hipMemcpyHostToDevice));
+  LD_HIP(hipMemcpy(d_tb, tile_range.data(), tile_range.size() * 8, hipMemcpyHostToDevice));
   LD_HIP(hipMemcpy(d_n, rows_i.data(), (size_t)count * 4, hipMemcpyHostToDevice));
 
   if (rmax == 0) return LD_OK;  // every member has degree 0: nothing to run, no graph
@@ -1512,10 +1528,11 @@ int build_batch(int count, const ld_csr* Bs, const double* a, const double* b, c
     L.nmat = count;
     L.tile_mat = d_tm;
     L.tile_row0 = d_tr;
-    L.ntiles = ntiles;
+    L.ntiles = active_tiles[k];
     L.tile_rows = sh.tile_rows;
     L.M = M;
     L.shape = sh;
+    if (L.ntiles == 0) continue;
     const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
     const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
     err = launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, pair ? MU_PAIR : MU_PROBE, cs);

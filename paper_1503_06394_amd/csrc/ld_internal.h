@@ -187,9 +187,9 @@ hipError_t launch_reduce_moments(const double* part, int64_t ntiles, int M, int 
                                  double* mu, int ldmu, double* tmp, hipStream_t s);
 size_t reduce_scratch_bytes(int nk, int M);
 
-// Batched reduction: for matrix i, tiles [tile_begin[i], tile_begin[i+1]) of degree k (k <= n[i])
+// Batched reduction: for matrix i, tiles [tile_range[2i], tile_range[2i+1]) of degree k (k <= n[i])
 // into mu[i][j][k].  part[(k-1) * kstride + tile * M + j].
-hipError_t launch_reduce_batched(const double* part, const int64_t* tile_begin, const int* n, int count, int M,
+hipError_t launch_reduce_batched(const double* part, const int64_t* tile_range, const int* n, int count, int M,
                                  int kmax, int64_t kstride, double* mu, hipStream_t s);
 
 hipError_t launch_sum_doubles(const double* x, int64_t n, double* out, hipStream_t s);

@@ -1114,7 +1114,7 @@ __global__ void __launch_bounds__(256) reduce_moments_stage2(const double* tmp, 
   }
 }
 
-__global__ void __launch_bounds__(1024) reduce_batched_kernel(const double* part, const int64_t* tile_begin,
+__global__ void __launch_bounds__(1024) reduce_batched_kernel(const double* part, const int64_t* tile_range,
                                                               const int* nvec, int M, int64_t kstride, double* mu,
                                                               int kmax) {
   const int i = blockIdx.x;        // matrix
@@ -1125,7 +1125,7 @@ __global__ void __launch_bounds__(1024) reduce_batched_kernel(const double* part
   double s = 0.0;
   if (j < M) {
     const double* p = part + (int64_t)(k - 1) * kstride + j;
-    for (int64_t t = tile_begin[i] + q; t < tile_begin[i + 1]; t += 16) s += p[t * M];
+    for (int64_t t = tile_range[2 * i] + q; t < tile_range[2 * i + 1]; t += 16) s += p[t * M];
   }
   __shared__ double sh[16][64];
   sh[q][threadIdx.x & 63] = s;
@@ -1707,11 +1707,11 @@ hipError_t launch_reduce_moments(const double* part, int64_t ntiles, int M, int 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_batched(const double* part, const int64_t* tile_begin, const int* n, int count, int M,
+hipError_t launch_reduce_batched(const double* part, const int64_t* tile_range, const int* n, int count, int M,
                                  int kmax, int64_t kstride, double* mu, hipStream_t s) {
   if (count <= 0 || kmax < 1) return hipSuccess;
   dim3 grid((unsigned)count, (unsigned)kmax, (unsigned)((M + 63) / 64));
-  hipLaunchKernelGGL(reduce_batched_kernel, grid, dim3(1024), 0, s, part, tile_begin, n, M, kstride, mu, kmax);
+  hipLaunchKernelGGL(reduce_batched_kernel, grid, dim3(1024), 0, s, part, tile_range, n, M, kstride, mu, kmax);
   return hipGetLastError();
 }
 
