@@ -80,6 +80,11 @@ typedef struct {
     int32_t n, M;
     uint32_t flags;         /* bit 0: LD_WBOUNDS seen */
     int32_t adjoint_form;   /* gradient entry point: how its adjoint ran (LD_ADJ_*); 0 elsewhere */
+    int32_t plane_tiles;    /* gradient entry point: 0 when the general kernels walked the row tiles
+                               in row order; > 0 when they walked them plane by plane (a lattice in
+                               natural order whose planes span more vector rows than an XCD's L2:
+                               each XCD takes one column of every plane, planes in turn), this many
+                               tiles per plane.  The results do not depend on the order. */
 } ld_result;
 
 /* ld_result.adjoint_form.  The product-identity forward (symmetric pattern) has two adjoints:

@@ -53,7 +53,7 @@ class _Result(ctypes.Structure):
         ("grad_shift", ctypes.c_double), ("kernel_ms", ctypes.c_double), ("adjoint_ms", ctypes.c_double),
         ("kernel_launches", ctypes.c_int32), ("adjoint_launches", ctypes.c_int32),
         ("n", ctypes.c_int32), ("M", ctypes.c_int32), ("flags", ctypes.c_uint32),
-        ("adjoint_form", ctypes.c_int32),
+        ("adjoint_form", ctypes.c_int32), ("plane_tiles", ctypes.c_int32),
     ]
 
 
@@ -182,7 +182,8 @@ def _result(r: _Result, rc: int) -> dict:
     return {"logdet": r.logdet, "std_err": r.std_err, "poly_bound": r.poly_bound, "grad_shift": r.grad_shift,
             "kernel_ms": r.kernel_ms, "kernel_launches": r.kernel_launches, "adjoint_ms": r.adjoint_ms,
             "adjoint_launches": r.adjoint_launches, "n": r.n, "M": r.M,
-            "flags": r.flags, "adjoint_form": _ADJ_FORMS.get(r.adjoint_form), "status": rc}
+            "flags": r.flags, "adjoint_form": _ADJ_FORMS.get(r.adjoint_form), "plane_tiles": r.plane_tiles,
+            "status": rc}
 
 
 def ld_logdet_cheb(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, *, vec_f64=None, tile=0,

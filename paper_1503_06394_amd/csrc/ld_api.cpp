@@ -904,6 +904,19 @@ Shape grad_shape(const ld_csr* B, int M, int vec_f64, const ld_opts* opt) {
   return with_tile(base_shape(vec_f64, M), B->rows, B->nnz, opt ? opt->tile : 0);
 }
 
+// Tile of the plane-major order (the default tile height unless the caller set one): a power-of-two
+// number of row passes no taller than the default tile, which divides the planes of lattices whose
+// sides are multiples of a power of two.
+Shape plane_shape(const Shape& def, const ld_opts* opt) {
+  Shape sh = def;
+  if (opt && opt->tile > 0) return sh;
+  const int rpi = rows_per_iter(sh);
+  int r = rpi;
+  while (2 * r <= sh.tile_rows) r *= 2;
+  sh.tile_rows = r;
+  return sh;
+}
+
 // Probes per gradient pass.  Wider blocks would hold one row per wave, where the adjoint's
 // cross-lane reductions cost more than a second pass over the matrix (FP32: 256 probes in one
 // pass take 13 % longer than two passes of 128).  A chunk size that is a multiple of 64 keeps
@@ -932,6 +945,12 @@ uint64_t pass_seed(uint64_t seed, int probe0) {
 
 int64_t tiles_of(const ld_csr* B, const Shape& sh) {
   return B->rows > 0 ? (B->rows + sh.tile_rows - 1) / sh.tile_rows : 0;
+}
+
+// Tiles a gradient pass of M probes may run: of the default tile or of the plane-major order's.
+int64_t grad_pass_tiles(const ld_csr* B, int M, int vec_f64, const ld_opts* opt) {
+  const Shape sh = grad_shape(B, M, vec_f64, opt);
+  return std::max(tiles_of(B, sh), tiles_of(B, plane_shape(sh, opt)));
 }
 
 // Pattern analysis of the gradient, cached per (device, row_ptr, col_idx, rows, nnz):
@@ -967,6 +986,8 @@ struct PatternInfo {
   std::map<std::pair<int, int>, std::shared_ptr<StencilPlan>> stencil;  // (tr, offset capacity) -> plan, or null:
                                                                         // not a stencil pattern for that tile
   uint64_t dist_hist[kDistBins] = {};  // entries per bit length of |i - j| (launch_distance_hist)
+  int64_t plane_rows = 0;  // lattice reach: the pattern's largest |i - j| when (nearly) every entry sits
+                           // near the diagonal or near that distance (launch_plane_fit), else 0
   int64_t* perm = nullptr;
   int64_t* rp_t = nullptr;
   int32_t* col_t = nullptr;
@@ -1022,23 +1043,34 @@ struct DevTmp {
 
 int analyze_pattern(const ld_csr* B, hipStream_t s, PatternInfo& P) {
   const int64_t d = B->rows, nnz = B->nnz;
-  DevTmp scratch;  // [0]: missing flag (int), [8]: hash (uint64), [64]: distance histogram
+  DevTmp scratch;  // [0]: missing flag (int), [8]: hash (uint64), [64]: distance histogram, [448]: plane fit
   LD_HIP(hipMalloc(&scratch.p, 512));
   int* missing = static_cast<int*>(scratch.p);
   uint64_t* hash = reinterpret_cast<uint64_t*>(static_cast<char*>(scratch.p) + 8);
   unsigned long long* hist = reinterpret_cast<unsigned long long*>(static_cast<char*>(scratch.p) + 64);
-  static_assert(64 + kDistBins * 8 <= 512, "pattern analysis scratch");
+  unsigned long long* fit = reinterpret_cast<unsigned long long*>(static_cast<char*>(scratch.p) + 448);
+  static_assert(64 + kDistBins * 8 <= 448, "pattern analysis scratch");
   int rc = dev_alloc(&P.perm, (size_t)nnz, "the transposed-entry index");
   if (rc) return rc;
   LD_HIP(launch_fill_zero(scratch.p, 512, s));
   LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, nnz, P.perm, missing, s));
   LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, nnz, hash, s));
   LD_HIP(launch_distance_hist(B->row_ptr, B->col_idx, d, nnz, hist, s));
+  LD_HIP(launch_plane_fit(B->row_ptr, B->col_idx, d, 0, fit, s));
   int miss = 0;
+  unsigned long long fit_h[2] = {0, 0};
   LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
   LD_HIP(hipMemcpyAsync(&P.hash, hash, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   LD_HIP(hipMemcpyAsync(P.dist_hist, hist, sizeof(P.dist_hist), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipMemcpyAsync(fit_h, fit, sizeof(fit_h), hipMemcpyDeviceToHost, s));
   LD_HIP(hipStreamSynchronize(s));
+  const int64_t reach = (int64_t)fit_h[0];
+  if (reach >= 16) {  // how many entries sit away from both the diagonal and the reach
+    LD_HIP(launch_plane_fit(B->row_ptr, B->col_idx, d, reach, fit, s));
+    LD_HIP(hipMemcpyAsync(fit_h, fit, sizeof(fit_h), hipMemcpyDeviceToHost, s));
+    LD_HIP(hipStreamSynchronize(s));
+    if (fit_h[1] * 100 <= (uint64_t)nnz) P.plane_rows = reach;
+  }
   P.sym = miss == 0;
   if (P.sym) return LD_OK;
   (void)hipFree(P.perm);
@@ -1238,6 +1270,29 @@ bool local_pattern(const PatternInfo& P, int64_t nnz, size_t row_bytes) {
   return far * 100 <= (uint64_t)std::max<int64_t>(nnz, 0);
 }
 
+// Plane-major tile order.  On a lattice in its natural order (3-D: neighbours at +-1, +-N, +-N^2)
+// row order re-reads a gathered vector row about 2 N^2 rows after its first use; once that span
+// of each vector outgrows an XCD's L2 the far neighbours are fetched twice.  Visiting the tiles
+// plane by plane within a column of each plane per XCD keeps three planes of a column in L2.
+// Taken for passes whose vector rows over one plane reach kPlaneMinBytes, when the tile height
+// divides the plane into a multiple of 8 tiles and the tiles fill whole planes (LD_PLANE=0 keeps
+// row order; LD_PLANE=1 drops the size condition, for tests).
+constexpr double kPlaneMinBytes = 1u << 20;
+
+int plane_tiles(const PatternInfo* P, const Shape& sh, int64_t d, size_t row_bytes) {
+  const char* e = std::getenv("LD_PLANE");
+  if (e && e[0] == '0') return 0;
+  const bool any_size = e && e[0] == '1';
+  if (!P || P->plane_rows <= 0 || sh.tile_rows <= 0 || d <= 0) return 0;
+  const int64_t reach = P->plane_rows;
+  if (!any_size && (double)reach * (double)row_bytes < kPlaneMinBytes) return 0;
+  if (reach % sh.tile_rows) return 0;
+  const int64_t per = reach / sh.tile_rows;
+  const int64_t nt = (d + sh.tile_rows - 1) / sh.tile_rows;
+  if (per % 8 || nt % per || per > INT32_MAX) return 0;
+  return (int)per;
+}
+
 // The stencil plans whose per-call buffers a gradient call uses, locked in the order its passes
 // need them (every call takes its full-size passes' plan before its last pass's), and released
 // only once the call's stream has drained.
@@ -1297,10 +1352,7 @@ int get_stencil(PatternInfo& P, const ld_csr* B, hipStream_t s, const Shape& sh,
 int64_t grad_diag_tiles(const ld_csr* B, int M, int vec_f64, const ld_opts* opt) {
   const GradChunks ch = grad_chunks(M, vec_f64);
   int64_t nt = 0;
-  for (int mp : {ch.size, ch.last}) {
-    const Shape sh = grad_shape(B, mp, vec_f64, opt);
-    nt = std::max(nt, tiles_of(B, sh));
-  }
+  for (int mp : {ch.size, ch.last}) nt = std::max(nt, grad_pass_tiles(B, mp, vec_f64, opt));
   return std::max<int64_t>(nt, 256);  // the staged steps' diagonal sum writes 256 partials
 }
 
@@ -1308,8 +1360,8 @@ size_t grad_workspace_for(const ld_csr* B, int n, int M, int vec_f64, const ld_o
   const size_t vb = vec_f64 ? 8 : 4;
   const GradPlan g = plan_grad(n, pair, stride);
   const GradChunks ch = grad_chunks(M, vec_f64);
-  const int64_t nt_full = tiles_of(B, grad_shape(B, ch.size, vec_f64, opt));
-  const int64_t nt_last = tiles_of(B, grad_shape(B, ch.last, vec_f64, opt));
+  const int64_t nt_full = grad_pass_tiles(B, ch.size, vec_f64, opt);
+  const int64_t nt_last = grad_pass_tiles(B, ch.last, vec_f64, opt);
   const int64_t ntiles = grad_diag_tiles(B, M, vec_f64, opt);
   const int64_t part_cols = std::max(nt_full * ch.size, nt_last * ch.last);  // per partial row
   const int rows = std::max(partial_rows(n, g.pair), 1);
@@ -1924,8 +1976,8 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
   // the per-probe moments collect over the passes
   const GradChunks ch = grad_chunks(M, vec_f64);
   const int64_t nt_max = grad_diag_tiles(B, M, vec_f64, opt);
-  const int64_t part_cols = std::max(tiles_of(B, grad_shape(B, ch.size, vec_f64, opt)) * ch.size,
-                                     tiles_of(B, grad_shape(B, ch.last, vec_f64, opt)) * ch.last);
+  const int64_t part_cols = std::max(grad_pass_tiles(B, ch.size, vec_f64, opt) * ch.size,
+                                     grad_pass_tiles(B, ch.last, vec_f64, opt) * ch.last);
   const GradStrides strides = choose_strides(B, n, M, vec_f64, opt);
   const size_t need = grad_workspace_strides(B, n, M, vec_f64, opt, strides);
   std::shared_ptr<PatternInfo> pat;
@@ -2025,12 +2077,19 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
   StencilHold sp_hold;
   sp_hold.s = s;
   int staged_passes = 0;  // passes whose adjoint ran on staged stencil tiles
+  int plane0 = 0;         // the first pass's plane-major order (tiles per plane)
 
   for (int pass = 0; pass < ch.count; ++pass) {
     const int probe0 = pass * ch.size;  // a multiple of 64 whenever there is more than one pass
     const uint64_t pseed = pass_seed(seed, probe0);
     const int Mp = pass + 1 < ch.count ? ch.size : ch.last;
-    const Shape sh = grad_shape(B, Mp, vec_f64, opt);
+    Shape sh = grad_shape(B, Mp, vec_f64, opt);
+    {
+      Shape ps = plane_shape(sh, opt);
+      ps.plane = plane_tiles(pat.get(), ps, d, (size_t)Mp * vb);
+      if (ps.plane) sh = ps;
+    }
+    if (pass == 0) plane0 = sh.plane;
     const int64_t ntiles = tiles_of(B, sh);
     const int64_t kstride = ntiles * Mp;
     std::shared_ptr<StencilPlan> sp;  // staged tiles of this pass's shifted adjoint
@@ -2245,6 +2304,7 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
                    : shifted  ? (staged_passes == ch.count ? LD_ADJ_SHIFTED_STAGED : LD_ADJ_SHIFTED)
                    : sym      ? LD_ADJ_EXPLICIT_SINGLE
                               : LD_ADJ_EXPLICIT_TWO;
+  r.plane_tiles = plane0;
   tm.report(&r);
   *out = r;
   return r.flags ? LD_WBOUNDS : LD_OK;

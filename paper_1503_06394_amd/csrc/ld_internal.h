@@ -46,6 +46,8 @@ struct Shape {
   int lpr_log2;     // log2 lanes per row (LPR * vpl >= min(M, 64 * vpl))
   int tile_rows;    // rows per workgroup tile (multiple of 4 * (64 / LPR))
   int probe_tiles;  // gridDim.y: ceil(M / (LPR * vpl))
+  int plane = 0;    // tiles per plane of the plane-major tile order (general step and adjoint kernels;
+                    // a multiple of 8 dividing the tile count), 0: tiles in row order
 };
 
 // Launch configuration for a whole step over a tile list.
@@ -174,6 +176,11 @@ hipError_t launch_transpose_index(const int64_t* row_ptr, const int32_t* col, in
 constexpr int kDistBins = 33;
 hipError_t launch_distance_hist(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t nnz,
                                 unsigned long long* hist, hipStream_t s);
+
+// out[0] = max(out[0], largest |i - j| of a stored entry); with band > 0 also out[1] += the entries
+// farther than band / 16 from both the diagonal and distance `band` (out zeroed by the caller).
+hipError_t launch_plane_fit(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t band,
+                            unsigned long long* out, hipStream_t s);
 
 // out[t] = scale * (a[t] + a[perm[t]]) / 2
 hipError_t launch_sym_scale(const void* a, int a_f64, const int64_t* perm, int64_t n, double scale, void* out,

@@ -146,6 +146,17 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Plane-major order (plane > 0 tiles per plane; the launcher checks that plane is a multiple of 8
+// and divides ntiles): the tiles form ntiles / plane planes of `plane` consecutive tiles, XCD x
+// owns the x-th eighth of every plane and walks its share plane after plane.  On a lattice whose
+// plane is the pattern's reach, the rows a tile gathers one plane up or down were read a plane
+// earlier by the same XCD and are still in its L2.
+__device__ __forceinline__ int64_t block_tile(int64_t ntiles, int64_t plane) {
+  if (plane == 0) return xcd_tile(ntiles);
+  const int64_t b = blockIdx.x, k = b >> 3, bu = plane >> 3;
+  return (k / bu) * plane + (b & 7) * bu + k % bu;
+}
+
 constexpr int kBlock = 256;  // 4 waves of 64
 constexpr int kWaves = kBlock / 64;
 constexpr int kUnroll = LD_UNROLL;  // nonzeros whose gathers are in flight together per row group
@@ -192,7 +203,7 @@ __device__ __forceinline__ bool stage_tile(TileCsr<VALT>& T, const int64_t* rp, 
 template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, int MU>
 __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
   typedef typename Val<VALT>::T MV;
-  const int64_t tile = xcd_tile(L.ntiles);
+  const int64_t tile = block_tile(L.ntiles, L.shape.plane);
   if (tile >= L.ntiles) return;
   const int mat = L.tile_mat ? L.tile_mat[tile] : 0;
   const StepDesc& D = L.descs ? L.descs[mat] : L.d0;
@@ -419,9 +430,9 @@ template <typename VT, int VALT, int VPL, bool SPMM, bool WHASH, bool Y2, bool S
 // vectors would spill at that budget: those keep the compiler's choice.
 __global__ void __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu((sizeof(VT) == 4 && SYM && VALT != VAL_F64) ? 5 : 1)))
-adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles) {
+adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles, int64_t plane) {
   typedef typename Val<VALT>::T MV;
-  const int64_t tile = xcd_tile(ntiles);
+  const int64_t tile = block_tile(ntiles, plane);
   if (tile >= ntiles) return;
   const int64_t row0 = tile * tile_rows;
   const int64_t row_end = min(A.d, row0 + tile_rows);
@@ -1055,6 +1066,34 @@ __global__ void __launch_bounds__(256) distance_hist_kernel(const int64_t* row_p
     if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
+// out[0] = max(out[0], max |i - j| over stored entries); with band > 0 also out[1] += the entries with
+// min(|i - j|, | |i - j| - band |) > band / 16: those that sit neither near the diagonal nor one
+// plane of `band` rows away.
+__global__ void __launch_bounds__(256) plane_fit_kernel(const int64_t* row_ptr, const int32_t* col, int64_t d,
+                                                        int64_t band, unsigned long long* out) {
+  __shared__ unsigned long long blk[2];
+  if (threadIdx.x < 2) blk[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long mx = 0, off = 0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < d; r += (int64_t)gridDim.x * 256) {
+    for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t) {
+      const int64_t dist = col[t] > r ? col[t] - r : r - col[t];
+      mx = max(mx, (unsigned long long)dist);
+      if (band > 0) {
+        const int64_t to_plane = dist > band ? dist - band : band - dist;
+        off += (unsigned long long)(min(dist, to_plane) * 16 > band);
+      }
+    }
+  }
+  if (mx) atomicMax(&blk[0], mx);
+  if (off) atomicAdd(&blk[1], off);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (blk[0]) atomicMax(&out[0], blk[0]);
+    if (blk[1]) atomicAdd(&out[1], blk[1]);
+  }
+}
+
 // out[t] = scale * (a[t] + a[perm[t]]) / 2: the derivative along symmetric perturbations from
 // per-entry accumulators (either orientation, since the mean is symmetric in the pair).
 template <typename TA, typename TO>
@@ -1424,8 +1463,16 @@ static unsigned grid_for(int64_t work, int per_block, unsigned cap = 65536u) {
   return (unsigned)g;
 }
 
+// A plane-major order needs whole planes of a multiple of 8 tiles (then every block maps to
+// one tile of [0, ntiles) and every tile to one block); single-matrix launches only.
+static bool plane_fits(int64_t plane, int64_t ntiles) {
+  return plane == 0 || (plane > 0 && plane % 8 == 0 && ntiles % plane == 0);
+}
+
 template <typename VT, int VALT, int VPL, int GSRC, int DSRC, int PSRC, int MU>
 static hipError_t go_step(const StepLaunch& L, hipStream_t s) {
+  if (!plane_fits(L.shape.plane, L.ntiles) || (L.shape.plane && (L.descs || L.tile_row0)))
+    return hipErrorInvalidValue;
   const int64_t per = (L.ntiles + 7) / 8;
   dim3 grid((unsigned)(per * 8), (unsigned)L.shape.probe_tiles);
   hipLaunchKernelGGL((step_kernel<VT, VALT, VPL, GSRC, DSRC, PSRC, MU>), grid, dim3(kBlock), 0, s, L);
@@ -1492,12 +1539,13 @@ template <typename VT, int VALT, int VPL>
 static hipError_t adj_by_flags(const AdjDesc& A, int M, const Shape& sh, bool spmm, bool wh, bool y2, bool sym,
                                hipStream_t s) {
   const int64_t ntiles = (A.d + sh.tile_rows - 1) / sh.tile_rows;
+  if (!plane_fits(sh.plane, ntiles)) return hipErrorInvalidValue;
   const int64_t per = (ntiles + 7) / 8;
   dim3 grid((unsigned)(per * 8));
 #define LD_ADJ(S_, W_, Y_, X_)                                                                                    \
   if (spmm == S_ && wh == W_ && y2 == Y_ && sym == X_) {                                                         \
     hipLaunchKernelGGL((adjoint_kernel<VT, VALT, VPL, S_, W_, Y_, X_>), grid, dim3(kBlock), 0, s, A, M,          \
-                       sh.lpr_log2, (int64_t)sh.tile_rows, ntiles);                                             \
+                       sh.lpr_log2, (int64_t)sh.tile_rows, ntiles, (int64_t)sh.plane);                          \
     return hipGetLastError();                                                                                   \
   }
   LD_ADJ(true, false, true, false)
@@ -1672,6 +1720,13 @@ hipError_t launch_distance_hist(const int64_t* row_ptr, const int32_t* col, int6
                                 unsigned long long* hist, hipStream_t s) {
   if (d <= 0) return hipSuccess;
   hipLaunchKernelGGL(distance_hist_kernel, dim3(grid_for(d, 256, 8192u)), dim3(256), 0, s, row_ptr, col, d, nnz, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_fit(const int64_t* row_ptr, const int32_t* col, int64_t d, int64_t band,
+                            unsigned long long* out, hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  hipLaunchKernelGGL(plane_fit_kernel, dim3(grid_for(d, 256, 8192u)), dim3(256), 0, s, row_ptr, col, d, band, out);
   return hipGetLastError();
 }
 

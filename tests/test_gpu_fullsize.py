@@ -201,7 +201,8 @@ def test_random_1m_gradient_bench_configuration(ld, oracle_lib):
 def test_gmrf_128_gradient_bench_configuration(ld, oracle_lib):
     """The benchmark's gmrf128 fwd+grad call (128^3 GMRF, FP32, M = 32, n = 60, shift 0.09) against the
     oracle's gradient averaged over the same 32 probes in CPU worker processes: 20000 sampled
-    entries (normwise, 1e-4) and d Gamma / d shift (1e-4)."""
+    entries (entry by entry, 1e-4) and d Gamma / d shift (1e-4).  The lattice's planes (16384 rows of
+    128-byte vector rows) run the general kernels in plane-major tile order."""
     import os
 
     import torch
@@ -213,6 +214,7 @@ def test_gmrf_128_gradient_bench_configuration(ld, oracle_lib):
     shift, a, b, n, M, seed = 0.09, 0.09, 12.09, 60, 32, 3
     say("full size gmrf128 gradient: GPU")
     r, g = ld.ld_logdet_cheb_grad(dev(B, shift=shift), a, b, n, M, seed, 1.0, grad_dtype=torch.float32)
+    assert r["plane_tiles"] == 128, r["plane_tiles"]  # 16384-row planes of 128-row tiles
     idx = np.sort(np.random.default_rng(10).choice(B.nnz, 20_000, replace=False))
     gg = g.double().cpu().numpy()[idx]
     workers = max(1, min(16, (os.cpu_count() or 1)))

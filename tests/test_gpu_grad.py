@@ -204,6 +204,74 @@ def test_grad_stencil_repeat_bit_identical(ld, oracle_lib):
     assert torch.equal(g1, g2) and r1["logdet"] == r2["logdet"] and r1["grad_shift"] == r2["grad_shift"]
 
 
+# 3-D lattices in natural order (neighbours at +-1, +-N, +-N^2): (N, storage, M, degree, tiles per plane)
+PLANE_CASES = {
+    "N16_f64_M16": (16, "f64", 16, 20, 8),
+    "N16_f32_M32": (16, "f32", 32, 24, 8),
+    "N32_f32_M32": (32, "f32", 32, 16, 32),
+}
+
+
+@pytest.mark.parametrize("case", sorted(PLANE_CASES))
+def test_grad_plane_order(ld, oracle_lib, case, monkeypatch):
+    """Plane-major tile order on 3-D lattices, forced at sizes where row order would be kept
+    (LD_PLANE=1): entry by entry against the oracle, and bit for bit equal to the row-order call
+    (LD_PLANE=0), since only the order in which the tiles run changes."""
+    import torch
+
+    monkeypatch.delenv("LD_GRAD_FORM", raising=False)
+    monkeypatch.delenv("LD_STENCIL", raising=False)
+    N, storage, M, n, per = PLANE_CASES[case]
+    B = synth.grid_laplacian_3d(N, storage)
+    shift = 0.15
+    a, b = oracle_lib.gershgorin(B, shift)
+    D = dev(B, shift=shift)
+    say(f"grad plane order {case} d={B.d} nnz={B.nnz}")
+    monkeypatch.setenv("LD_PLANE", "1")
+    r1, g1 = ld.ld_logdet_cheb_grad(D, a, b, n, M, 5)
+    assert r1["plane_tiles"] == per, r1["plane_tiles"]
+    monkeypatch.setenv("LD_PLANE", "0")
+    r0, g0 = ld.ld_logdet_cheb_grad(D, a, b, n, M, 5)
+    assert r0["plane_tiles"] == 0
+    assert torch.equal(g0, g1) and r0["logdet"] == r1["logdet"] and r0["grad_shift"] == r1["grad_shift"]
+    monkeypatch.delenv("LD_PLANE")
+    r2, _ = ld.ld_logdet_cheb_grad(D, a, b, n, M, 5)
+    assert r2["plane_tiles"] == 0  # planes of N^2 rows too short to leave row order by default
+    tol = 1e-10 if storage == "f64" else 1e-4
+    o = oracle_lib.logdet_grad(B, a, b, n, M, seed=5, shift=shift)
+    assert entrywise(g1.cpu().numpy(), o["grad"]) <= tol
+    assert rel(r1["grad_shift"], o["grad_shift"]) <= tol
+    assert rel(r1["logdet"], o["gamma"]) <= tol
+
+
+def test_grad_plane_order_default_on_large_planes(ld, monkeypatch):
+    """A 96^3 lattice with 32 FP32 probes (planes of 9216 rows, 1.1 MiB of vector rows) takes the
+    plane-major order by default, 72 tiles of 128 rows per plane (the default row-order tile is 224
+    rows), and gives the result of row order on the same 128-row tiles bit for bit.  A 12^3 lattice,
+    whose +-N neighbours are too far from the diagonal relative to a plane, is not taken for one."""
+    import torch
+
+    monkeypatch.delenv("LD_GRAD_FORM", raising=False)
+    monkeypatch.delenv("LD_STENCIL", raising=False)
+    monkeypatch.delenv("LD_PLANE", raising=False)
+    B = synth.grid_laplacian_3d(96, "f32")
+    D = dev(B, shift=0.1)
+    a, b = ld.ld_gershgorin(D)
+    say(f"grad plane order default d={B.d}")
+    r1, g1 = ld.ld_logdet_cheb_grad(D, a, b, 20, 32, 8)
+    assert r1["plane_tiles"] == 72, r1["plane_tiles"]
+    monkeypatch.setenv("LD_PLANE", "0")
+    r0, g0 = ld.ld_logdet_cheb_grad(D, a, b, 20, 32, 8, tile=128)
+    assert r0["plane_tiles"] == 0
+    assert torch.equal(g0, g1) and r0["logdet"] == r1["logdet"] and r0["grad_shift"] == r1["grad_shift"]
+    monkeypatch.setenv("LD_PLANE", "1")
+    C = synth.grid_laplacian_3d(12, "f32")
+    DC = dev(C, shift=0.1)
+    ac, bc = ld.ld_gershgorin(DC)
+    rc_, _ = ld.ld_logdet_cheb_grad(DC, ac, bc, 10, 32, 8)
+    assert rc_["plane_tiles"] == 0
+
+
 def _pattern_case(kind: str):
     """Symmetric matrices whose patterns stress the transpose lookup of the symmetric adjoint:
     a hub row joined to every vertex, rows left empty (carried by the diagonal shift alone), and
