@@ -54,6 +54,7 @@ class _Result(ctypes.Structure):
         ("kernel_launches", ctypes.c_int32), ("adjoint_launches", ctypes.c_int32),
         ("n", ctypes.c_int32), ("M", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("adjoint_form", ctypes.c_int32), ("plane_tiles", ctypes.c_int32),
+        ("staged_steps", ctypes.c_int32),
     ]
 
 
@@ -183,7 +184,7 @@ def _result(r: _Result, rc: int) -> dict:
             "kernel_ms": r.kernel_ms, "kernel_launches": r.kernel_launches, "adjoint_ms": r.adjoint_ms,
             "adjoint_launches": r.adjoint_launches, "n": r.n, "M": r.M,
             "flags": r.flags, "adjoint_form": _ADJ_FORMS.get(r.adjoint_form), "plane_tiles": r.plane_tiles,
-            "status": rc}
+            "staged_steps": r.staged_steps, "status": rc}
 
 
 def ld_logdet_cheb(B: DeviceCSR, a: float, b: float, n: int, M: int, seed: int, *, vec_f64=None, tile=0,

@@ -592,171 +592,10 @@ size_t fwd_workspace(const ld_csr* B, int n, int M, int vec_f64, bool ns, const 
   c.take((size_t)rows * tiles * M * 8);  // per-tile partials
   c.take((size_t)M * rows * 8);          // reduced partials
   c.take(reduce_scratch_bytes(rows, M));  // reduction stage 1
+  c.take(256);                            // pattern hash (staged steps)
   return align_up(c.off);
 }
 
-// Shared body of ld_logdet_cheb and ld_logabsdet_cheb.
-// fixed_plan: no autotuning and no timing events (the planner's default shape), for callers that
-// must not allocate; the workspace is then always opt->workspace.
-int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double b, int n, int M_out, uint64_t seed,
-                const ld_opts* opt, hipStream_t s, ld_result* out, bool fixed_plan = false) {
-  const int valt = valt_of(B->dtype);
-  const int vec_f64 = vec_f64_of(opt, valt);
-  const int64_t d = B->rows;
-  const int M = padded_probes(M_out, vec_f64, opt);  // probes run; the estimate uses the first M_out
-  const bool pair = use_pairs(opt);
-  const int nsteps = steps_for(n, pair);
-  const int nrows = partial_rows(n, pair);
-  const size_t need = fwd_workspace(B, n, M_out, vec_f64, ns, opt);
-  Workspace ws;
-  int rc = get_workspace(opt, need, s, ws);
-  if (rc) return rc;
-
-  FwdPlan p = plan_fwd(B, vec_f64, M, opt);
-  Carve cv;
-  cv.base = static_cast<char*>(ws.ptr);
-  const size_t vecb = (size_t)d * M * p.vb;
-  void* bufA = cv.take(vecb);
-  void* bufB = cv.take(vecb);
-  void* bufT = nullptr;
-  ld_csr Ct{};
-  if (ns) {
-    bufT = cv.take(vecb);
-    int64_t* rpt = static_cast<int64_t*>(cv.take((size_t)(d + 1) * 8));
-    int32_t* colt = static_cast<int32_t*>(cv.take((size_t)B->nnz * 4));
-    void* valt_ = cv.take((size_t)B->nnz * val_bytes(valt));
-    int64_t* cursor = static_cast<int64_t*>(cv.take((size_t)d * 8));
-    void* scan = cv.take(transpose_scratch_bytes(d));
-    if (Ct_in) {
-      Ct = *Ct_in;
-    } else {
-      LD_HIP(launch_transpose(B->row_ptr, B->col_idx, B->values, valt, d, B->nnz, rpt, colt, valt_, cursor, scan,
-                              transpose_scratch_bytes(d), s));
-      Ct = *B;
-      Ct.row_ptr = rpt;
-      Ct.col_idx = colt;
-      Ct.values = valt_;
-    }
-  }
-  const bool tune = !fixed_plan && (!opt || opt->tile == 0) && autotune_enabled() && d >= 65536;
-  double* part_base =
-      static_cast<double*>(cv.take((size_t)std::max(nrows, 1) * max_tiles(B, vec_f64, M, opt) * M * 8));
-  double* red_out = static_cast<double*>(cv.take((size_t)M * std::max(nrows, 1) * 8));
-  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(nrows, M)));
-  const int mu_mode = pair ? MU_PAIR : MU_PROBE;
-
-  if (tune && !ns) {
-    TuneKey key{vec_f64, valt, M, (opt ? opt->probe_tile : 0) * 4 + mu_mode, d, B->nnz};
-    Shape sh{};
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      auto it = g_tune.find(key);
-      if (it != g_tune.end()) sh = it->second;
-    }
-    if (!sh.tile_rows) {
-      const std::vector<Shape> shapes = (opt && opt->probe_tile > 0) ? std::vector<Shape>{p.sh}
-                                                                      : shape_candidates(vec_f64, M);
-      sh = autotune(B, shapes, vec_f64, valt, M, mu_mode, bufA, bufB, part_base, s);
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune[key] = sh;
-    }
-    if (sh.tile_rows > 0) {
-      p.sh = sh;
-      p.ntiles = (d + sh.tile_rows - 1) / sh.tile_rows;
-    }
-  }
-
-  const std::vector<double> c = cheb_coeffs(a, b, n);
-  const double alpha = 4.0 / (b - a);
-  const double beta = -2.0 * (a + b) / (b - a);
-  const double shift = ns ? 0.0 : B->diag_shift;
-  const double beff = beta + alpha * shift;
-  const int64_t kstride = p.ntiles * M;
-
-  StepTimer tm;
-  tm.on = !fixed_plan && opt && opt->timing;
-  tm.s = s;
-
-  StepLaunch L{};
-  L.nmat = 1;
-  L.ntiles = p.ntiles;
-  L.tile_rows = p.sh.tile_rows;
-  L.M = M;
-  L.shape = p.sh;
-
-  auto base_desc = [&](const ld_csr* X) {
-    StepDesc D{};
-    D.row_ptr = X->row_ptr;
-    D.col = X->col_idx;
-    D.val = X->values;
-    D.seed = seed;
-    D.d = d;
-    D.active = 1;
-    return D;
-  };
-  // step k writes partial row k (plain) or rows 2k, 2k+1 (pairs)
-  auto set_parts = [&](StepDesc& D, int k) {
-    D.mu_part = part_base + (int64_t)(pair ? 2 * k : k) * kstride;
-    D.mu_part2 = pair ? part_base + (int64_t)(2 * k + 1) * kstride : nullptr;
-  };
-
-  // W_k lives in: k = 0 -> probe hash, odd k -> A, even k >= 2 -> B.
-  auto wbuf = [&](int k) -> void* { return k == 0 ? nullptr : ((k & 1) ? bufA : bufB); };
-  LD_HIP(tm.mark(T_OTHER));
-  for (int k = 0; k < nsteps && d > 0; ++k) {
-    const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
-    const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
-    const double h = k == 0 ? 0.5 : 1.0;  // W_1 = At V carries half of 2 At
-    if (!ns) {
-      StepDesc D = base_desc(B);
-      D.G = wbuf(k);
-      D.P = k >= 2 ? wbuf(k - 1) : nullptr;
-      D.out = wbuf(k + 1);
-      D.ag = h * alpha;
-      D.bd = h * beff;
-      D.cp = k == 0 ? 0.0 : -1.0;
-      set_parts(D, k);
-      L.d0 = D;
-      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu_mode, s));
-      LD_HIP(tm.mark(T_STEP));
-    } else {
-      // T = C W_k
-      StepDesc D1 = base_desc(B);
-      D1.G = wbuf(k);
-      D1.out = bufT;
-      D1.ag = 1.0;
-      L.d0 = D1;
-      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_NONE, SRC_NONE, MU_NONE, s));
-      LD_HIP(tm.mark(T_STEP));
-      // W_{k+1} = alpha C^T T + beta W_k - W_{k-1}   (halved at k = 0)
-      StepDesc D2 = base_desc(&Ct);
-      D2.G = bufT;
-      D2.D = wbuf(k);
-      D2.P = k >= 2 ? wbuf(k - 1) : nullptr;
-      D2.out = wbuf(k + 1);
-      D2.ag = h * alpha;
-      D2.bd = h * beta;
-      D2.cp = k == 0 ? 0.0 : -1.0;
-      set_parts(D2, k);
-      L.d0 = D2;
-      LD_HIP(launch_step(L, vec_f64, valt, SRC_BUF, k == 0 ? SRC_HASH : SRC_BUF, psrc, mu_mode, s));
-      LD_HIP(tm.mark(T_STEP));
-    }
-  }
-  std::vector<double> red((size_t)M * std::max(nrows, 1), 0.0);
-  if (nrows >= 1 && d > 0) {
-    LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 0, nrows - 1, kstride, red_out, nrows, red_tmp, s));
-    LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * nrows * 8, hipMemcpyDeviceToHost, s));
-  }
-  LD_HIP(hipStreamSynchronize(s));
-  std::vector<double> mu((size_t)M_out * (n + 1), 0.0);
-  assemble_moments(red, nrows, pair, n, M_out, d, mu);  // rows of red are per probe: the first M_out
-  combine(mu, c, n, M_out, d, ns ? 0.5 : 1.0, out, opt);
-  out->poly_bound = lemma_bound(a, b, n, d) * (ns ? 0.5 : 1.0);
-  out->grad_shift = 0.0;
-  tm.report(out);
-  return out->flags ? LD_WBOUNDS : LD_OK;
-}
 
 // ------------------------------------------------------------------------------------
 // Taylor-series comparator: W_k = A W_{k-1}, A = I - (B + shift I)/(a + b), moments v^T A^k v
@@ -953,15 +792,18 @@ int64_t grad_pass_tiles(const ld_csr* B, int M, int vec_f64, const ld_opts* opt)
   return std::max(tiles_of(B, sh), tiles_of(B, plane_shape(sh, opt)));
 }
 
-// Pattern analysis of the gradient, cached per (device, row_ptr, col_idx, rows, nnz):
+// Pattern analysis, cached per (device, row_ptr, col_idx, rows, nnz).  Every user gets:
+//  hash:  the pattern hash at analysis time.  Every call that relies on the analysis hashes the
+//         pattern again on the device and compares once its results are back (no extra
+//         synchronisation); a pattern rewritten in place at the same addresses is then analysed
+//         afresh and the call repeated;
+//  dist_hist, plane_rows: how far entries sit from the diagonal (stencil plans, plane-major order).
+// The gradient adds (full):
 //  sym:   every stored (i, j) has its transposed entry (j, i) stored as well;
 //  perm:  (sym) the index of the transposed entry of every entry;
 //  rp_t, col_t, src_t: (not sym) the pattern of B^T and, for each of its entries, the entry of B it
-//         comes from;
-//  hash:  the pattern hash at analysis time.  Every gradient call hashes the pattern again on the
-//         device and compares once its results are back (no extra synchronisation); a pattern
-//         rewritten in place at the same addresses is then analysed afresh and the call repeated.
-// Only the first call on a pattern synchronises to learn its symmetry.
+//         comes from.
+// Only the first call on a pattern synchronises for it.
 // Stencil plan of a pattern for staged tiles of `tr` rows (see StencilDesc), with the per-call
 // buffers of the padded layout (values, accumulators); `mu` serialises the calls that use them.
 struct StencilPlan {
@@ -981,6 +823,8 @@ struct StencilPlan {
 };
 
 struct PatternInfo {
+  std::mutex full_mu;
+  bool full = false;  // the gradient's part below (sym, perm or the pattern of B^T) is filled in
   bool sym = false;
   std::mutex stencil_mu;
   std::map<std::pair<int, int>, std::shared_ptr<StencilPlan>> stencil;  // (tr, offset capacity) -> plan, or null:
@@ -1041,25 +885,21 @@ struct DevTmp {
   }
 };
 
-int analyze_pattern(const ld_csr* B, hipStream_t s, PatternInfo& P) {
+// The part of the analysis every user of the cache needs: the pattern hash, the row-distance
+// histogram and the lattice reach.
+int analyze_light(const ld_csr* B, hipStream_t s, PatternInfo& P) {
   const int64_t d = B->rows, nnz = B->nnz;
-  DevTmp scratch;  // [0]: missing flag (int), [8]: hash (uint64), [64]: distance histogram, [448]: plane fit
+  DevTmp scratch;  // [8]: hash (uint64), [64]: distance histogram, [448]: plane fit
   LD_HIP(hipMalloc(&scratch.p, 512));
-  int* missing = static_cast<int*>(scratch.p);
   uint64_t* hash = reinterpret_cast<uint64_t*>(static_cast<char*>(scratch.p) + 8);
   unsigned long long* hist = reinterpret_cast<unsigned long long*>(static_cast<char*>(scratch.p) + 64);
   unsigned long long* fit = reinterpret_cast<unsigned long long*>(static_cast<char*>(scratch.p) + 448);
   static_assert(64 + kDistBins * 8 <= 448, "pattern analysis scratch");
-  int rc = dev_alloc(&P.perm, (size_t)nnz, "the transposed-entry index");
-  if (rc) return rc;
   LD_HIP(launch_fill_zero(scratch.p, 512, s));
-  LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, nnz, P.perm, missing, s));
   LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, nnz, hash, s));
   LD_HIP(launch_distance_hist(B->row_ptr, B->col_idx, d, nnz, hist, s));
   LD_HIP(launch_plane_fit(B->row_ptr, B->col_idx, d, 0, fit, s));
-  int miss = 0;
   unsigned long long fit_h[2] = {0, 0};
-  LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
   LD_HIP(hipMemcpyAsync(&P.hash, hash, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   LD_HIP(hipMemcpyAsync(P.dist_hist, hist, sizeof(P.dist_hist), hipMemcpyDeviceToHost, s));
   LD_HIP(hipMemcpyAsync(fit_h, fit, sizeof(fit_h), hipMemcpyDeviceToHost, s));
@@ -1071,6 +911,23 @@ int analyze_pattern(const ld_csr* B, hipStream_t s, PatternInfo& P) {
     LD_HIP(hipStreamSynchronize(s));
     if (fit_h[1] * 100 <= (uint64_t)nnz) P.plane_rows = reach;
   }
+  return LD_OK;
+}
+
+// The gradient's part: whether every entry has its transpose (then the transposed-entry index),
+// else the pattern of B^T.
+int analyze_full(const ld_csr* B, hipStream_t s, PatternInfo& P) {
+  const int64_t d = B->rows, nnz = B->nnz;
+  DevTmp flag;
+  LD_HIP(hipMalloc(&flag.p, 256));
+  int* missing = static_cast<int*>(flag.p);
+  int rc = dev_alloc(&P.perm, (size_t)nnz, "the transposed-entry index");
+  if (rc) return rc;
+  LD_HIP(launch_fill_zero(flag.p, 256, s));
+  LD_HIP(launch_transpose_index(B->row_ptr, B->col_idx, d, nnz, P.perm, missing, s));
+  int miss = 0;
+  LD_HIP(hipMemcpyAsync(&miss, missing, sizeof(int), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
   P.sym = miss == 0;
   if (P.sym) return LD_OK;
   (void)hipFree(P.perm);
@@ -1087,22 +944,34 @@ int analyze_pattern(const ld_csr* B, hipStream_t s, PatternInfo& P) {
   return LD_OK;
 }
 
-// The cached analysis of B's pattern, made on first sight.
-int get_pattern(const ld_csr* B, hipStream_t s, std::shared_ptr<PatternInfo>& out) {
+// Completes the gradient's part of an analysis once.
+int ensure_full(const ld_csr* B, hipStream_t s, PatternInfo& P) {
+  std::lock_guard<std::mutex> lk(P.full_mu);
+  if (P.full) return LD_OK;
+  const int rc = analyze_full(B, s, P);
+  if (rc) return rc;
+  P.full = true;
+  return LD_OK;
+}
+
+// The cached analysis of B's pattern, made on first sight (full: with the gradient's part).
+int get_pattern(const ld_csr* B, hipStream_t s, std::shared_ptr<PatternInfo>& out, bool full = true) {
   PatternKey key;
   int rc = pattern_key(B, key);
   if (rc) return rc;
   {
-    std::lock_guard<std::mutex> lk(g_pat_mu);
+    std::unique_lock<std::mutex> lk(g_pat_mu);
     auto it = g_pat.find(key);
     if (it != g_pat.end()) {
       it->second->last_use = ++g_pat_clock;
       out = it->second;
-      return LD_OK;
+      lk.unlock();
+      return full ? ensure_full(B, s, *out) : LD_OK;
     }
   }
   auto P = std::make_shared<PatternInfo>();
-  rc = analyze_pattern(B, s, *P);
+  rc = analyze_light(B, s, *P);
+  if (!rc && full) rc = ensure_full(B, s, *P);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(g_pat_mu);
   if (g_pat.size() >= kPatternCacheEntries) {
@@ -1345,6 +1214,217 @@ int get_stencil(PatternInfo& P, const ld_csr* B, hipStream_t s, const Shape& sh,
   P.stencil[ss] = S;
   out = S;
   return LD_OK;
+}
+
+// Shared body of ld_logdet_cheb and ld_logabsdet_cheb.
+// fixed_plan: no autotuning and no timing events (the planner's default shape), for callers that
+// must not allocate; the workspace is then always opt->workspace.
+// staged: the product-identity steps may run on staged stencil tiles (ld_logdet_cheb); the pattern
+// is then hashed again during the call, and a pattern found rewritten in place returns kRetryPattern
+// (allow_retry) or an error.
+int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double b, int n, int M_out, uint64_t seed,
+                const ld_opts* opt, hipStream_t s, ld_result* out, bool fixed_plan = false, bool staged = false,
+                bool allow_retry = true) {
+  const int valt = valt_of(B->dtype);
+  const int vec_f64 = vec_f64_of(opt, valt);
+  const int64_t d = B->rows;
+  const int M = padded_probes(M_out, vec_f64, opt);  // probes run; the estimate uses the first M_out
+  const bool pair = use_pairs(opt);
+  const int nsteps = steps_for(n, pair);
+  const int nrows = partial_rows(n, pair);
+  const size_t need = fwd_workspace(B, n, M_out, vec_f64, ns, opt);
+  Workspace ws;
+  int rc = get_workspace(opt, need, s, ws);
+  if (rc) return rc;
+
+  FwdPlan p = plan_fwd(B, vec_f64, M, opt);
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  const size_t vecb = (size_t)d * M * p.vb;
+  void* bufA = cv.take(vecb);
+  void* bufB = cv.take(vecb);
+  void* bufT = nullptr;
+  ld_csr Ct{};
+  if (ns) {
+    bufT = cv.take(vecb);
+    int64_t* rpt = static_cast<int64_t*>(cv.take((size_t)(d + 1) * 8));
+    int32_t* colt = static_cast<int32_t*>(cv.take((size_t)B->nnz * 4));
+    void* valt_ = cv.take((size_t)B->nnz * val_bytes(valt));
+    int64_t* cursor = static_cast<int64_t*>(cv.take((size_t)d * 8));
+    void* scan = cv.take(transpose_scratch_bytes(d));
+    if (Ct_in) {
+      Ct = *Ct_in;
+    } else {
+      LD_HIP(launch_transpose(B->row_ptr, B->col_idx, B->values, valt, d, B->nnz, rpt, colt, valt_, cursor, scan,
+                              transpose_scratch_bytes(d), s));
+      Ct = *B;
+      Ct.row_ptr = rpt;
+      Ct.col_idx = colt;
+      Ct.values = valt_;
+    }
+  }
+  const bool tune = !fixed_plan && (!opt || opt->tile == 0) && autotune_enabled() && d >= 65536;
+  double* part_base =
+      static_cast<double*>(cv.take((size_t)std::max(nrows, 1) * max_tiles(B, vec_f64, M, opt) * M * 8));
+  double* red_out = static_cast<double*>(cv.take((size_t)M * std::max(nrows, 1) * 8));
+  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(nrows, M)));
+  const int mu_mode = pair ? MU_PAIR : MU_PROBE;
+
+  if (tune && !ns) {
+    TuneKey key{vec_f64, valt, M, (opt ? opt->probe_tile : 0) * 4 + mu_mode, d, B->nnz};
+    Shape sh{};
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) sh = it->second;
+    }
+    if (!sh.tile_rows) {
+      const std::vector<Shape> shapes = (opt && opt->probe_tile > 0) ? std::vector<Shape>{p.sh}
+                                                                      : shape_candidates(vec_f64, M);
+      sh = autotune(B, shapes, vec_f64, valt, M, mu_mode, bufA, bufB, part_base, s);
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = sh;
+    }
+    if (sh.tile_rows > 0) {
+      p.sh = sh;
+      p.ntiles = (d + sh.tile_rows - 1) / sh.tile_rows;
+    }
+  }
+
+  // Staged steps on stencil patterns: the steps from k = 1 on read W_k's rows from LDS tiles.
+  std::shared_ptr<PatternInfo> pat;
+  std::shared_ptr<StencilPlan> sp;
+  StencilHold sp_hold;
+  sp_hold.s = s;
+  StencilDesc sd{};
+  uint64_t* hash_dev = static_cast<uint64_t*>(cv.take(256));
+  if (staged && !ns && !fixed_plan && pair && stencil_enabled() && d > 0 && !vec_f64 && valt != VAL_F64 &&
+      p.sh.probe_tiles == 1) {
+    rc = get_pattern(B, s, pat, false);
+    if (rc) return rc;
+    if (local_pattern(*pat, B->nnz, (size_t)M * p.vb)) {
+      rc = get_stencil(*pat, B, s, p.sh, p.vb, sp);
+      if (rc) return rc;
+    }
+    if (sp) {
+      sp_hold.take(sp.get());  // its packed entries, until this call's stream has drained
+      sd.ent = sp->ent;
+      sd.hacc = sp->hacc;
+      sd.K = sp->K;
+      sd.nofs = sp->nofs;
+      sd.nruns = sp->nruns;
+      std::copy(sp->run_base, sp->run_base + kStencilRuns, sd.run_base);
+      std::copy(sp->run_delta, sp->run_delta + kStencilRuns, sd.run_delta);
+      LD_HIP(launch_stencil_pack(B->values, valt, sp->emap, sp->lcol, sp->slots, sp->ent, s));
+      LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, B->nnz, hash_dev, s));
+    }
+  }
+  int staged_steps = 0;
+
+  const std::vector<double> c = cheb_coeffs(a, b, n);
+  const double alpha = 4.0 / (b - a);
+  const double beta = -2.0 * (a + b) / (b - a);
+  const double shift = ns ? 0.0 : B->diag_shift;
+  const double beff = beta + alpha * shift;
+  const int64_t kstride = p.ntiles * M;
+
+  StepTimer tm;
+  tm.on = !fixed_plan && opt && opt->timing;
+  tm.s = s;
+
+  StepLaunch L{};
+  L.nmat = 1;
+  L.ntiles = p.ntiles;
+  L.tile_rows = p.sh.tile_rows;
+  L.M = M;
+  L.shape = p.sh;
+
+  auto base_desc = [&](const ld_csr* X) {
+    StepDesc D{};
+    D.row_ptr = X->row_ptr;
+    D.col = X->col_idx;
+    D.val = X->values;
+    D.seed = seed;
+    D.d = d;
+    D.active = 1;
+    return D;
+  };
+  // step k writes partial row k (plain) or rows 2k, 2k+1 (pairs)
+  auto set_parts = [&](StepDesc& D, int k) {
+    D.mu_part = part_base + (int64_t)(pair ? 2 * k : k) * kstride;
+    D.mu_part2 = pair ? part_base + (int64_t)(2 * k + 1) * kstride : nullptr;
+  };
+
+  // W_k lives in: k = 0 -> probe hash, odd k -> A, even k >= 2 -> B.
+  auto wbuf = [&](int k) -> void* { return k == 0 ? nullptr : ((k & 1) ? bufA : bufB); };
+  LD_HIP(tm.mark(T_OTHER));
+  for (int k = 0; k < nsteps && d > 0; ++k) {
+    const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
+    const int psrc = k == 0 ? SRC_NONE : (k == 1 ? SRC_HASH : SRC_BUF);
+    const double h = k == 0 ? 0.5 : 1.0;  // W_1 = At V carries half of 2 At
+    if (!ns) {
+      StepDesc D = base_desc(B);
+      D.G = wbuf(k);
+      D.P = k >= 2 ? wbuf(k - 1) : nullptr;
+      D.out = wbuf(k + 1);
+      D.ag = h * alpha;
+      D.bd = h * beff;
+      D.cp = k == 0 ? 0.0 : -1.0;
+      set_parts(D, k);
+      L.d0 = D;
+      if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu_mode)) {
+        LD_HIP(launch_step_stencil(L, sd, valt, psrc, mu_mode, s));
+        ++staged_steps;
+      } else {
+        LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu_mode, s));
+      }
+      LD_HIP(tm.mark(T_STEP));
+    } else {
+      // T = C W_k
+      StepDesc D1 = base_desc(B);
+      D1.G = wbuf(k);
+      D1.out = bufT;
+      D1.ag = 1.0;
+      L.d0 = D1;
+      LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_NONE, SRC_NONE, MU_NONE, s));
+      LD_HIP(tm.mark(T_STEP));
+      // W_{k+1} = alpha C^T T + beta W_k - W_{k-1}   (halved at k = 0)
+      StepDesc D2 = base_desc(&Ct);
+      D2.G = bufT;
+      D2.D = wbuf(k);
+      D2.P = k >= 2 ? wbuf(k - 1) : nullptr;
+      D2.out = wbuf(k + 1);
+      D2.ag = h * alpha;
+      D2.bd = h * beta;
+      D2.cp = k == 0 ? 0.0 : -1.0;
+      set_parts(D2, k);
+      L.d0 = D2;
+      LD_HIP(launch_step(L, vec_f64, valt, SRC_BUF, k == 0 ? SRC_HASH : SRC_BUF, psrc, mu_mode, s));
+      LD_HIP(tm.mark(T_STEP));
+    }
+  }
+  std::vector<double> red((size_t)M * std::max(nrows, 1), 0.0);
+  if (nrows >= 1 && d > 0) {
+    LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 0, nrows - 1, kstride, red_out, nrows, red_tmp, s));
+    LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * nrows * 8, hipMemcpyDeviceToHost, s));
+  }
+  uint64_t hash = 0;
+  if (sp) LD_HIP(hipMemcpyAsync(&hash, hash_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  LD_HIP(hipStreamSynchronize(s));
+  if (sp && hash != pat->hash) {
+    // the stencil plan was made for another pattern at these addresses: analyse afresh and repeat
+    drop_pattern(B);
+    if (!allow_retry) return fail(LD_EINVAL, "the pattern of B changed while the estimate ran");
+    return kRetryPattern;
+  }
+  std::vector<double> mu((size_t)M_out * (n + 1), 0.0);
+  assemble_moments(red, nrows, pair, n, M_out, d, mu);  // rows of red are per probe: the first M_out
+  combine(mu, c, n, M_out, d, ns ? 0.5 : 1.0, out, opt);
+  out->poly_bound = lemma_bound(a, b, n, d) * (ns ? 0.5 : 1.0);
+  out->grad_shift = 0.0;
+  out->staged_steps = staged_steps;
+  tm.report(out);
+  return out->flags ? LD_WBOUNDS : LD_OK;
 }
 
 // Diagonal partials any adjoint launch of a gradient call may write: one per tile of the pass
@@ -1665,7 +1745,9 @@ static int logdet_cheb_impl(const ld_csr* B, double a, double b, int n, int M, u
   if (rc) return rc;
   if (!out) return fail(LD_EINVAL, "out is NULL");
   ld_result r{};
-  rc = run_forward(B, nullptr, false, a, b, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = run_forward(B, nullptr, false, a, b, n, M, seed, opt, s, &r, false, true, true);
+  if (rc == kRetryPattern) rc = run_forward(B, nullptr, false, a, b, n, M, seed, opt, s, &r, false, true, false);
   if (rc < 0) return rc;
   *out = r;
   return rc;
@@ -2078,6 +2160,7 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
   sp_hold.s = s;
   int staged_passes = 0;  // passes whose adjoint ran on staged stencil tiles
   int plane0 = 0;         // the first pass's plane-major order (tiles per plane)
+  int staged_steps = 0;   // forward steps on staged stencil tiles, over all passes
 
   for (int pass = 0; pass < ch.count; ++pass) {
     const int probe0 = pass * ch.size;  // a multiple of 64 whenever there is more than one pass
@@ -2138,8 +2221,10 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
         D.mu_part2 = pair ? part + (int64_t)(2 * k + 1) * kstride : nullptr;
       }
       L.d0 = D;
-      if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu))
+      if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu)) {
+        ++staged_steps;
         return launch_step_stencil(L, sd, valt, psrc, mu, s);
+      }
       return launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu, s);
     };
 
@@ -2305,6 +2390,7 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
                    : sym      ? LD_ADJ_EXPLICIT_SINGLE
                               : LD_ADJ_EXPLICIT_TWO;
   r.plane_tiles = plane0;
+  r.staged_steps = staged_steps;
   tm.report(&r);
   *out = r;
   return r.flags ? LD_WBOUNDS : LD_OK;

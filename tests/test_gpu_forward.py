@@ -14,6 +14,7 @@ import pytest
 import synth
 from tests import _ref
 from tests._gpu import U32, U64, b_form_moments, dev, floor_for, normwise, rel, say
+from tests._patterns import _banded, _grid2d_rect, _hex2d
 
 pytestmark = pytest.mark.gpu
 
@@ -107,6 +108,67 @@ def test_fp32_path_parity(ld, oracle_lib, case, plain):
     r = ld.ld_logdet_cheb(dev(B, shift=shift), a, b, n, M, 11, want_moments=True, want_probes=True, plain=plain)
     o = oracle_lib.logdet(B, a, b, n, M, seed=11, shift=shift, want_moments=True)
     _compare(r, o, TOL32, B.d, name, a, b, n)
+
+
+STAGED_CASES = {
+    # name: (builder, shift, degree, M, staged)
+    "grid2d_64_f32_M32": (lambda: _grid2d_rect(64, 64, "f32"), 0.05, 40, 32, True),
+    "grid2d_37x41_bf16_M16": (lambda: _grid2d_rect(37, 41, "bf16"), 0.2, 31, 16, True),  # ragged last tile
+    "hex2d_f32_M24": (lambda: _hex2d(33, 29, "f32"), 0.1, 22, 24, True),  # K = 7; 24 probes run as 32
+    "band3_bf16_M64": (lambda: _banded(1500, 3, "bf16", 4), 0.0, 20, 64, True),
+    "grid3d_12_f32_M64": (lambda: synth.grid_laplacian_3d(12, "f32"), 0.09, 30, 64, False),  # halo > 3 tiles
+    "grid2d_64_f32_M8": (lambda: _grid2d_rect(64, 64, "f32"), 0.05, 20, 8, False),  # 128-row pass: too tall
+}
+
+
+@pytest.mark.parametrize("case", sorted(STAGED_CASES))
+def test_staged_forward(ld, oracle_lib, case, monkeypatch):
+    """Stencil patterns (grids, lattices in natural order, bands) with FP32 vectors: every
+    product-identity step after the first reads W_k's rows from LDS tiles.  Moments, per-probe
+    values and the estimate against the oracle, and the estimate against the general step kernel
+    (LD_STENCIL=0); patterns the staged layout does not take run the general kernel."""
+    monkeypatch.delenv("LD_STENCIL", raising=False)
+    build, shift, n, M, staged = STAGED_CASES[case]
+    B = build()
+    a, b = oracle_lib.gershgorin(B, shift)
+    D = dev(B, shift=shift)
+    say(f"staged forward {case} d={B.d} nnz={B.nnz}")
+    r = ld.ld_logdet_cheb(D, a, b, n, M, 11, want_moments=True, want_probes=True)
+    assert r["staged_steps"] == ((n + 1) // 2 - 1 if staged else 0), r["staged_steps"]
+    o = oracle_lib.logdet(B, a, b, n, M, seed=11, shift=shift, want_moments=True)
+    _compare(r, o, TOL32, B.d, case, a, b, n)
+    monkeypatch.setenv("LD_STENCIL", "0")
+    r0 = ld.ld_logdet_cheb(D, a, b, n, M, 11)
+    assert r0["staged_steps"] == 0
+    fl = floor_for(a, b, n, B.d, TOL32, U32)
+    assert rel(r["logdet"], r0["logdet"], fl) <= TOL32
+
+
+def test_staged_forward_pattern_rewritten_in_place(ld, oracle_lib):
+    """The staged forward keeps its stencil plan per pattern; the same device arrays rewritten with
+    another pattern of the same sizes (a 64 x 32 grid renumbered as 32 x 64: vertical neighbours at
+    +-64 instead of +-32) are noticed by the pattern hash and the call is repeated with a new plan."""
+    import torch
+
+    A = _grid2d_rect(64, 32, "f32")
+    C = _grid2d_rect(32, 64, "f32")
+    assert A.nnz == C.nnz and A.d == C.d
+    D = dev(A, shift=0.1)
+    a, b = oracle_lib.gershgorin(A, 0.1)
+    say("staged forward: first pattern")
+    r1 = ld.ld_logdet_cheb(D, a, b, 24, 32, 5)
+    assert r1["staged_steps"] == 11
+    o1 = oracle_lib.logdet(A, a, b, 24, 32, seed=5, shift=0.1)
+    assert rel(r1["logdet"], o1["gamma"]) <= TOL32
+    D.row_ptr.copy_(torch.tensor(C.row_ptr, device=D.row_ptr.device))
+    D.col.copy_(torch.tensor(C.col, device=D.col.device))
+    D.values.copy_(torch.tensor(C.val, device=D.values.device))
+    say("staged forward: pattern rewritten in place")
+    r2 = ld.ld_logdet_cheb(D, a, b, 24, 32, 5, want_probes=True)
+    assert r2["staged_steps"] == 11
+    o2 = oracle_lib.logdet(C, a, b, 24, 32, seed=5, shift=0.1)
+    assert rel(r2["logdet"], o2["gamma"]) <= TOL32
+    assert np.max(np.abs(np.asarray(r2["s"]) - o2["s"])) <= TOL32 * np.max(np.abs(o2["s"]))
 
 
 def test_fp64_vectors_with_fp32_values(ld, oracle_lib):
