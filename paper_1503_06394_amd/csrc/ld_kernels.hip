@@ -418,6 +418,25 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
 // adjoint step (gradient): Clenshaw-type backward recurrence fused with the SDDMM
 // ------------------------------------------------------------------------------------
 
+// DPP lane exchange within a row of 16 lanes (a VALU operand modifier: no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, typename VT>
+__device__ __forceinline__ VT dpp_x(VT v) {
+  if constexpr (sizeof(VT) == 4)
+    return dpp_f32<CTRL>(v);
+  else
+    return dpp_f64<CTRL>(v);
+}
+
 // Two forms of the SDDMM term G_ij += gw * sum_p y1[i,p] w[j,p] for stored (i, j):
 //  * general pattern: gather w[j] next to y1[j] (two gathers per nonzero);
 //  * symmetric pattern (SYM): row i computes, for each stored (i, j), the value of the
@@ -636,35 +655,27 @@ adjoint_kernel(AdjDesc A, int M, int lpr_log2, int64_t tile_rows, int64_t ntiles
 // shifted adjoint step on vector tiles staged in LDS (stencil patterns)
 // ------------------------------------------------------------------------------------
 
-// DPP lane exchange within a row of 16 lanes (a VALU operand modifier: no LDS traffic).
-template <int CTRL>
-__device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL, typename VT>
-__device__ __forceinline__ VT dpp_x(VT v) {
-  if constexpr (sizeof(VT) == 4)
-    return dpp_f32<CTRL>(v);
-  else
-    return dpp_f64<CTRL>(v);
-}
-
 // Sum over the LPR consecutive lanes of a row group (LPR a power of two), every lane receiving
 // the total: exchanges within quads, then the mirrored half-row and row, then (LPR >= 32) shuffles.
-template <typename VT>
-__device__ __forceinline__ VT row_sum(VT v, int LPR) {
-  if (LPR >= 2) v += dpp_x<0xB1>(v);   // quad_perm [1,0,3,2]
-  if (LPR >= 4) v += dpp_x<0x4E>(v);   // quad_perm [2,3,0,1]
-  if (LPR >= 8) v += dpp_x<0x141>(v);  // row_half_mirror: lane i of 8 <- lane 7 - i
-  if (LPR >= 16) v += dpp_x<0x140>(v); // row_mirror: lane i of 16 <- lane 15 - i
-  for (int o = 16; o < LPR; o <<= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// N independent sums at once: one uniform branch per exchange level for all of them, and the N
+// exchanges of a level back to back.
+template <typename VT, int N>
+__device__ __forceinline__ void row_sums(VT (&v)[N], int LPR) {
+  if (LPR >= 2)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_x<0xB1>(v[k]);   // quad_perm [1,0,3,2]
+  if (LPR >= 4)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_x<0x4E>(v[k]);   // quad_perm [2,3,0,1]
+  if (LPR >= 8)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_x<0x141>(v[k]);  // row_half_mirror: lane i of 8 <- lane 7 - i
+  if (LPR >= 16)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_x<0x140>(v[k]);  // row_mirror: lane i of 16 <- lane 15 - i
+  for (int o = 16; o < LPR; o <<= 1)
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], o, 64);
 }
 
 // Packed entry of the stencil layout: LDS slot of the column and the value.
@@ -747,6 +758,8 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
     vload<VT, VPL>(W + roff, wown);
     if constexpr (Y2) vload_nt<VT, VPL>(static_cast<const VT*>(A.Y2) + roff, x2);
   }
+  // Ys holds the product's operand z = y_{k+1} + ck w_k of every staged row, Ws holds w_k
+  const VT ck = (VT)A.ck;
   for (int j = lr; j < S.nofs; j += TR) {
     int off = j + S.run_delta[0];  // run q holds halo indices [run_base[q], run_base[q + 1])
 #pragma unroll
@@ -760,10 +773,15 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
       vload<VT, VPL>(Y1 + r * M + p0, y);
       vload<VT, VPL>(W + r * M + p0, w);
     }
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) y[i] = fma(ck, w[i], y[i]);
     vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, y);
     vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, w);
   }
-  vstore<VT, VPL>(Ys + lr * tp + sub * VPL, yown);
+  VT zown[VPL];
+#pragma unroll
+  for (int i = 0; i < VPL; ++i) zown[i] = fma(ck, wown[i], yown[i]);
+  vstore<VT, VPL>(Ys + lr * tp + sub * VPL, zown);
   vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
 
   // the row's entry slots, issued before the barrier (their addresses do not depend on it); rows
@@ -782,27 +800,30 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   }
   __syncthreads();
 
-  const VT ag = (VT)A.ag, ck = (VT)A.ck, ce = (VT)A.ce, gw = (VT)A.gw;
+  const VT ag = (VT)A.ag, ce = (VT)A.ce, gw = (VT)A.gw;
   VT ysd[VPL], acc[VPL];
 #pragma unroll
   for (int i = 0; i < VPL; ++i) {
     ysd[i] = fma(-ce, wown[i], yown[i]);
     acc[i] = VT(0);
   }
+  VT dp[KK];
 #pragma unroll
   for (int k = 0; k < KK; ++k) {
-    VT yg[VPL], wg[VPL];
-    vload<VT, VPL>(Ys + lc[k] * tp + sub * VPL, yg);
+    VT zg[VPL], wg[VPL];
+    vload<VT, VPL>(Ys + lc[k] * tp + sub * VPL, zg);
     vload<VT, VPL>(Ws + lc[k] * tp + sub * VPL, wg);
     const VT a = ag * va[k];
-    VT dp = VT(0);
+    dp[k] = VT(0);
 #pragma unroll
     for (int i = 0; i < VPL; ++i) {
-      acc[i] = fma(a, fma(ck, wg[i], yg[i]), acc[i]);
-      dp = fma(ysd[i], wg[i], dp);
+      acc[i] = fma(a, zg[i], acc[i]);
+      dp[k] = fma(ysd[i], wg[i], dp[k]);
     }
-    h[k] = fma(gw, row_sum<VT>(dp, LPR), h[k]);
   }
+  row_sums<VT, KK>(dp, LPR);
+#pragma unroll
+  for (int k = 0; k < KK; ++k) h[k] = fma(gw, dp[k], h[k]);
   if (!has) return;
   // every lane of the row holds the sums: lane 0 writes the KK slots back (padding too: never read out)
   if (sub == 0)
@@ -811,7 +832,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   const VT bd = (VT)A.bd, cp = (VT)A.cp, cw = (VT)A.cw;
 #pragma unroll
   for (int i = 0; i < VPL; ++i) {
-    VT o = fma(bd, fma(ck, wown[i], yown[i]), acc[i]);
+    VT o = fma(bd, zown[i], acc[i]);
     o = fma(cw, wown[i], o);
     acc[i] = Y2 ? fma(cp, x2[i], o) : o;
   }
