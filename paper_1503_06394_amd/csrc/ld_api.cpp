@@ -1270,7 +1270,40 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
   double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(nrows, M)));
   const int mu_mode = pair ? MU_PAIR : MU_PROBE;
 
-  if (tune && !ns) {
+  // Staged steps on stencil patterns: the steps from k = 1 on read W_k's rows from LDS tiles.
+  std::shared_ptr<PatternInfo> pat;
+  std::shared_ptr<StencilPlan> sp;
+  StencilHold sp_hold;
+  sp_hold.s = s;
+  StencilDesc sd{};
+  uint64_t* hash_dev = static_cast<uint64_t*>(cv.take(256));
+  if (staged && !ns && !fixed_plan && pair && stencil_enabled() && d > 0 && !vec_f64 && valt != VAL_F64 &&
+      p.sh.probe_tiles == 1) {
+    rc = get_pattern(B, s, pat, false);
+    if (rc) return rc;
+    if (local_pattern(*pat, B->nnz, (size_t)M * p.vb)) {
+      rc = get_stencil(*pat, B, s, p.sh, p.vb, sp);
+      if (rc) return rc;
+    }
+    if (sp) {
+      // the staged step's tile: a power-of-two number of stencil tiles (on the 4096^2 grid 256 rows
+      // run the step in 1.35 ms, the default 320 in 1.42 ms); the tuner times the general kernel only
+      p.sh = plane_shape(p.sh, opt);
+      p.ntiles = (d + p.sh.tile_rows - 1) / p.sh.tile_rows;
+      sp_hold.take(sp.get());  // its packed entries, until this call's stream has drained
+      sd.ent = sp->ent;
+      sd.hacc = sp->hacc;
+      sd.K = sp->K;
+      sd.nofs = sp->nofs;
+      sd.nruns = sp->nruns;
+      std::copy(sp->run_base, sp->run_base + kStencilRuns, sd.run_base);
+      std::copy(sp->run_delta, sp->run_delta + kStencilRuns, sd.run_delta);
+      LD_HIP(launch_stencil_pack(B->values, valt, sp->emap, sp->lcol, sp->slots, sp->ent, s));
+      LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, B->nnz, hash_dev, s));
+    }
+  }
+
+  if (tune && !ns && !sp) {
     TuneKey key{vec_f64, valt, M, (opt ? opt->probe_tile : 0) * 4 + mu_mode, d, B->nnz};
     Shape sh{};
     {
@@ -1291,34 +1324,6 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
     }
   }
 
-  // Staged steps on stencil patterns: the steps from k = 1 on read W_k's rows from LDS tiles.
-  std::shared_ptr<PatternInfo> pat;
-  std::shared_ptr<StencilPlan> sp;
-  StencilHold sp_hold;
-  sp_hold.s = s;
-  StencilDesc sd{};
-  uint64_t* hash_dev = static_cast<uint64_t*>(cv.take(256));
-  if (staged && !ns && !fixed_plan && pair && stencil_enabled() && d > 0 && !vec_f64 && valt != VAL_F64 &&
-      p.sh.probe_tiles == 1) {
-    rc = get_pattern(B, s, pat, false);
-    if (rc) return rc;
-    if (local_pattern(*pat, B->nnz, (size_t)M * p.vb)) {
-      rc = get_stencil(*pat, B, s, p.sh, p.vb, sp);
-      if (rc) return rc;
-    }
-    if (sp) {
-      sp_hold.take(sp.get());  // its packed entries, until this call's stream has drained
-      sd.ent = sp->ent;
-      sd.hacc = sp->hacc;
-      sd.K = sp->K;
-      sd.nofs = sp->nofs;
-      sd.nruns = sp->nruns;
-      std::copy(sp->run_base, sp->run_base + kStencilRuns, sd.run_base);
-      std::copy(sp->run_delta, sp->run_delta + kStencilRuns, sd.run_delta);
-      LD_HIP(launch_stencil_pack(B->values, valt, sp->emap, sp->lcol, sp->slots, sp->ent, s));
-      LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, B->nnz, hash_dev, s));
-    }
-  }
   int staged_steps = 0;
 
   const std::vector<double> c = cheb_coeffs(a, b, n);
@@ -2172,14 +2177,15 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
       ps.plane = plane_tiles(pat.get(), ps, d, (size_t)Mp * vb);
       if (ps.plane) sh = ps;
     }
-    if (pass == 0) plane0 = sh.plane;
-    const int64_t ntiles = tiles_of(B, sh);
-    const int64_t kstride = ntiles * Mp;
     std::shared_ptr<StencilPlan> sp;  // staged tiles of this pass's shifted adjoint
     if (shifted && stencil_on && pat) {
       rc = get_stencil(*pat, B, s, sh, vb, sp);
       if (rc) return rc;
     }
+    if (sp && !sh.plane) sh = plane_shape(sh, opt);  // the staged step's tile, as in the estimator
+    if (pass == 0) plane0 = sh.plane;
+    const int64_t ntiles = tiles_of(B, sh);
+    const int64_t kstride = ntiles * Mp;
     StencilDesc sd{};
     if (sp) {
       ++staged_passes;
