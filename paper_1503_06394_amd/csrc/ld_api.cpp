@@ -1059,7 +1059,7 @@ int build_stencil_plan(const ld_csr* B, hipStream_t s, int tr, int cap, std::sha
   }
   if ((int)runs.size() > kStencilRuns) return LD_OK;
   // a halo beyond three tiles' worth of rows (3-D lattices: four) stages more than the entries save
-  // (measured on the 128^3 GMRF: 0.66 ms per step staged against 0.40 ms explicit)
+  // (measured on the 128^3 GMRF: adjoint 0.52 ms per step staged against 0.40 ms explicit)
   if ((int64_t)ofs.size() > 3 * (int64_t)tr) return LD_OK;
   for (auto& r : runs)
     if (r.first < INT32_MIN / 2 || r.first > INT32_MAX / 2) return LD_OK;
