@@ -709,6 +709,17 @@ struct StencilEnt<VAL_F64> {
   }
 };
 
+constexpr int kHaloPasses = 3;  // halo rows per thread of a staged tile: the plan keeps nofs <= 3 TR
+
+// Offset (from the tile's first row) of halo index j: run q holds indices [run_base[q], run_base[q + 1]).
+__device__ __forceinline__ int halo_offset(const StencilDesc& S, int j) {
+  int off = j + S.run_delta[0];
+#pragma unroll
+  for (int q = 1; q < kStencilRuns; ++q)
+    if (q < S.nruns && j >= S.run_base[q]) off = j + S.run_delta[q];
+  return off;
+}
+
 // The shifted adjoint gathers rows of both y_{k+1} and w_k at every stored entry.  On a stencil
 // pattern the rows a tile's entries reach are its own rows and r0 + ofs[j] for a short offset list
 // (a few runs, passed by value), so the block copies those rows of both operands into LDS once, all
@@ -760,23 +771,29 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   }
   // Ys holds the product's operand z = y_{k+1} + ck w_k of every staged row, Ws holds w_k
   const VT ck = (VT)A.ck;
-  for (int j = lr; j < S.nofs; j += TR) {
-    int off = j + S.run_delta[0];  // run q holds halo indices [run_base[q], run_base[q + 1])
+  // every halo row this thread stages (at most kHaloPasses: the plan keeps nofs <= kHaloPasses TR)
+  // loaded first, all in flight together, then written to LDS
+  VT hy[kHaloPasses][VPL], hw[kHaloPasses][VPL];
 #pragma unroll
-    for (int q = 1; q < kStencilRuns; ++q)
-      if (q < S.nruns && j >= S.run_base[q]) off = j + S.run_delta[q];
-    const int64_t r = row0 + off;
-    VT y[VPL], w[VPL];
+  for (int h = 0; h < kHaloPasses; ++h) {
+    const int j = lr + h * TR;
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) y[i] = w[i] = VT(0);
-    if (r >= 0 && r < A.d && pact) {
-      vload<VT, VPL>(Y1 + r * M + p0, y);
-      vload<VT, VPL>(W + r * M + p0, w);
+    for (int i = 0; i < VPL; ++i) hy[h][i] = hw[h][i] = VT(0);
+    const int64_t r = row0 + halo_offset(S, j);
+    if (j < S.nofs && r >= 0 && r < A.d && pact) {
+      vload<VT, VPL>(Y1 + r * M + p0, hy[h]);
+      vload<VT, VPL>(W + r * M + p0, hw[h]);
     }
+  }
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) y[i] = fma(ck, w[i], y[i]);
-    vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, y);
-    vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, w);
+  for (int h = 0; h < kHaloPasses; ++h) {
+    const int j = lr + h * TR;
+    if (j < S.nofs) {
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) hy[h][i] = fma(ck, hw[h][i], hy[h][i]);
+      vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, hy[h]);
+      vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
+    }
   }
   VT zown[VPL];
 #pragma unroll
@@ -900,17 +917,19 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
     } else if constexpr (PSRC == SRC_HASH) {
       probe_signs<VT, VPL>(D.seed, row, p0, pv);
     }
-    for (int j = lr; j < S.nofs; j += TR) {
-      int off = j + S.run_delta[0];
+    VT hw[kHaloPasses][VPL];
 #pragma unroll
-      for (int q = 1; q < kStencilRuns; ++q)
-        if (q < S.nruns && j >= S.run_base[q]) off = j + S.run_delta[q];
-      const int64_t r = sr0 + off;
-      VT w[VPL];
+    for (int h = 0; h < kHaloPasses; ++h) {
+      const int j = lr + h * TR;
 #pragma unroll
-      for (int i = 0; i < VPL; ++i) w[i] = VT(0);
-      if (r >= 0 && r < D.d && pact) vload<VT, VPL>(G + r * M + p0, w);
-      vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, w);
+      for (int i = 0; i < VPL; ++i) hw[h][i] = VT(0);
+      const int64_t r = sr0 + halo_offset(S, j);
+      if (j < S.nofs && r >= 0 && r < D.d && pact) vload<VT, VPL>(G + r * M + p0, hw[h]);
+    }
+#pragma unroll
+    for (int h = 0; h < kHaloPasses; ++h) {
+      const int j = lr + h * TR;
+      if (j < S.nofs) vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
     }
     vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
     const int64_t e0 = row * (int64_t)KK;  // slot (tile * TR + lr) * KK of the padded layout
@@ -1615,7 +1634,7 @@ static hipError_t adj_stencil_by_vpl(const AdjDesc& A, const StencilDesc& S, int
   const int64_t per = (ntiles + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
   const size_t lds = 2 * (size_t)(tr + S.nofs) * (size_t)((1 << sh.lpr_log2) * sh.vpl) * sizeof(VT);
-  if (tr > kStencilRows || lds > (size_t)kStencilLdsBytes) return hipErrorInvalidValue;
+  if (tr > kStencilRows || lds > (size_t)kStencilLdsBytes || S.nofs > kHaloPasses * tr) return hipErrorInvalidValue;
   // K = 5 and 7 (2-D and 3-D grids) run exactly; other K up to kStencilK are planned as 8
 #define LD_STEN(V_, Y_, K_)                                                                                      \
   if (sh.vpl == V_ && y2 == Y_ && S.K == K_) {                                                                   \
@@ -1681,7 +1700,7 @@ hipError_t launch_step_stencil(const StepLaunch& L, const StencilDesc& S, int va
   const size_t tp = (size_t)(1 << L.shape.lpr_log2) * L.shape.vpl;
   const size_t lds = std::max((size_t)(tr + S.nofs) * tp * sizeof(float),
                               mu == MU_PAIR ? (size_t)2 * kWaves * 256 * sizeof(double) : (size_t)0);
-  if (lds > (size_t)kStencilLdsBytes) return hipErrorInvalidValue;
+  if (lds > (size_t)kStencilLdsBytes || S.nofs > kHaloPasses * tr) return hipErrorInvalidValue;
   const int64_t per = (L.ntiles + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
   if (valt == VAL_BF16)
