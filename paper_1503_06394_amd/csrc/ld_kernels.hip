@@ -189,11 +189,40 @@ __device__ __forceinline__ bool stage_tile(TileCsr<VALT>& T, const int64_t* rp, 
   const int nrows = (int)(row_end - row0);
   const bool fits = (nz1 - nz0) <= kStageNnz && nrows <= kStageRows;
   if (fits) {
-    for (int i = threadIdx.x; i <= nrows; i += kBlock) T.rp[i] = (int)(rp[row0 + i] - nz0);
+    // every load of the thread's share in flight before the first LDS write (a loop that wrote each
+    // value before loading the next waited one round trip per value)
+    constexpr int kRpPer = (kStageRows + 1 + kBlock - 1) / kBlock, kNzPer = (kStageNnz + kBlock - 1) / kBlock;
     const int nnz = (int)(nz1 - nz0);
-    for (int i = threadIdx.x; i < nnz; i += kBlock) {
-      T.col[i] = ci[nz0 + i];
-      T.val[i] = Val<VALT>::get(val, nz0 + i);
+    int64_t rv[kRpPer];
+    int cv[kNzPer];
+    typename Val<VALT>::T vv[kNzPer];
+#pragma unroll
+    for (int q = 0; q < kRpPer; ++q) {
+      const int i = (int)threadIdx.x + q * kBlock;
+      rv[q] = i <= nrows ? rp[row0 + i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kNzPer; ++q) {
+      const int i = (int)threadIdx.x + q * kBlock;
+      cv[q] = 0;
+      vv[q] = 0;
+      if (i < nnz) {
+        cv[q] = ci[nz0 + i];
+        vv[q] = Val<VALT>::get(val, nz0 + i);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kRpPer; ++q) {
+      const int i = (int)threadIdx.x + q * kBlock;
+      if (i <= nrows) T.rp[i] = (int)(rv[q] - nz0);
+    }
+#pragma unroll
+    for (int q = 0; q < kNzPer; ++q) {
+      const int i = (int)threadIdx.x + q * kBlock;
+      if (i < nnz) {
+        T.col[i] = cv[q];
+        T.val[i] = vv[q];
+      }
     }
   }
   __syncthreads();
@@ -243,135 +272,144 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepLaunch L) {
 #pragma unroll
   for (int i = 0; i < VPL; ++i) mu[i] = mu2[i] = VT(0);
 
-  for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
-    const int64_t row = base + grp;
-    const bool has = row < row_end;
-    const int lr = (int)(row - row0);
-    int64_t s = 0, e = 0;  // entry range relative to nz0
-    if (has) {
-      if (staged) {
-        s = T.rp[lr];
-        e = T.rp[lr + 1];
-      } else {
-        s = rp[row] - nz0;
-        e = rp[row + 1] - nz0;
-      }
-    }
-    const int64_t off = (has ? row : row0) * (int64_t)M + p0;
-    // streamed operands first, so their latency overlaps the gathers
-    VT pv[VPL];
-    if constexpr (PSRC == SRC_BUF) {
-      if (has) vload_nt<VT, VPL>(P + off, pv);
-    } else if constexpr (PSRC == SRC_HASH) {
-      probe_signs<VT, VPL>(D.seed, row, p0, pv);
-    }
-    VT dv[VPL];
-    if constexpr (DSRC == SRC_BUF) {
-      if (has) vload<VT, VPL>(Dv + off, dv);
-    } else if constexpr (DSRC == SRC_HASH) {
-      probe_signs<VT, VPL>(D.seed, row, p0, dv);
-    }
-
-    VT acc[VPL];
-    VT wk[VPL];  // own row of the gathered operand (MU_PAIR with the diagonal folded in)
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) acc[i] = wk[i] = VT(0);
-    bool hd = false;
-    for (int64_t t = s; t < e; t += kUnrollStep) {
-      int cc[kUnrollStep];
-      VT aa[kUnrollStep];
-      bool ok[kUnrollStep];
-#pragma unroll
-      for (int u = 0; u < kUnrollStep; ++u) {
-        ok[u] = t + u < e;
-        int cu = 0;
-        MV vu = MV(0);
-        if (ok[u]) {
-          if (staged) {
-            cu = T.col[t + u];
-            vu = T.val[t + u];
-          } else {
-            cu = ci[nz0 + t + u];
-            vu = Val<VALT>::get(D.val, nz0 + t + u);
-          }
-        }
-        VT a = ag * (VT)vu;
-        if constexpr (DSRC == SRC_SAME) {
-          if (ok[u] && cu == row) {
-            a += bd;
-            hd = true;
-          }
-        }
-        aa[u] = a;
-        cc[u] = cu;
-      }
-      VT gg[kUnrollStep][VPL];
-#pragma unroll
-      for (int u = 0; u < kUnrollStep; ++u) {
-        if (ok[u]) {
-          if constexpr (GSRC == SRC_BUF)
-            vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
-          else
-            probe_signs<VT, VPL>(D.seed, cc[u], p0, gg[u]);
+  // the row passes, compiled once for the staged slice and once for the global one (one code path
+  // each: a runtime choice per entry left loads of both kinds in flight and forced full waits)
+  auto row_passes = [&](auto stg) {
+    constexpr bool STG = decltype(stg)::value;
+    for (int64_t base = row0 + wave * RPW; base < row_end; base += (int64_t)kWaves * RPW) {
+      const int64_t row = base + grp;
+      const bool has = row < row_end;
+      const int lr = (int)(row - row0);
+      int64_t s = 0, e = 0;  // entry range relative to nz0
+      if (has) {
+        if constexpr (STG) {
+          s = T.rp[lr];
+          e = T.rp[lr + 1];
         } else {
-#pragma unroll
-          for (int i = 0; i < VPL; ++i) gg[u][i] = VT(0);
+          s = rp[row] - nz0;
+          e = rp[row + 1] - nz0;
         }
       }
-#pragma unroll
-      for (int u = 0; u < kUnrollStep; ++u)
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
-      if constexpr (MU == MU_PAIR && DSRC == SRC_SAME) {
-#pragma unroll
-        for (int u = 0; u < kUnrollStep; ++u)
-          if (ok[u] && cc[u] == row)
-#pragma unroll
-            for (int i = 0; i < VPL; ++i) wk[i] = gg[u][i];
+      const int64_t off = (has ? row : row0) * (int64_t)M + p0;
+      // streamed operands first, so their latency overlaps the gathers
+      VT pv[VPL];
+      if constexpr (PSRC == SRC_BUF) {
+        if (has) vload_nt<VT, VPL>(P + off, pv);
+      } else if constexpr (PSRC == SRC_HASH) {
+        probe_signs<VT, VPL>(D.seed, row, p0, pv);
       }
-    }
+      VT dv[VPL];
+      if constexpr (DSRC == SRC_BUF) {
+        if (has) vload<VT, VPL>(Dv + off, dv);
+      } else if constexpr (DSRC == SRC_HASH) {
+        probe_signs<VT, VPL>(D.seed, row, p0, dv);
+      }
 
-    if (has) {
-      if constexpr (DSRC == SRC_SAME) {
-        if (!hd) {  // pattern without a stored diagonal in this row
-          VT g[VPL];
-          if constexpr (GSRC == SRC_BUF)
-            vload<VT, VPL>(G + off, g);
-          else
-            probe_signs<VT, VPL>(D.seed, row, p0, g);
-#pragma unroll
-          for (int i = 0; i < VPL; ++i) {
-            acc[i] = fma(bd, g[i], acc[i]);
-            wk[i] = g[i];
+      VT acc[VPL];
+      VT wk[VPL];  // own row of the gathered operand (MU_PAIR with the diagonal folded in)
+  #pragma unroll
+      for (int i = 0; i < VPL; ++i) acc[i] = wk[i] = VT(0);
+      bool hd = false;
+      for (int64_t t = s; t < e; t += kUnrollStep) {
+        int cc[kUnrollStep];
+        VT aa[kUnrollStep];
+        bool ok[kUnrollStep];
+  #pragma unroll
+        for (int u = 0; u < kUnrollStep; ++u) {
+          ok[u] = t + u < e;
+          int cu = 0;
+          MV vu = MV(0);
+          if (ok[u]) {
+            if constexpr (STG) {
+              cu = T.col[t + u];
+              vu = T.val[t + u];
+            } else {
+              cu = ci[nz0 + t + u];
+              vu = Val<VALT>::get(D.val, nz0 + t + u);
+            }
+          }
+          VT a = ag * (VT)vu;
+          if constexpr (DSRC == SRC_SAME) {
+            if (ok[u] && cu == row) {
+              a += bd;
+              hd = true;
+            }
+          }
+          aa[u] = a;
+          cc[u] = cu;
+        }
+        VT gg[kUnrollStep][VPL];
+  #pragma unroll
+        for (int u = 0; u < kUnrollStep; ++u) {
+          if (ok[u]) {
+            if constexpr (GSRC == SRC_BUF)
+              vload<VT, VPL>(G + (int64_t)cc[u] * M + p0, gg[u]);
+            else
+              probe_signs<VT, VPL>(D.seed, cc[u], p0, gg[u]);
+          } else {
+  #pragma unroll
+            for (int i = 0; i < VPL; ++i) gg[u][i] = VT(0);
           }
         }
-      } else if constexpr (DSRC != SRC_NONE) {
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) wk[i] = dv[i];
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
+  #pragma unroll
+        for (int u = 0; u < kUnrollStep; ++u)
+  #pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(aa[u], gg[u][i], acc[i]);
+        if constexpr (MU == MU_PAIR && DSRC == SRC_SAME) {
+  #pragma unroll
+          for (int u = 0; u < kUnrollStep; ++u)
+            if (ok[u] && cc[u] == row)
+  #pragma unroll
+              for (int i = 0; i < VPL; ++i) wk[i] = gg[u][i];
+        }
       }
-      if constexpr (PSRC != SRC_NONE) {
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
-      }
-      if (pact) {
-        vstore_nt<VT, VPL>(out + off, acc);
-        if constexpr (MU == MU_PROBE) {
-          const uint64_t w = probe_word(D.seed, (uint64_t)row, (uint32_t)(p0 >> 6));
-          const uint32_t bits = (uint32_t)(w >> (p0 & 63));
-#pragma unroll
-          for (int i = 0; i < VPL; ++i) mu[i] += ((bits >> i) & 1u) ? -acc[i] : acc[i];
-        } else if constexpr (MU == MU_PAIR) {
-#pragma unroll
-          for (int i = 0; i < VPL; ++i) {
-            mu[i] = fma(acc[i], wk[i], mu[i]);
-            mu2[i] = fma(acc[i], acc[i], mu2[i]);
+
+      if (has) {
+        if constexpr (DSRC == SRC_SAME) {
+          if (!hd) {  // pattern without a stored diagonal in this row
+            VT g[VPL];
+            if constexpr (GSRC == SRC_BUF)
+              vload<VT, VPL>(G + off, g);
+            else
+              probe_signs<VT, VPL>(D.seed, row, p0, g);
+  #pragma unroll
+            for (int i = 0; i < VPL; ++i) {
+              acc[i] = fma(bd, g[i], acc[i]);
+              wk[i] = g[i];
+            }
+          }
+        } else if constexpr (DSRC != SRC_NONE) {
+  #pragma unroll
+          for (int i = 0; i < VPL; ++i) wk[i] = dv[i];
+  #pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(bd, dv[i], acc[i]);
+        }
+        if constexpr (PSRC != SRC_NONE) {
+  #pragma unroll
+          for (int i = 0; i < VPL; ++i) acc[i] = fma(cp, pv[i], acc[i]);
+        }
+        if (pact) {
+          vstore_nt<VT, VPL>(out + off, acc);
+          if constexpr (MU == MU_PROBE) {
+            const uint64_t w = probe_word(D.seed, (uint64_t)row, (uint32_t)(p0 >> 6));
+            const uint32_t bits = (uint32_t)(w >> (p0 & 63));
+  #pragma unroll
+            for (int i = 0; i < VPL; ++i) mu[i] += ((bits >> i) & 1u) ? -acc[i] : acc[i];
+          } else if constexpr (MU == MU_PAIR) {
+  #pragma unroll
+            for (int i = 0; i < VPL; ++i) {
+              mu[i] = fma(acc[i], wk[i], mu[i]);
+              mu2[i] = fma(acc[i], acc[i], mu2[i]);
+            }
           }
         }
       }
     }
-  }
+  };
+  if (staged)
+    row_passes(std::integral_constant<bool, true>{});
+  else
+    row_passes(std::integral_constant<bool, false>{});
 
   if constexpr (MU != MU_NONE) {
     // fixed-order reduction: wave butterfly, then waves summed in order through LDS that
