@@ -840,7 +840,8 @@ def bench_taylor(args, W, copy_gbps) -> None:
     mu = 2.0 - 2.0 * np.cos(np.pi * np.arange(1, N + 1) / (N + 1))
     exact = float(np.log((mu[:, None] + mu[None, :]).ravel() + W["shift"]).sum())
     value = M * n * B.nnz / (ms / 1e3)
-    sb = step_bytes(B.d, B.nnz, M, 2, 4)
+    # a Taylor step W_{k+1} = A W_k reads the matrix and W_k once and writes W_{k+1}: two vector blocks
+    sb = csr_bytes(B.d, B.nnz, 2) + 2 * B.d * M * 4
     avg = kms / max(kn, 1)
     cpu = parity = None
     if not args.no_cpu_baseline:

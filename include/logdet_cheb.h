@@ -85,9 +85,9 @@ typedef struct {
                                natural order whose planes span more vector rows than an XCD's L2:
                                each XCD takes one column of every plane, planes in turn), this many
                                tiles per plane.  The results do not depend on the order. */
-    int32_t staged_steps;   /* ld_logdet_cheb and the gradient: recurrence steps that ran on vector
-                               tiles staged in LDS (stencil patterns, FP32 vectors, FP32 or BF16
-                               values, product identities: every step after the first); 0 elsewhere */
+    int32_t staged_steps;   /* ld_logdet_cheb, the gradient and the Taylor comparator: recurrence steps
+                               that ran on vector tiles staged in LDS (stencil patterns, FP32 vectors,
+                               FP32 or BF16 values, one probe tile: every step); 0 elsewhere */
 } ld_result;
 
 /* ld_result.adjoint_form.  The product-identity forward (symmetric pattern) has two adjoints:

@@ -611,80 +611,10 @@ size_t taylor_workspace(const ld_csr* B, int n, int M, int vec_f64, const ld_opt
   c.take((size_t)rows * tiles * M * 8);
   c.take((size_t)M * rows * 8);
   c.take(reduce_scratch_bytes(rows, M));
+  c.take(256);  // pattern hash (staged steps)
   return align_up(c.off);
 }
 
-int run_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt, hipStream_t s,
-               ld_result* out) {
-  const int valt = valt_of(B->dtype);
-  const int vec_f64 = vec_f64_of(opt, valt);
-  const int64_t d = B->rows;
-  Workspace ws;
-  int rc = get_workspace(opt, taylor_workspace(B, n, M, vec_f64, opt), s, ws);
-  if (rc) return rc;
-  FwdPlan p = plan_fwd(B, vec_f64, M, opt);
-  Carve cv;
-  cv.base = static_cast<char*>(ws.ptr);
-  const size_t vecb = (size_t)d * M * p.vb;
-  void* buf[2] = {cv.take(vecb), cv.take(vecb)};
-  const int rows = std::max(n, 1);
-  double* part_base = static_cast<double*>(cv.take((size_t)rows * max_tiles(B, vec_f64, M, opt) * M * 8));
-  double* red_out = static_cast<double*>(cv.take((size_t)M * rows * 8));
-  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(rows, M)));
-  const int64_t kstride = p.ntiles * M;
-  const double scale = a + b;  // B/(a + b) has spectrum in [delta, 1 - delta] (Section 3.1)
-
-  StepTimer tm;
-  tm.on = opt && opt->timing;
-  tm.s = s;
-  StepLaunch L{};
-  L.nmat = 1;
-  L.ntiles = p.ntiles;
-  L.tile_rows = p.sh.tile_rows;
-  L.M = M;
-  L.shape = p.sh;
-  LD_HIP(tm.mark(T_OTHER));
-  for (int k = 0; k < n && d > 0; ++k) {  // W_{k+1} = A W_k with W_0 = V from the probe hash
-    StepDesc D{};
-    D.row_ptr = B->row_ptr;
-    D.col = B->col_idx;
-    D.val = B->values;
-    D.seed = seed;
-    D.d = d;
-    D.active = 1;
-    D.G = k == 0 ? nullptr : buf[(k - 1) & 1];
-    D.out = buf[k & 1];
-    D.ag = -1.0 / scale;
-    D.bd = 1.0 - B->diag_shift / scale;
-    D.cp = 0.0;  // the probe-hash third operand costs no memory traffic and is scaled away
-    D.mu_part = part_base + (int64_t)k * kstride;
-    L.d0 = D;
-    LD_HIP(launch_step(L, vec_f64, valt, k == 0 ? SRC_HASH : SRC_BUF, SRC_SAME, k == 0 ? SRC_NONE : SRC_HASH,
-                       MU_PROBE, s));
-    LD_HIP(tm.mark(T_STEP));
-  }
-  std::vector<double> red((size_t)M * rows, 0.0);
-  if (n >= 1 && d > 0) {
-    LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 0, n - 1, kstride, red_out, n, red_tmp, s));
-    LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * n * 8, hipMemcpyDeviceToHost, s));
-  }
-  LD_HIP(hipStreamSynchronize(s));
-  // log det B = d log(a + b) - sum_k tr(A^k)/k: coefficients log(a + b) on mu_0 = v^T v = d and -1/k
-  std::vector<double> mu((size_t)M * (n + 1), 0.0), c(n + 1);
-  c[0] = std::log(scale);
-  for (int k = 1; k <= n; ++k) c[k] = -1.0 / k;
-  for (int j = 0; j < M; ++j) {
-    mu[(size_t)j * (n + 1)] = (double)d;
-    for (int k = 1; k <= n; ++k) mu[(size_t)j * (n + 1) + k] = red[(size_t)j * rows + (k - 1)];
-  }
-  combine(mu, c, n, M, d, 1.0, out, opt);
-  // truncation: |sum_{k>n} tr(A^k)/k| <= d q^{n+1} / ((n+1)(1-q)), q = 1 - delta = b/(a+b)
-  const double q = b / scale;
-  out->poly_bound = (double)d * std::pow(q, n + 1) / ((n + 1) * (1.0 - q));
-  out->grad_shift = 0.0;
-  tm.report(out);
-  return out->flags ? LD_WBOUNDS : LD_OK;
-}
 
 }  // namespace
 
@@ -1217,6 +1147,72 @@ int get_stencil(PatternInfo& P, const ld_csr* B, hipStream_t s, const Shape& sh,
   return LD_OK;
 }
 
+// Staged steps of an estimator call (ld_logdet_cheb, ld_logdet_taylor) on a stencil pattern: the
+// cached plan of the pattern (only the cheap part of its analysis), its packed entries refreshed
+// from the values of this call and held until the call's stream has drained, and the pattern hashed
+// again during the call.  A pattern rewritten in place since the plan was made is caught by check()
+// once the stream has drained: the caller analyses it again and repeats the call.
+struct StagedSteps {
+  std::shared_ptr<PatternInfo> pat;
+  std::shared_ptr<StencilPlan> sp;
+  StencilHold hold;
+  StencilDesc sd{};
+  uint64_t* hash_dev = nullptr;  // 256 bytes of the caller's workspace
+  uint64_t hash = 0;
+  int steps = 0;
+
+  // Sets the plan up when B is a stencil pattern for the shape sh (one probe tile); sh then takes
+  // the staged tile height (a power-of-two number of stencil tiles) and ntiles follows it.
+  int setup(const ld_csr* B, hipStream_t s, Shape& sh, int64_t& ntiles, int M, size_t vb, int valt, int vec_f64,
+            const ld_opts* opt, void* hash_buf) {
+    hold.s = s;
+    hash_dev = static_cast<uint64_t*>(hash_buf);
+    const int64_t d = B->rows;
+    if (!stencil_enabled() || d <= 0 || vec_f64 || valt == VAL_F64 || sh.probe_tiles != 1) return LD_OK;
+    int rc = get_pattern(B, s, pat, false);
+    if (rc) return rc;
+    if (local_pattern(*pat, B->nnz, (size_t)M * vb)) {
+      rc = get_stencil(*pat, B, s, sh, vb, sp);
+      if (rc) return rc;
+    }
+    if (!sp) return LD_OK;
+    // on the 4096^2 grid 256-row blocks run the staged step in 1.33 ms, the 320-row default in 1.42 ms
+    sh = plane_shape(sh, opt);
+    ntiles = (d + sh.tile_rows - 1) / sh.tile_rows;
+    hold.take(sp.get());
+    sd.ent = sp->ent;
+    sd.hacc = sp->hacc;
+    sd.K = sp->K;
+    sd.nofs = sp->nofs;
+    sd.nruns = sp->nruns;
+    std::copy(sp->run_base, sp->run_base + kStencilRuns, sd.run_base);
+    std::copy(sp->run_delta, sp->run_delta + kStencilRuns, sd.run_delta);
+    LD_HIP(launch_stencil_pack(B->values, valt, sp->emap, sp->lcol, sp->slots, sp->ent, s));
+    LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, B->nnz, hash_dev, s));
+    return LD_OK;
+  }
+  // One step, staged when the plan and the step's form allow it.
+  hipError_t step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu, hipStream_t s) {
+    if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, dsrc, psrc, mu)) {
+      ++steps;
+      return launch_step_stencil(L, sd, valt, gsrc, psrc, mu, s);
+    }
+    return launch_step(L, vec_f64, valt, gsrc, dsrc, psrc, mu, s);
+  }
+  // Before the call's final synchronisation.
+  int enqueue_hash(hipStream_t s) {
+    if (sp) LD_HIP(hipMemcpyAsync(&hash, hash_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    return LD_OK;
+  }
+  // After it: the pattern is the one the plan was made for, or kRetryPattern / an error.
+  int check(const ld_csr* B, bool allow_retry) {
+    if (!sp || hash == pat->hash) return LD_OK;
+    drop_pattern(B);
+    if (!allow_retry) return fail(LD_EINVAL, "the pattern of B changed while the estimate ran");
+    return kRetryPattern;
+  }
+};
+
 // Shared body of ld_logdet_cheb and ld_logabsdet_cheb.
 // fixed_plan: no autotuning and no timing events (the planner's default shape), for callers that
 // must not allocate; the workspace is then always opt->workspace.
@@ -1271,40 +1267,15 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
   double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(nrows, M)));
   const int mu_mode = pair ? MU_PAIR : MU_PROBE;
 
-  // Staged steps on stencil patterns: the steps from k = 1 on read W_k's rows from LDS tiles.
-  std::shared_ptr<PatternInfo> pat;
-  std::shared_ptr<StencilPlan> sp;
-  StencilHold sp_hold;
-  sp_hold.s = s;
-  StencilDesc sd{};
-  uint64_t* hash_dev = static_cast<uint64_t*>(cv.take(256));
-  if (staged && !ns && !fixed_plan && pair && stencil_enabled() && d > 0 && !vec_f64 && valt != VAL_F64 &&
-      p.sh.probe_tiles == 1) {
-    rc = get_pattern(B, s, pat, false);
+  // Staged steps on stencil patterns: every step reads W_k's rows (or the probe signs) from LDS tiles.
+  StagedSteps st;
+  void* hash_buf = cv.take(256);
+  if (staged && !ns && !fixed_plan) {
+    rc = st.setup(B, s, p.sh, p.ntiles, M, p.vb, valt, vec_f64, opt, hash_buf);
     if (rc) return rc;
-    if (local_pattern(*pat, B->nnz, (size_t)M * p.vb)) {
-      rc = get_stencil(*pat, B, s, p.sh, p.vb, sp);
-      if (rc) return rc;
-    }
-    if (sp) {
-      // the staged step's tile: a power-of-two number of stencil tiles (on the 4096^2 grid 256 rows
-      // run the step in 1.35 ms, the default 320 in 1.42 ms); the tuner times the general kernel only
-      p.sh = plane_shape(p.sh, opt);
-      p.ntiles = (d + p.sh.tile_rows - 1) / p.sh.tile_rows;
-      sp_hold.take(sp.get());  // its packed entries, until this call's stream has drained
-      sd.ent = sp->ent;
-      sd.hacc = sp->hacc;
-      sd.K = sp->K;
-      sd.nofs = sp->nofs;
-      sd.nruns = sp->nruns;
-      std::copy(sp->run_base, sp->run_base + kStencilRuns, sd.run_base);
-      std::copy(sp->run_delta, sp->run_delta + kStencilRuns, sd.run_delta);
-      LD_HIP(launch_stencil_pack(B->values, valt, sp->emap, sp->lcol, sp->slots, sp->ent, s));
-      LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, B->nnz, hash_dev, s));
-    }
   }
 
-  if (tune && !ns && !sp) {
+  if (tune && !ns && !st.sp) {
     TuneKey key{vec_f64, valt, M, (opt ? opt->probe_tile : 0) * 4 + mu_mode, d, B->nnz};
     Shape sh{};
     {
@@ -1324,8 +1295,6 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       p.ntiles = (d + sh.tile_rows - 1) / sh.tile_rows;
     }
   }
-
-  int staged_steps = 0;
 
   const std::vector<double> c = cheb_coeffs(a, b, n);
   const double alpha = 4.0 / (b - a);
@@ -1378,12 +1347,7 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
       D.cp = k == 0 ? 0.0 : -1.0;
       set_parts(D, k);
       L.d0 = D;
-      if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu_mode)) {
-        LD_HIP(launch_step_stencil(L, sd, valt, psrc, mu_mode, s));
-        ++staged_steps;
-      } else {
-        LD_HIP(launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu_mode, s));
-      }
+      LD_HIP(st.step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu_mode, s));
       LD_HIP(tm.mark(T_STEP));
     } else {
       // T = C W_k
@@ -1414,21 +1378,97 @@ int run_forward(const ld_csr* B, const ld_csr* Ct_in, bool ns, double a, double 
     LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 0, nrows - 1, kstride, red_out, nrows, red_tmp, s));
     LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * nrows * 8, hipMemcpyDeviceToHost, s));
   }
-  uint64_t hash = 0;
-  if (sp) LD_HIP(hipMemcpyAsync(&hash, hash_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  rc = st.enqueue_hash(s);
+  if (rc) return rc;
   LD_HIP(hipStreamSynchronize(s));
-  if (sp && hash != pat->hash) {
-    // the stencil plan was made for another pattern at these addresses: analyse afresh and repeat
-    drop_pattern(B);
-    if (!allow_retry) return fail(LD_EINVAL, "the pattern of B changed while the estimate ran");
-    return kRetryPattern;
-  }
+  rc = st.check(B, allow_retry);
+  if (rc) return rc;
   std::vector<double> mu((size_t)M_out * (n + 1), 0.0);
   assemble_moments(red, nrows, pair, n, M_out, d, mu);  // rows of red are per probe: the first M_out
   combine(mu, c, n, M_out, d, ns ? 0.5 : 1.0, out, opt);
   out->poly_bound = lemma_bound(a, b, n, d) * (ns ? 0.5 : 1.0);
   out->grad_shift = 0.0;
-  out->staged_steps = staged_steps;
+  out->staged_steps = st.steps;
+  tm.report(out);
+  return out->flags ? LD_WBOUNDS : LD_OK;
+}
+
+int run_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed, const ld_opts* opt, hipStream_t s,
+               ld_result* out, bool allow_retry = true) {
+  const int valt = valt_of(B->dtype);
+  const int vec_f64 = vec_f64_of(opt, valt);
+  const int64_t d = B->rows;
+  Workspace ws;
+  int rc = get_workspace(opt, taylor_workspace(B, n, M, vec_f64, opt), s, ws);
+  if (rc) return rc;
+  FwdPlan p = plan_fwd(B, vec_f64, M, opt);
+  Carve cv;
+  cv.base = static_cast<char*>(ws.ptr);
+  const size_t vecb = (size_t)d * M * p.vb;
+  void* buf[2] = {cv.take(vecb), cv.take(vecb)};
+  const int rows = std::max(n, 1);
+  double* part_base = static_cast<double*>(cv.take((size_t)rows * max_tiles(B, vec_f64, M, opt) * M * 8));
+  double* red_out = static_cast<double*>(cv.take((size_t)M * rows * 8));
+  double* red_tmp = static_cast<double*>(cv.take(reduce_scratch_bytes(rows, M)));
+  StagedSteps st;
+  rc = st.setup(B, s, p.sh, p.ntiles, M, p.vb, valt, vec_f64, opt, cv.take(256));
+  if (rc) return rc;
+  const int64_t kstride = p.ntiles * M;
+  const double scale = a + b;  // B/(a + b) has spectrum in [delta, 1 - delta] (Section 3.1)
+
+  StepTimer tm;
+  tm.on = opt && opt->timing;
+  tm.s = s;
+  StepLaunch L{};
+  L.nmat = 1;
+  L.ntiles = p.ntiles;
+  L.tile_rows = p.sh.tile_rows;
+  L.M = M;
+  L.shape = p.sh;
+  LD_HIP(tm.mark(T_OTHER));
+  for (int k = 0; k < n && d > 0; ++k) {  // W_{k+1} = A W_k with W_0 = V from the probe hash
+    StepDesc D{};
+    D.row_ptr = B->row_ptr;
+    D.col = B->col_idx;
+    D.val = B->values;
+    D.seed = seed;
+    D.d = d;
+    D.active = 1;
+    D.G = k == 0 ? nullptr : buf[(k - 1) & 1];
+    D.out = buf[k & 1];
+    D.ag = -1.0 / scale;
+    D.bd = 1.0 - B->diag_shift / scale;
+    D.cp = 0.0;  // the probe-hash third operand costs no memory traffic and is scaled away
+    D.mu_part = part_base + (int64_t)k * kstride;
+    L.d0 = D;
+    LD_HIP(st.step(L, vec_f64, valt, k == 0 ? SRC_HASH : SRC_BUF, SRC_SAME, k == 0 ? SRC_NONE : SRC_HASH, MU_PROBE,
+                   s));
+    LD_HIP(tm.mark(T_STEP));
+  }
+  std::vector<double> red((size_t)M * rows, 0.0);
+  if (n >= 1 && d > 0) {
+    LD_HIP(launch_reduce_moments(part_base, p.ntiles, M, 0, n - 1, kstride, red_out, n, red_tmp, s));
+    LD_HIP(hipMemcpyAsync(red.data(), red_out, (size_t)M * n * 8, hipMemcpyDeviceToHost, s));
+  }
+  rc = st.enqueue_hash(s);
+  if (rc) return rc;
+  LD_HIP(hipStreamSynchronize(s));
+  rc = st.check(B, allow_retry);
+  if (rc) return rc;
+  // log det B = d log(a + b) - sum_k tr(A^k)/k: coefficients log(a + b) on mu_0 = v^T v = d and -1/k
+  std::vector<double> mu((size_t)M * (n + 1), 0.0), c(n + 1);
+  c[0] = std::log(scale);
+  for (int k = 1; k <= n; ++k) c[k] = -1.0 / k;
+  for (int j = 0; j < M; ++j) {
+    mu[(size_t)j * (n + 1)] = (double)d;
+    for (int k = 1; k <= n; ++k) mu[(size_t)j * (n + 1) + k] = red[(size_t)j * rows + (k - 1)];
+  }
+  combine(mu, c, n, M, d, 1.0, out, opt);
+  // truncation: |sum_{k>n} tr(A^k)/k| <= d q^{n+1} / ((n+1)(1-q)), q = 1 - delta = b/(a+b)
+  const double q = b / scale;
+  out->poly_bound = (double)d * std::pow(q, n + 1) / ((n + 1) * (1.0 - q));
+  out->grad_shift = 0.0;
+  out->staged_steps = st.steps;
   tm.report(out);
   return out->flags ? LD_WBOUNDS : LD_OK;
 }
@@ -1794,7 +1834,9 @@ static int logdet_taylor_impl(const ld_csr* B, double a, double b, int n, int M,
   if (rc) return rc;
   if (!out) return fail(LD_EINVAL, "out is NULL");
   ld_result r{};
-  rc = run_taylor(B, a, b, n, M, seed, opt, static_cast<hipStream_t>(stream), &r);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = run_taylor(B, a, b, n, M, seed, opt, s, &r, true);
+  if (rc == kRetryPattern) rc = run_taylor(B, a, b, n, M, seed, opt, s, &r, false);
   if (rc < 0) return rc;
   *out = r;
   return rc;
@@ -2230,7 +2272,7 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
       L.d0 = D;
       if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu)) {
         ++staged_steps;
-        return launch_step_stencil(L, sd, valt, psrc, mu, s);
+        return launch_step_stencil(L, sd, valt, gsrc, psrc, mu, s);
       }
       return launch_step(L, vec_f64, valt, gsrc, SRC_SAME, psrc, mu, s);
     };

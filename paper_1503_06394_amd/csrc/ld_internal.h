@@ -142,11 +142,13 @@ inline size_t stencil_entry_bytes(int valt) { return valt == VAL_BF16 ? 4 : (val
 hipError_t launch_adjoint_stencil(const AdjDesc& A, const StencilDesc& S, int M, const Shape& sh, int vec_f64,
                                   int valt, bool y2, hipStream_t s);
 // The recurrence step (launch_step's operands) on staged stencil tiles, for the combinations
-// step_stencil_supported accepts: FP32 vectors, FP32/BF16 values, W_k from a buffer with the
-// diagonal folded, W_{k-1} from a buffer or the probe hash, MU_PAIR or MU_NONE, one probe tile,
-// tiles a whole number of stencil tiles.  S's plan must be for the launch shape's stencil tile.
+// step_stencil_supported accepts: FP32 vectors, FP32/BF16 values, the diagonal folded into the product,
+// W_k from a buffer (W_{k-1} from a buffer or the probe hash, or none with probe moments) or from the
+// probe hash (no W_{k-1}), MU_PAIR, MU_PROBE or MU_NONE, one probe tile, tiles a whole number of
+// stencil tiles.  S's plan must be for the launch shape's stencil tile.
 bool step_stencil_supported(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu);
-hipError_t launch_step_stencil(const StepLaunch& L, const StencilDesc& S, int valt, int psrc, int mu, hipStream_t s);
+hipError_t launch_step_stencil(const StepLaunch& L, const StencilDesc& S, int valt, int gsrc, int psrc, int mu,
+                               hipStream_t s);
 // ent[i] = packed (lcol[i], emap[i] >= 0 ? val[emap[i]] : 0), i < n.
 hipError_t launch_stencil_pack(const void* val, int valt, const int32_t* emap, const uint16_t* lcol, int64_t n,
                                void* ent, hipStream_t s);

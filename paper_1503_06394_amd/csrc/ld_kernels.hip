@@ -905,8 +905,9 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
 // moment partials, where W_k's rows reach each entry from LDS.  A block covers one row tile of the
 // pass shape (so that its moment partials keep the step kernel's [tile][M] layout) as a sequence of
 // stencil tiles of one row pass each: stage the own and offset rows of W_k, barrier, one row per
-// lane group, barrier.  FP32 vectors, FP32 or BF16 values, a single probe tile.
-template <int VALT, int VPL, int PSRC, int MU, int KK>
+// lane group, barrier.  FP32 vectors, FP32 or BF16 values, a single probe tile.  W_k comes from a
+// buffer or (k = 0) from the probe hash, for own and offset rows alike.
+template <int VALT, int VPL, int GSRC, int PSRC, int MU, int KK>
 __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, StencilDesc S) {
   typedef float VT;
   typedef typename Val<VALT>::T MV;
@@ -949,7 +950,12 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
     VT wown[VPL], pv[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) wown[i] = pv[i] = VT(0);
-    if (has && pact) vload<VT, VPL>(G + roff, wown);
+    if (has && pact) {
+      if constexpr (GSRC == SRC_HASH)
+        probe_signs<VT, VPL>(D.seed, row, p0, wown);
+      else
+        vload<VT, VPL>(G + roff, wown);
+    }
     if constexpr (PSRC == SRC_BUF) {
       if (has && pact) vload_nt<VT, VPL>(P + roff, pv);
     } else if constexpr (PSRC == SRC_HASH) {
@@ -962,7 +968,12 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
 #pragma unroll
       for (int i = 0; i < VPL; ++i) hw[h][i] = VT(0);
       const int64_t r = sr0 + halo_offset(S, j);
-      if (j < S.nofs && r >= 0 && r < D.d && pact) vload<VT, VPL>(G + r * M + p0, hw[h]);
+      if (j < S.nofs && r >= 0 && r < D.d && pact) {
+        if constexpr (GSRC == SRC_HASH)
+          probe_signs<VT, VPL>(D.seed, r, p0, hw[h]);
+        else
+          vload<VT, VPL>(G + r * M + p0, hw[h]);
+      }
     }
 #pragma unroll
     for (int h = 0; h < kHaloPasses; ++h) {
@@ -1003,12 +1014,18 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
           mu[i] = fma(acc[i], wown[i], mu[i]);
           mu2[i] = fma(acc[i], acc[i], mu2[i]);
         }
+      } else if constexpr (MU == MU_PROBE) {
+        const uint64_t w = probe_word(D.seed, (uint64_t)row, (uint32_t)(p0 >> 6));
+        const uint32_t bits = (uint32_t)(w >> (p0 & 63));
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) mu[i] += ((bits >> i) & 1u) ? -acc[i] : acc[i];
       }
     }
     __syncthreads();  // the next stencil tile overwrites the staged rows
   }
 
-  if constexpr (MU == MU_PAIR) {
+  if constexpr (MU != MU_NONE) {
+    constexpr int NQ = MU == MU_PAIR ? 2 : 1;
     // fixed-order reduction as in the step kernel: wave butterfly, then waves summed in order
     double m1[VPL], m2[VPL];
 #pragma unroll
@@ -1020,17 +1037,17 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
         m1[i] += __shfl_xor(m1[i], o, 64);
-        m2[i] += __shfl_xor(m2[i], o, 64);
+        if constexpr (NQ == 2) m2[i] += __shfl_xor(m2[i], o, 64);
       }
-    double* red = reinterpret_cast<double*>(ld_step_smem);  // [2][kWaves][256] (the launch sizes it)
+    double* red = reinterpret_cast<double*>(ld_step_smem);  // [NQ][kWaves][256] (the launch sizes it)
     if (grp == 0)
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
         red[wave * 256 + sub * VPL + i] = m1[i];
-        red[(kWaves + wave) * 256 + sub * VPL + i] = m2[i];
+        if constexpr (NQ == 2) red[(kWaves + wave) * 256 + sub * VPL + i] = m2[i];
       }
     __syncthreads();
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       double* dst = (q == 0 ? D.mu_part : D.mu_part2) + (tile - D.tile0) * (int64_t)M;
       for (int j = threadIdx.x; j < tp; j += kBlock)
         if (j < M) {
@@ -1707,46 +1724,62 @@ hipError_t launch_adjoint_stencil(const AdjDesc& A, const StencilDesc& S, int M,
   return hipErrorInvalidValue;
 }
 
+// Operand sources and moment forms the staged step is built for: the product-identity forward (k = 0
+// from the hash, k = 1 with the hash as W_{k-1}, then buffers), its recomputation without moments,
+// the plain recurrence's probe moments, and the plain product with probe moments (Taylor series).
+static bool stencil_combo(int g, int p, int mu) {
+  if (g == SRC_HASH) return p == SRC_NONE && (mu == MU_PAIR || mu == MU_NONE || mu == MU_PROBE);
+  if (g != SRC_BUF) return false;
+  if (p == SRC_BUF || p == SRC_HASH) return mu == MU_PAIR || mu == MU_NONE || mu == MU_PROBE;
+  return p == SRC_NONE && mu == MU_PROBE;
+}
+
 template <int VALT, int VPL>
-static hipError_t step_stencil_by_flags(const StepLaunch& L, const StencilDesc& S, int psrc, int mu, size_t lds,
-                                        dim3 grid, hipStream_t s) {
-#define LD_SS(P_, MU_, K_)                                                                                       \
-  if (psrc == P_ && mu == MU_ && S.K == K_) {                                                                   \
-    hipLaunchKernelGGL((step_stencil_kernel<VALT, VPL, P_, MU_, K_>), grid, dim3(kBlock), lds, s, L, S);       \
+static hipError_t step_stencil_by_flags(const StepLaunch& L, const StencilDesc& S, int gsrc, int psrc, int mu,
+                                        size_t lds, dim3 grid, hipStream_t s) {
+#define LD_SS(G_, P_, MU_, K_)                                                                                   \
+  if (gsrc == G_ && psrc == P_ && mu == MU_ && S.K == K_) {                                                     \
+    hipLaunchKernelGGL((step_stencil_kernel<VALT, VPL, G_, P_, MU_, K_>), grid, dim3(kBlock), lds, s, L, S);   \
     return hipGetLastError();                                                                                   \
   }
-#define LD_SS_K(P_, MU_) LD_SS(P_, MU_, 5) LD_SS(P_, MU_, 7) LD_SS(P_, MU_, 8)
-  LD_SS_K(SRC_BUF, MU_PAIR)
-  LD_SS_K(SRC_HASH, MU_PAIR)
-  LD_SS_K(SRC_BUF, MU_NONE)
-  LD_SS_K(SRC_HASH, MU_NONE)
+#define LD_SS_K(G_, P_, MU_) LD_SS(G_, P_, MU_, 5) LD_SS(G_, P_, MU_, 7) LD_SS(G_, P_, MU_, 8)
+  LD_SS_K(SRC_BUF, SRC_BUF, MU_PAIR)
+  LD_SS_K(SRC_BUF, SRC_HASH, MU_PAIR)
+  LD_SS_K(SRC_HASH, SRC_NONE, MU_PAIR)
+  LD_SS_K(SRC_BUF, SRC_BUF, MU_NONE)
+  LD_SS_K(SRC_BUF, SRC_HASH, MU_NONE)
+  LD_SS_K(SRC_HASH, SRC_NONE, MU_NONE)
+  LD_SS_K(SRC_BUF, SRC_BUF, MU_PROBE)
+  LD_SS_K(SRC_BUF, SRC_HASH, MU_PROBE)
+  LD_SS_K(SRC_HASH, SRC_NONE, MU_PROBE)
+  LD_SS_K(SRC_BUF, SRC_NONE, MU_PROBE)
 #undef LD_SS_K
 #undef LD_SS
   return hipErrorInvalidValue;
 }
 
 bool step_stencil_supported(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu) {
-  return !vec_f64 && valt != VAL_F64 && gsrc == SRC_BUF && dsrc == SRC_SAME && (psrc == SRC_BUF || psrc == SRC_HASH) &&
-         (mu == MU_PAIR || mu == MU_NONE) && L.descs == nullptr && L.shape.probe_tiles == 1 &&
-         (L.shape.vpl == 2 || L.shape.vpl == 4) && L.tile_rows % stencil_tile_rows(L.shape.lpr_log2) == 0 &&
-         stencil_tile_rows(L.shape.lpr_log2) <= kStencilRows;
+  return !vec_f64 && valt != VAL_F64 && dsrc == SRC_SAME && stencil_combo(gsrc, psrc, mu) && L.descs == nullptr &&
+         L.shape.probe_tiles == 1 && (L.shape.vpl == 2 || L.shape.vpl == 4) &&
+         L.tile_rows % stencil_tile_rows(L.shape.lpr_log2) == 0 && stencil_tile_rows(L.shape.lpr_log2) <= kStencilRows;
 }
 
-hipError_t launch_step_stencil(const StepLaunch& L, const StencilDesc& S, int valt, int psrc, int mu, hipStream_t s) {
+hipError_t launch_step_stencil(const StepLaunch& L, const StencilDesc& S, int valt, int gsrc, int psrc, int mu,
+                               hipStream_t s) {
   if (L.ntiles <= 0) return hipSuccess;
   const int tr = stencil_tile_rows(L.shape.lpr_log2);
   const size_t tp = (size_t)(1 << L.shape.lpr_log2) * L.shape.vpl;
   const size_t lds = std::max((size_t)(tr + S.nofs) * tp * sizeof(float),
-                              mu == MU_PAIR ? (size_t)2 * kWaves * 256 * sizeof(double) : (size_t)0);
+                              (size_t)(mu == MU_PAIR ? 2 : mu == MU_PROBE ? 1 : 0) * kWaves * 256 * sizeof(double));
   if (lds > (size_t)kStencilLdsBytes || S.nofs > kHaloPasses * tr) return hipErrorInvalidValue;
   const int64_t per = (L.ntiles + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
   if (valt == VAL_BF16)
-    return L.shape.vpl == 4 ? step_stencil_by_flags<VAL_BF16, 4>(L, S, psrc, mu, lds, grid, s)
-                            : step_stencil_by_flags<VAL_BF16, 2>(L, S, psrc, mu, lds, grid, s);
+    return L.shape.vpl == 4 ? step_stencil_by_flags<VAL_BF16, 4>(L, S, gsrc, psrc, mu, lds, grid, s)
+                            : step_stencil_by_flags<VAL_BF16, 2>(L, S, gsrc, psrc, mu, lds, grid, s);
   if (valt == VAL_F32)
-    return L.shape.vpl == 4 ? step_stencil_by_flags<VAL_F32, 4>(L, S, psrc, mu, lds, grid, s)
-                            : step_stencil_by_flags<VAL_F32, 2>(L, S, psrc, mu, lds, grid, s);
+    return L.shape.vpl == 4 ? step_stencil_by_flags<VAL_F32, 4>(L, S, gsrc, psrc, mu, lds, grid, s)
+                            : step_stencil_by_flags<VAL_F32, 2>(L, S, gsrc, psrc, mu, lds, grid, s);
   return hipErrorInvalidValue;
 }
 

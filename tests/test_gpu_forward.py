@@ -121,24 +121,27 @@ STAGED_CASES = {
 }
 
 
+@pytest.mark.parametrize("plain", [False, True])
 @pytest.mark.parametrize("case", sorted(STAGED_CASES))
-def test_staged_forward(ld, oracle_lib, case, monkeypatch):
-    """Stencil patterns (grids, lattices in natural order, bands) with FP32 vectors: every
-    product-identity step after the first reads W_k's rows from LDS tiles.  Moments, per-probe
-    values and the estimate against the oracle, and the estimate against the general step kernel
-    (LD_STENCIL=0); patterns the staged layout does not take run the general kernel."""
+def test_staged_forward(ld, oracle_lib, case, plain, monkeypatch):
+    """Stencil patterns (grids, lattices in natural order, bands) with FP32 vectors: every step of
+    the product-identity or the plain recurrence reads W_k's rows (the first the probe signs) from LDS
+    tiles.  Moments, per-probe values and the estimate against the oracle, and the estimate against
+    the general step kernel (LD_STENCIL=0); patterns the staged layout does not take run the general
+    kernel."""
     monkeypatch.delenv("LD_STENCIL", raising=False)
     build, shift, n, M, staged = STAGED_CASES[case]
     B = build()
     a, b = oracle_lib.gershgorin(B, shift)
     D = dev(B, shift=shift)
-    say(f"staged forward {case} d={B.d} nnz={B.nnz}")
-    r = ld.ld_logdet_cheb(D, a, b, n, M, 11, want_moments=True, want_probes=True)
-    assert r["staged_steps"] == ((n + 1) // 2 - 1 if staged else 0), r["staged_steps"]
+    say(f"staged forward {case} plain={plain} d={B.d} nnz={B.nnz}")
+    r = ld.ld_logdet_cheb(D, a, b, n, M, 11, want_moments=True, want_probes=True, plain=plain)
+    steps = n if plain else (n + 1) // 2
+    assert r["staged_steps"] == (steps if staged else 0), r["staged_steps"]
     o = oracle_lib.logdet(B, a, b, n, M, seed=11, shift=shift, want_moments=True)
     _compare(r, o, TOL32, B.d, case, a, b, n)
     monkeypatch.setenv("LD_STENCIL", "0")
-    r0 = ld.ld_logdet_cheb(D, a, b, n, M, 11)
+    r0 = ld.ld_logdet_cheb(D, a, b, n, M, 11, plain=plain)
     assert r0["staged_steps"] == 0
     fl = floor_for(a, b, n, B.d, TOL32, U32)
     assert rel(r["logdet"], r0["logdet"], fl) <= TOL32
@@ -157,7 +160,7 @@ def test_staged_forward_pattern_rewritten_in_place(ld, oracle_lib):
     a, b = oracle_lib.gershgorin(A, 0.1)
     say("staged forward: first pattern")
     r1 = ld.ld_logdet_cheb(D, a, b, 24, 32, 5)
-    assert r1["staged_steps"] == 11
+    assert r1["staged_steps"] == 12
     o1 = oracle_lib.logdet(A, a, b, 24, 32, seed=5, shift=0.1)
     assert rel(r1["logdet"], o1["gamma"]) <= TOL32
     D.row_ptr.copy_(torch.tensor(C.row_ptr, device=D.row_ptr.device))
@@ -165,7 +168,7 @@ def test_staged_forward_pattern_rewritten_in_place(ld, oracle_lib):
     D.values.copy_(torch.tensor(C.val, device=D.values.device))
     say("staged forward: pattern rewritten in place")
     r2 = ld.ld_logdet_cheb(D, a, b, 24, 32, 5, want_probes=True)
-    assert r2["staged_steps"] == 11
+    assert r2["staged_steps"] == 12
     o2 = oracle_lib.logdet(C, a, b, 24, 32, seed=5, shift=0.1)
     assert rel(r2["logdet"], o2["gamma"]) <= TOL32
     assert np.max(np.abs(np.asarray(r2["s"]) - o2["s"])) <= TOL32 * np.max(np.abs(o2["s"]))

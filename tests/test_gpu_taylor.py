@@ -46,6 +46,30 @@ def test_taylor_parity(ld, oracle_lib, name, make, shift, n, M, tol):
     assert np.all(np.abs(r["moments"]) <= B.d * (1 + 1e-6))
 
 
+@pytest.mark.parametrize("storage,M", [("bf16", 32), ("f32", 16)])
+def test_taylor_staged_steps(ld, oracle_lib, storage, M, monkeypatch):
+    """On a grid (a stencil pattern) with FP32 vectors every Taylor step reads W_k's rows from LDS
+    tiles (the first from the probe hash): per-probe parity with the oracle and with the general step
+    kernel (LD_STENCIL=0)."""
+    monkeypatch.delenv("LD_STENCIL", raising=False)
+    B = synth.grid_laplacian_2d(100, storage)
+    shift, n = 0.05, 25
+    a, b = oracle_lib.gershgorin(B, shift)
+    D = dev(B, shift=shift)
+    say(f"taylor staged {storage} M={M}")
+    r = ld.ld_logdet_taylor(D, a, b, n, M, 7, want_probes=True)
+    assert r["staged_steps"] == n, r["staged_steps"]
+    o = oracle_lib.logdet_taylor(B, a, b, n, M, seed=7, shift=shift)
+    fl = floor_taylor(a, b, n, B.d, 1e-4, U32)
+    assert rel(r["logdet"], o["gamma"], fl) <= 1e-4
+    for j in range(M):
+        assert rel(r["s"][j], o["s"][j], fl) <= 1e-4, j
+    monkeypatch.setenv("LD_STENCIL", "0")
+    r0 = ld.ld_logdet_taylor(D, a, b, n, M, 7)
+    assert r0["staged_steps"] == 0
+    assert rel(r["logdet"], r0["logdet"], fl) <= 1e-4
+
+
 @pytest.mark.parametrize("n", [0, 1, 2])
 def test_taylor_low_degree(ld, oracle_lib, n):
     B = synth.random_sparse_spd(2000, 3, 8, 1.0, "f64")
