@@ -743,9 +743,37 @@ struct StencilPlan {
   uint16_t* lcol = nullptr;
   int32_t* emap = nullptr;
   int64_t* dslot = nullptr;  // [d] slot of each row's diagonal entry
-  void* ent = nullptr;       // 16 bytes per slot: room for any packed entry
-  void* hacc = nullptr;      // 8 bytes per slot: room for either accumulator type
-  std::mutex mu;
+  void* ent = nullptr;       // packed entries, ent_bytes per slot
+  void* hacc = nullptr;      // adjoint accumulators, hacc_bytes per slot
+  size_t ent_bytes = 0, hacc_bytes = 0;
+  std::mutex mu;             // held by the call that uses ent and hacc (StencilHold)
+  // Per-call buffers for a call's value type and vector precision, grown on demand (the caller holds
+  // mu, and the previous holder's stream has drained).
+  int ensure(size_t eb, size_t hb) {
+    if (eb > ent_bytes) {
+      if (ent) (void)hipFree(ent);
+      ent = nullptr;
+      ent_bytes = 0;
+      hipError_t e = hipMalloc(&ent, (size_t)std::max<int64_t>(slots, 1) * eb);
+      if (e != hipSuccess) {
+        ent = nullptr;
+        return fail(LD_ENOMEM, "hipMalloc for the stencil plan's entries: %s", hipGetErrorString(e));
+      }
+      ent_bytes = eb;
+    }
+    if (hb > hacc_bytes) {
+      if (hacc) (void)hipFree(hacc);
+      hacc = nullptr;
+      hacc_bytes = 0;
+      hipError_t e = hipMalloc(&hacc, (size_t)std::max<int64_t>(slots, 1) * hb);
+      if (e != hipSuccess) {
+        hacc = nullptr;
+        return fail(LD_ENOMEM, "hipMalloc for the stencil plan's accumulators: %s", hipGetErrorString(e));
+      }
+      hacc_bytes = hb;
+    }
+    return LD_OK;
+  }
   ~StencilPlan() {
     for (void* p : {(void*)lcol, (void*)emap, (void*)dslot, ent, hacc})
       if (p) (void)hipFree(p);
@@ -1041,14 +1069,6 @@ int build_stencil_plan(const ld_csr* B, hipStream_t s, int tr, int cap, std::sha
   if ((rc = dev_alloc(&P->lcol, (size_t)slots, "the stencil plan")) || (rc = dev_alloc(&P->emap, (size_t)slots, "the stencil plan")) ||
       (rc = dev_alloc(&P->dslot, (size_t)d, "the stencil plan")))
     return rc;
-  {
-    uint4* v = nullptr;
-    if ((rc = dev_alloc(&v, (size_t)slots, "the stencil plan"))) return rc;
-    P->ent = v;
-    double* h = nullptr;
-    if ((rc = dev_alloc(&h, (size_t)slots, "the stencil plan"))) return rc;
-    P->hacc = h;
-  }
   LD_HIP(hipMemcpyAsync(P->dslot, ds.data(), (size_t)d * 8, hipMemcpyHostToDevice, s));
   LD_HIP(hipMemcpyAsync(P->lcol, lc.data(), (size_t)slots * 2, hipMemcpyHostToDevice, s));
   LD_HIP(hipMemcpyAsync(P->emap, em.data(), (size_t)slots * 4, hipMemcpyHostToDevice, s));
@@ -1180,6 +1200,8 @@ struct StagedSteps {
     sh = plane_shape(sh, opt);
     ntiles = (d + sh.tile_rows - 1) / sh.tile_rows;
     hold.take(sp.get());
+    rc = sp->ensure(stencil_entry_bytes(valt), 0);
+    if (rc) return rc;
     sd.ent = sp->ent;
     sd.hacc = sp->hacc;
     sd.K = sp->K;
@@ -2233,6 +2255,8 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
     if (sp) {
       ++staged_passes;
       sp_hold.take(sp.get());  // its per-call buffers, until this call's stream has drained
+      rc = sp->ensure(stencil_entry_bytes(valt), vb);
+      if (rc) return rc;
       sd = StencilDesc{};
       sd.ent = sp->ent;
       sd.hacc = sp->hacc;
