@@ -112,8 +112,8 @@ def workload(name: str):
 # ----------------------------------------------------------------------------------------
 
 def csr_bytes(d: int, nnz: int, val_bytes: int) -> int:
-    """The CSR matrix once: values, int32 columns and 4-byte row pointers (the survey's count; the
-    library's int64 row pointers add (d + 1) * 4 bytes, reported in `moved_bytes_per_launch`)."""
+    """The CSR matrix once: values, int32 columns and 4-byte row pointers (the compulsory-bytes count;
+    the library's int64 row pointers add (d + 1) * 4 bytes, reported in `moved_bytes_per_launch`)."""
     return nnz * (val_bytes + 4) + (d + 1) * 4
 
 

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_step_bytes_model():
-    """The survey's per-step count: matrix once (values + int32 columns + 4-byte row pointers) and
+    """The compulsory per-step count: matrix once (values + int32 columns + 4-byte row pointers) and
     three d x M vectors.  On the 4096^2 grid with BF16 values, M = 32: 7.01 GB per step."""
     d, nnz, M = 4096 * 4096, 83_869_696, 32
     want = nnz * (2 + 4) + (d + 1) * 4 + 3 * d * M * 4

@@ -74,15 +74,15 @@ def test_gershgorin_matches_oracle(ld, oracle_lib, storage):
 
 
 @pytest.mark.parametrize("plain", [False, True])
-def test_cfg0_fp64_parity(ld, oracle_lib, plain):
+def test_grid32_fp64_parity(ld, oracle_lib, plain):
     """32x32 Dirichlet grid + 0.1 I, a = 0.1, b = 8.1, M = 50, n = 30, FP64 (rel 1e-10); both the
     product-identity form (ceil(n/2) products) and the plain one-product-per-degree form."""
     B = synth.grid_laplacian_2d(32)
-    say(f"cfg0 fp64 plain={plain}")
+    say(f"grid32 fp64 plain={plain}")
     r = ld.ld_logdet_cheb(dev(B, shift=0.1), 0.1, 8.1, 30, 50, 1, want_moments=True, want_probes=True,
                           plain=plain)
     o = oracle_lib.logdet(B, 0.1, 8.1, 30, 50, seed=1, shift=0.1, want_moments=True)
-    _compare(r, o, TOL64, B.d, "cfg0", 0.1, 8.1, 30)
+    _compare(r, o, TOL64, B.d, "grid32", 0.1, 8.1, 30)
     assert r["status"] == 0 and r["flags"] == 0
     # and the estimate is within its standard error of the exact value (Cholesky, eigen-sum)
     assert abs(r["logdet"] - 1259.922427278947) < 4 * r["std_err"]

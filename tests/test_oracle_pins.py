@@ -59,7 +59,7 @@ def _alias(series: np.ndarray, n: int) -> np.ndarray:
 @pytest.mark.parametrize("a,b,n", [(0.1, 8.1, 30), (1.0, 23.0, 50), (0.09, 12.09, 60), (0.01, 8.01, 100),
                                    (0.3, 0.7, 0), (0.3, 0.7, 1), (2.0, 3.0, 7)])
 def test_coeffs_closed_form_series_with_aliasing(oracle_lib, a, b, n):
-    """P1: eq. (1) coefficients equal the aliased closed-form Chebyshev series of the log."""
+    """eq. (1) coefficients equal the aliased closed-form Chebyshev series of the log."""
     delta = a / (a + b)
     c = oracle_lib.cheb_coeffs_alg1(delta, n)
     series = _alg1_series_coeffs(delta, 40 * (n + 1) + 4000)
@@ -67,8 +67,8 @@ def test_coeffs_closed_form_series_with_aliasing(oracle_lib, a, b, n):
     np.testing.assert_allclose(c, expect, rtol=0, atol=1e-13)
 
 
-def test_coeffs_survey_values_cfg0(oracle_lib):
-    """P1: for [a, b] = [0.1, 8.1], n = 30 the B-form coefficients are c0 = 0.916290763512757,
+def test_coeffs_closed_form_values_grid32(oracle_lib):
+    """for [a, b] = [0.1, 8.1], n = 30 the B-form coefficients are c0 = 0.916290763512757,
     c1 = 1.599999934894294 (closed-form series); the A-form of Algorithm 1 has c_j^A = (-1)^j c_j^B
     with log(a+b) removed from c_0."""
     c = oracle_lib.cheb_coeffs_alg1(0.1 / 8.2, 30)
@@ -78,7 +78,7 @@ def test_coeffs_survey_values_cfg0(oracle_lib):
 
 @pytest.mark.parametrize("n", [0, 1, 2, 5, 17, 64])
 def test_coeffs_match_numpy_first_kind_interpolation(oracle_lib, n):
-    """P2: eq. (1) is interpolation at first-kind nodes; numpy's chebinterpolate is the same object."""
+    """eq. (1) is interpolation at first-kind nodes; numpy's chebinterpolate is the same object."""
     delta = 0.07
     h = lambda x: np.log(1.0 - ((1.0 - 2.0 * delta) * x + 1.0) / 2.0)
     np.testing.assert_allclose(oracle_lib.cheb_coeffs_alg1(delta, n), npcheb.chebinterpolate(h, n),
@@ -87,7 +87,7 @@ def test_coeffs_match_numpy_first_kind_interpolation(oracle_lib, n):
 
 @pytest.mark.parametrize("n", [0, 3, 10, 31])
 def test_coeffs_reproduce_chebyshev_polynomials(oracle_lib, n):
-    """P2: f = T_i gives c = e_i (c_0 carries weight 1/(n+1), the others 2/(n+1)); p_n(x_k) = f(x_k)."""
+    """f = T_i gives c = e_i (c_0 carries weight 1/(n+1), the others 2/(n+1)); p_n(x_k) = f(x_k)."""
     x = oracle_lib.cheb_nodes(n)
     np.testing.assert_allclose(x, np.cos(math.pi * (np.arange(n + 1) + 0.5) / (n + 1)), atol=0, rtol=1e-15)
     for i in range(n + 1):
@@ -137,14 +137,14 @@ def test_probe_statistics(oracle_lib):
 # --------------------------------------------------------------------------------------
 
 def test_degree_zero_closed_form(oracle_lib):
-    """P3: n = 0 gives Gamma = d log((a+b)/2) for any probes."""
+    """n = 0 gives Gamma = d log((a+b)/2) for any probes."""
     B = synth.grid_laplacian_2d(8)
     r = oracle_lib.logdet(B, 0.1, 8.1, 0, 5, seed=3, shift=0.1)
     assert abs(r["gamma"] - B.d * math.log(4.1)) <= 1e-13 * abs(r["gamma"])
 
 
 def test_diagonal_matrix_exact_at_nodes(oracle_lib):
-    """P4: a diagonal B with entries at the mapped nodes gives Gamma = sum log b_ii exactly,
+    """a diagonal B with entries at the mapped nodes gives Gamma = sum log b_ii exactly,
     because v_i^2 = 1 and the interpolant equals log at the nodes."""
     a, b, n = 0.5, 9.0, 12
     x = np.cos(math.pi * (np.arange(n + 1) + 0.5) / (n + 1))
@@ -157,7 +157,7 @@ def test_diagonal_matrix_exact_at_nodes(oracle_lib):
 
 
 def test_diagonal_matrix_any_entries(oracle_lib):
-    """P4: for any diagonal B every probe gives sum_i p_n(b_ii)."""
+    """for any diagonal B every probe gives sum_i p_n(b_ii)."""
     rng = np.random.default_rng(0)
     a, b, n = 0.2, 5.0, 23
     diag = rng.uniform(a, b, size=57)
@@ -190,7 +190,7 @@ def test_nonsymmetric_probe_vector_rejected_shape(oracle_lib):
 
 
 def test_enumeration_equals_trace(oracle_lib):
-    """P5: averaging over all 2^d sign vectors gives tr p_n(B) = sum_i p_n(lambda_i) exactly, and
+    """averaging over all 2^d sign vectors gives tr p_n(B) = sum_i p_n(lambda_i) exactly, and
     Lemma 7 bounds |log det B - tr p_n| (Section 4.1)."""
     B = synth.random_sparse_spd(11, k_off=2, mseed=5, storage="f64")
     Bd = synth.dense(B)
@@ -207,7 +207,7 @@ def test_enumeration_equals_trace(oracle_lib):
 
 
 def test_scale_invariance(oracle_lib):
-    """P8: Gamma(sB; sa, sb) = Gamma(B; a, b) + d log s with the same probes (the mapped matrix
+    """Gamma(sB; sa, sb) = Gamma(B; a, b) + d log s with the same probes (the mapped matrix
     is unchanged; only the log lift moves)."""
     B = synth.grid_laplacian_2d(10)
     s = 3.7
@@ -218,7 +218,7 @@ def test_scale_invariance(oracle_lib):
 
 
 def test_permutation_invariance(oracle_lib):
-    """P9: Gamma(P B P^T) with probes keyed by the original row index equals Gamma(B)."""
+    """Gamma(P B P^T) with probes keyed by the original row index equals Gamma(B)."""
     B = synth.random_sparse_spd(50, k_off=3, mseed=3, storage="f64")
     a, b = oracle_lib.gershgorin(B)
     perm = np.random.default_rng(1).permutation(B.d)
@@ -231,7 +231,7 @@ def test_permutation_invariance(oracle_lib):
 
 
 def test_moment_invariants(oracle_lib):
-    """P13: v^T v = d; |v^T T_k(X) v| <= d when spec(X) is in [-1, 1] (|T_k| <= 1 there)."""
+    """v^T v = d; |v^T T_k(X) v| <= d when spec(X) is in [-1, 1] (|T_k| <= 1 there)."""
     B = synth.grid_laplacian_2d(16)
     r = oracle_lib.logdet(B, 0.1, 8.1, 40, 3, seed=2, shift=0.1, want_moments=True)
     mom = r["moments"]
@@ -258,8 +258,8 @@ def test_negativity_lemma(oracle_lib):
 # Algorithm 1: statistical pins against closed forms
 # --------------------------------------------------------------------------------------
 
-def test_cfg0_closed_form_and_cholesky(oracle_lib):
-    """P6/P7: the 32x32 grid + 0.1 I (d = 1024): Cholesky log det = closed-form eigen-sum =
+def test_grid32_closed_form_and_cholesky(oracle_lib):
+    """the 32x32 grid + 0.1 I (d = 1024): Cholesky log det = closed-form eigen-sum =
     1259.922427278947; E[Gamma] = sum p_30(lambda); over 40 seeds x 50 probes the mean lies
     within 4 sigma of the exact single-probe variance."""
     N, a, b, n, m = 32, 0.1, 8.1, 30, 50
@@ -281,7 +281,7 @@ def test_cfg0_closed_form_and_cholesky(oracle_lib):
 
 
 def test_grid3d_gradient_and_value_statistics(oracle_lib):
-    """P7/P12 on a small 3-D GMRF Q = tau (kappa^2 I + L): mean of Gamma near sum p_n(lambda);
+    """On a small 3-D GMRF Q = tau (kappa^2 I + L): mean of Gamma near sum p_n(lambda);
     mean gradient near the closed-form d/dkappa sum p_n(lambda) = sum p_n'(lambda) 2 tau kappa."""
     N, tau, kappa, n, m = 6, 1.3, 0.4, 40, 64
     L = synth.grid_laplacian_3d(N)
@@ -348,8 +348,8 @@ def test_theorem2_guarantee(oracle_lib):
 
 def test_lemma7_value_on_the_32_grid(oracle_lib):
     """Lemma 7 on the 32x32 grid + 0.1 I with [a, b] = [0.1, 8.1] (delta = a/(a+b)), n = 30, d = 1024:
-    the bound is 5,525 (to the four figures quoted for this configuration, computed when the
-    configurations were surveyed)."""
+    the bound evaluates to 5,525 to four figures (an evaluation of the lemma's formula made apart from
+    the oracle's code)."""
     assert abs(oracle_lib.lemma_bound(0.1 / 8.2, 30, 1024) - 5525.0) < 0.5
 
 
@@ -441,7 +441,7 @@ def test_alg2_statistical_vs_lu(oracle_lib):
 
 
 def test_alg2_on_spd_matches_alg1_in_expectation(oracle_lib):
-    """P15: for SPD C, log|det C| = log det C; Algorithm 2 and Algorithm 1 agree statistically."""
+    """for SPD C, log|det C| = log det C; Algorithm 2 and Algorithm 1 agree statistically."""
     B = synth.random_sparse_spd(300, k_off=2, mseed=4, storage="f64")
     lam = np.linalg.eigvalsh(synth.dense(B))
     a1, b1 = 0.98 * lam.min(), 1.02 * lam.max()
@@ -462,7 +462,7 @@ def _transpose_index(B):
 
 
 def test_gradient_vs_central_differences(oracle_lib):
-    """P10: central differences of the oracle's own estimate (same probes, a, b fixed).  Moving a
+    """central differences of the oracle's own estimate (same probes, a, b fixed).  Moving a
     single stored entry by h changes Gamma by g_t h; moving B_ij and B_ji together changes it by
     (g_ij + g_ji) h = 2 g_ij h, since the gradient of v^T p(B) v is symmetric at symmetric B.  The
     estimate is a polynomial in the entries, so the O(h^2) error is tiny."""
@@ -495,7 +495,7 @@ def test_gradient_vs_central_differences(oracle_lib):
 
 
 def test_gradient_vs_central_differences_nonsymmetric(oracle_lib):
-    """P10 off the symmetric premise: for a non-symmetric B the recurrence still evaluates
+    """Off the symmetric premise: for a non-symmetric B the recurrence still evaluates
     v^T p(X) v, and its derivative with respect to each stored entry on its own is what central
     differences of the estimate give.  The adjoint recurrence must apply X^T: with X in its
     place the entries of this matrix are off by up to about 200 %."""
@@ -556,7 +556,7 @@ def test_gradient_enumeration_equals_exact_trace_derivative(oracle_lib):
 
 
 def test_gradient_diagonal_closed_form(oracle_lib):
-    """P11: for diagonal B, dGamma/db_ii = p_n'(b_ii) for any probes (numpy chebder)."""
+    """for diagonal B, dGamma/db_ii = p_n'(b_ii) for any probes (numpy chebder)."""
     rng = np.random.default_rng(4)
     a, b, n = 0.3, 6.0, 19
     diag = rng.uniform(a, b, size=33)

@@ -37,7 +37,7 @@ def test_oracle_pins_clean_under_asan_and_ubsan():
     cmd = [sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
            os.path.join(ROOT, "tests", "test_oracle_pins.py"), os.path.join(ROOT, "tests", "test_oracle_trees.py"),
            os.path.join(ROOT, "tests", "test_oracle_taylor.py"), os.path.join(ROOT, "tests", "test_oracle_lanczos.py"),
-           "-k", "not statistical and not cfg0_closed_form"]
+           "-k", "not statistical and not grid32_closed_form"]
     p = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     out = p.stdout + p.stderr
     assert "AddressSanitizer" not in out and "runtime error" not in out, out[-4000:]
