@@ -722,28 +722,34 @@ struct StencilEnt;
 template <>
 struct StencilEnt<VAL_BF16> {
   typedef uint32_t T;  // value bits << 16 | slot
-  __device__ static void get(const void* p, int64_t i, int& lc, float& v) {
-    const uint32_t w = static_cast<const uint32_t*>(p)[i];
+  __device__ static void dec(const T& w, int& lc, float& v) {
     lc = (int)(w & 0xFFFFu);
     v = __uint_as_float(w & 0xFFFF0000u);
+  }
+  __device__ static void get(const void* p, int64_t i, int& lc, float& v) {
+    dec(static_cast<const T*>(p)[i], lc, v);
   }
 };
 template <>
 struct StencilEnt<VAL_F32> {
   typedef uint2 T;  // (slot, value bits)
-  __device__ static void get(const void* p, int64_t i, int& lc, float& v) {
-    const uint2 w = static_cast<const uint2*>(p)[i];
+  __device__ static void dec(const T& w, int& lc, float& v) {
     lc = (int)w.x;
     v = __uint_as_float(w.y);
+  }
+  __device__ static void get(const void* p, int64_t i, int& lc, float& v) {
+    dec(static_cast<const T*>(p)[i], lc, v);
   }
 };
 template <>
 struct StencilEnt<VAL_F64> {
   typedef uint4 T;  // (slot, 0, value bits low, high)
-  __device__ static void get(const void* p, int64_t i, int& lc, double& v) {
-    const uint4 w = static_cast<const uint4*>(p)[i];
+  __device__ static void dec(const T& w, int& lc, double& v) {
     lc = (int)w.x;
     v = __hiloint2double((int)w.w, (int)w.z);
+  }
+  __device__ static void get(const void* p, int64_t i, int& lc, double& v) {
+    dec(static_cast<const T*>(p)[i], lc, v);
   }
 };
 
@@ -763,10 +769,10 @@ __device__ __forceinline__ int halo_offset(const StencilDesc& S, int j) {
 // (a few runs, passed by value), so the block copies those rows of both operands into LDS once, all
 // loads in flight together and none depending on another, and every entry reads them from there: a
 // vector row crosses the cache hierarchy (TR + nofs) / TR times per step instead of once per entry
-// that reaches it.  After the barrier each row loads its KK packed entry slots and accumulators
-// (arithmetic addresses in the padded layout), forms the product on z = y_{k+1} + ck w_k and the
-// SDDMM dots, sums each dot over the row's lanes with DPP exchanges, and writes the accumulators
-// back.  The diagonal entries' accumulators carry d Gamma / d shift, summed after the steps.
+// that reaches it.  Each row's KK packed entry slots and accumulators (arithmetic addresses in the
+// padded layout) load together with the staged rows; after the barrier the row forms the product
+// on z = y_{k+1} + ck w_k and the SDDMM dots, sums each dot over the row's lanes with DPP
+// exchanges, and writes the accumulators back.  The diagonal entries' accumulators carry d Gamma / d shift, summed after the steps.
 template <typename VT, int VALT, int VPL, bool Y2, int KK>
 __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, StencilDesc S, int M, int lpr_log2,
                                                                  int64_t ntiles) {
@@ -823,6 +829,21 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
       vload<VT, VPL>(W + r * M + p0, hw[h]);
     }
   }
+  // the row's entry slots and accumulators, in flight with the staged rows (loaded after the LDS
+  // writes they would cost one more round trip per block); rows past the end read the tile's first
+  // row's slots (valid memory, results dropped), so that the KK consecutive loads carry no
+  // predicate and merge into wide ones
+  const int64_t e0 = (tile * TR + (has ? lr : 0)) * (int64_t)KK;
+  VT* __restrict__ hacc = static_cast<VT*>(S.hacc) + e0;
+  int lc[KK];
+  VT va[KK], h[KK];
+#pragma unroll
+  for (int k = 0; k < KK; ++k) {
+    MV v;
+    StencilEnt<VALT>::get(S.ent, e0 + k, lc[k], v);
+    va[k] = (VT)v;
+    h[k] = hacc[k];
+  }
 #pragma unroll
   for (int h = 0; h < kHaloPasses; ++h) {
     const int j = lr + h * TR;
@@ -839,20 +860,6 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   vstore<VT, VPL>(Ys + lr * tp + sub * VPL, zown);
   vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
 
-  // the row's entry slots, issued before the barrier (their addresses do not depend on it); rows
-  // past the end read the tile's first row's slots (valid memory, results dropped), so that the KK
-  // consecutive loads carry no predicate and merge into wide ones
-  const int64_t e0 = (tile * TR + (has ? lr : 0)) * (int64_t)KK;
-  VT* __restrict__ hacc = static_cast<VT*>(S.hacc) + e0;
-  int lc[KK];
-  VT va[KK], h[KK];
-#pragma unroll
-  for (int k = 0; k < KK; ++k) {
-    MV v;
-    StencilEnt<VALT>::get(S.ent, e0 + k, lc[k], v);
-    va[k] = (VT)v;
-    h[k] = hacc[k];
-  }
   __syncthreads();
 
   const VT ag = (VT)A.ag, ce = (VT)A.ce, gw = (VT)A.gw;
@@ -904,8 +911,8 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
 // Recurrence step on stencil tiles: the step kernel's W_{k+1} = alpha B W_k + beta W_k + cp P with its
 // moment partials, where W_k's rows reach each entry from LDS.  A block covers one row tile of the
 // pass shape (so that its moment partials keep the step kernel's [tile][M] layout) as a sequence of
-// stencil tiles of one row pass each: stage the own and offset rows of W_k, barrier, one row per
-// lane group, barrier.  FP32 vectors, FP32 or BF16 values, a single probe tile.  W_k comes from a
+// stencil tiles of one row pass each: stage the own and offset rows of W_k (the rows' packed entries
+// loaded with them), barrier, one row per lane group, barrier.  FP32 vectors, FP32 or BF16 values, a single probe tile.  W_k comes from a
 // buffer or (k = 0) from the probe hash, for own and offset rows alike.
 template <int VALT, int VPL, int GSRC, int PSRC, int MU, int KK>
 __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, StencilDesc S) {
@@ -975,30 +982,29 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
           vload<VT, VPL>(G + r * M + p0, hw[h]);
       }
     }
+    const int64_t e0 = row * (int64_t)KK;  // slot (tile * TR + lr) * KK of the padded layout
+    typedef typename StencilEnt<VALT>::T ET;
+    ET ew[KK];  // packed entries: loaded with the rows, decoded where they are used
+#pragma unroll
+    for (int k = 0; k < KK; ++k) ew[k] = static_cast<const ET*>(S.ent)[e0 + k];
 #pragma unroll
     for (int h = 0; h < kHaloPasses; ++h) {
       const int j = lr + h * TR;
       if (j < S.nofs) vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
     }
     vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
-    const int64_t e0 = row * (int64_t)KK;  // slot (tile * TR + lr) * KK of the padded layout
-    int lc[KK];
-    VT va[KK];
-#pragma unroll
-    for (int k = 0; k < KK; ++k) {
-      MV v;
-      StencilEnt<VALT>::get(S.ent, e0 + k, lc[k], v);
-      va[k] = (VT)v;
-    }
     __syncthreads();
     VT acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = bd * wown[i];
 #pragma unroll
     for (int k = 0; k < KK; ++k) {
+      int lck;
+      MV vk;
+      StencilEnt<VALT>::dec(ew[k], lck, vk);
       VT g[VPL];
-      vload<VT, VPL>(Ws + lc[k] * tp + sub * VPL, g);
-      const VT a = ag * va[k];
+      vload<VT, VPL>(Ws + lck * tp + sub * VPL, g);
+      const VT a = ag * (VT)vk;
 #pragma unroll
       for (int i = 0; i < VPL; ++i) acc[i] = fma(a, g[i], acc[i]);
     }
