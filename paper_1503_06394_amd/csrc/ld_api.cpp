@@ -1017,8 +1017,9 @@ int build_stencil_plan(const ld_csr* B, hipStream_t s, int tr, int cap, std::sha
   }
   if ((int)runs.size() > kStencilRuns) return LD_OK;
   // a halo beyond three tiles' worth of rows (3-D lattices: four) stages more than the entries save,
-  // and the staged kernels load at most three halo rows per thread
-  // (measured on the 128^3 GMRF: adjoint 0.52 ms per step staged against 0.40 ms explicit)
+  // and the staged kernels load at most three halo rows per thread (on the 128^3 GMRF five halo
+  // rows per thread gave the staged adjoint 0.372 ms against 0.387 ms explicit but the staged step
+  // 0.243 against 0.234 ms, and slowed the 2-D grids' staged kernels by 3 %)
   if ((int64_t)ofs.size() > 3 * (int64_t)tr) return LD_OK;
   for (auto& r : runs)
     if (r.first < INT32_MIN / 2 || r.first > INT32_MAX / 2) return LD_OK;
