@@ -428,9 +428,9 @@ def main() -> None:
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if vec_f64 else "f32", "data": "synthetic",
         "config": {"workload": W["desc"], "d": d, "nnz": nnz, "M": M, "n": n, "values": B.storage,
-                   "step": ("gershgorin bounds + forward + gradient" if do_grad else
-                            "Algorithm 2 forward (sigma bounds estimated once, before timing)" if nonsingular
-                            else "bounds + forward"),
+                   "step": ("Algorithm 2 forward (sigma bounds estimated once, before timing)" if nonsingular
+                            else ("gershgorin bounds + " if W["a"] is None else "")
+                            + ("forward + gradient" if do_grad else "forward")),
                    "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "accuracy": accuracy, "kernels": extra,
     }
