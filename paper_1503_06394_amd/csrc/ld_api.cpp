@@ -954,8 +954,8 @@ void drop_pattern(const ld_csr* B) {
 // Builds the stencil plan on the host from a copy of the pattern, or leaves `out` null when the
 // pattern is not one for tiles of `tr` rows: more than `cap` distinct offsets (column - tile's first
 // row) outside the tile over all tiles, or more than kStencilRuns runs of them, rows longer than
-// kStencilK, a row without its diagonal, or a padded layout more than 1.5 times the stored entries.  Tiles are independent, so ranges of them are scanned on several
-// host threads.
+// kStencilK, a row without its diagonal, or a padded layout more than 1.5 times the stored entries.
+// Tiles are independent, so ranges of them are scanned on several host threads.
 int build_stencil_plan(const ld_csr* B, hipStream_t s, int tr, int cap, std::shared_ptr<StencilPlan>& out) {
   out.reset();
   const int64_t d = B->rows, nnz = B->nnz;
@@ -2401,7 +2401,7 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
             A.cwp = al[j];
           }
           if (sp)
-            LD_HIP(launch_adjoint_stencil(A, sd, Mp, sh, vec_f64, valt, y2 != nullptr, s));
+            LD_HIP(launch_adjoint_stencil(A, sd, Mp, sh, vec_f64, valt, y2 != nullptr, false, s));
           else
             LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, true, false, y2 != nullptr, sym, s));
           LD_HIP(tm.mark(T_ADJ));
@@ -2409,11 +2409,8 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
           y1 = o;
         }
       }
-      if (sp) {  // the staged steps' accumulators: the shift's derivative off the diagonal, then entry order
-        LD_HIP(launch_stencil_diag_sum(sp->hacc, vec_f64, sp->dslot, d, gdiag_part, s));
-        LD_HIP(launch_stencil_unpack(sp->hacc, vec_f64, sp->emap, sp->slots, Gacc, s));
-      }
-      // the y_1 w_0^T term, w_0 = v
+      // the y_1 w_0^T term, w_0 = v: on the staged tiles into their accumulators when the form allows,
+      // else by the general kernel into entry order after them
       A.Y1 = y1;
       A.Y2 = nullptr;
       A.out = nullptr;
@@ -2423,7 +2420,13 @@ static int grad_body(const ld_csr* B, double a, double b, int n, int M, uint64_t
       A.ck = 0.0;
       A.ce = shifted ? eps[1] : 0.0;  // y_1 = yh_1 - eps_1 w_0
       A.gw = 1.0;
-      LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, false, true, false, sym, s));
+      const bool staged_close = sp && adjoint_stencil_sddmm_supported(vec_f64, valt, sh, sd);
+      if (staged_close) LD_HIP(launch_adjoint_stencil(A, sd, Mp, sh, vec_f64, valt, false, true, s));
+      if (sp) {  // the staged steps' accumulators: the shift's derivative off the diagonal, then entry order
+        LD_HIP(launch_stencil_diag_sum(sp->hacc, vec_f64, sp->dslot, d, gdiag_part, s));
+        LD_HIP(launch_stencil_unpack(sp->hacc, vec_f64, sp->emap, sp->slots, Gacc, s));
+      }
+      if (!staged_close) LD_HIP(launch_adjoint(A, Mp, sh, vec_f64, valt, false, true, false, sym, s));
       LD_HIP(tm.mark(T_OTHER));  // an SDDMM without the product: not timed with the adjoint steps
     }
   }

@@ -139,8 +139,11 @@ inline size_t stencil_entry_bytes(int valt) { return valt == VAL_BF16 ? 4 : (val
 
 // The shifted adjoint step (spmm, ck/ce, no Wm/Wp) on staged stencil tiles; the SDDMM accumulates
 // into S.hacc (the diagonal entries' accumulators carry the shift's derivative; no gdiag partials).
+// sddmm: the closing term y_1 w_0^T alone (A.Y1 = yh_1, A.ce = eps_1, w_0 from the probe hash of
+// A.seed; no product, no output), for the forms adjoint_stencil_sddmm_supported admits.
 hipError_t launch_adjoint_stencil(const AdjDesc& A, const StencilDesc& S, int M, const Shape& sh, int vec_f64,
-                                  int valt, bool y2, hipStream_t s);
+                                  int valt, bool y2, bool sddmm, hipStream_t s);
+bool adjoint_stencil_sddmm_supported(int vec_f64, int valt, const Shape& sh, const StencilDesc& S);
 // The recurrence step (launch_step's operands) on staged stencil tiles, for the combinations
 // step_stencil_supported accepts: FP32 vectors, FP32/BF16 values, the diagonal folded into the product,
 // W_k from a buffer (W_{k-1} from a buffer or the probe hash, or none with probe moments) or from the

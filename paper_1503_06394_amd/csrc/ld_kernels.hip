@@ -772,8 +772,10 @@ __device__ __forceinline__ int halo_offset(const StencilDesc& S, int j) {
 // that reaches it.  Each row's KK packed entry slots and accumulators (arithmetic addresses in the
 // padded layout) load together with the staged rows; after the barrier the row forms the product
 // on z = y_{k+1} + ck w_k and the SDDMM dots, sums each dot over the row's lanes with DPP
-// exchanges, and writes the accumulators back.  The diagonal entries' accumulators carry d Gamma / d shift, summed after the steps.
-template <typename VT, int VALT, int VPL, bool Y2, int KK>
+// exchanges, and writes the accumulators back.  The diagonal entries' accumulators carry
+// d Gamma / d shift, summed after the steps.  SD: the closing SDDMM term y_1 w_0^T alone, w_0 the
+// probe block (own and offset rows from the probe hash, nothing staged but them), no product.
+template <typename VT, int VALT, int VPL, bool Y2, int KK, bool SD = false>
 __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, StencilDesc S, int M, int lpr_log2,
                                                                  int64_t ntiles) {
   typedef typename Val<VALT>::T MV;
@@ -810,7 +812,10 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   for (int i = 0; i < VPL; ++i) yown[i] = wown[i] = x2[i] = VT(0);
   if (has && pact) {
     vload<VT, VPL>(Y1 + roff, yown);
-    vload<VT, VPL>(W + roff, wown);
+    if constexpr (SD)
+      probe_signs<VT, VPL>(A.seed, row, p0, wown);
+    else
+      vload<VT, VPL>(W + roff, wown);
     if constexpr (Y2) vload_nt<VT, VPL>(static_cast<const VT*>(A.Y2) + roff, x2);
   }
   // Ys holds the product's operand z = y_{k+1} + ck w_k of every staged row, Ws holds w_k
@@ -825,8 +830,12 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
     for (int i = 0; i < VPL; ++i) hy[h][i] = hw[h][i] = VT(0);
     const int64_t r = row0 + halo_offset(S, j);
     if (j < S.nofs && r >= 0 && r < A.d && pact) {
-      vload<VT, VPL>(Y1 + r * M + p0, hy[h]);
-      vload<VT, VPL>(W + r * M + p0, hw[h]);
+      if constexpr (SD) {
+        probe_signs<VT, VPL>(A.seed, r, p0, hw[h]);
+      } else {
+        vload<VT, VPL>(Y1 + r * M + p0, hy[h]);
+        vload<VT, VPL>(W + r * M + p0, hw[h]);
+      }
     }
   }
   // the row's entry slots and accumulators, in flight with the staged rows (loaded after the LDS
@@ -848,16 +857,18 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   for (int h = 0; h < kHaloPasses; ++h) {
     const int j = lr + h * TR;
     if (j < S.nofs) {
+      if constexpr (!SD) {
 #pragma unroll
-      for (int i = 0; i < VPL; ++i) hy[h][i] = fma(ck, hw[h][i], hy[h][i]);
-      vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, hy[h]);
+        for (int i = 0; i < VPL; ++i) hy[h][i] = fma(ck, hw[h][i], hy[h][i]);
+        vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, hy[h]);
+      }
       vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
     }
   }
   VT zown[VPL];
 #pragma unroll
   for (int i = 0; i < VPL; ++i) zown[i] = fma(ck, wown[i], yown[i]);
-  vstore<VT, VPL>(Ys + lr * tp + sub * VPL, zown);
+  if constexpr (!SD) vstore<VT, VPL>(Ys + lr * tp + sub * VPL, zown);
   vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
 
   __syncthreads();
@@ -873,13 +884,13 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
 #pragma unroll
   for (int k = 0; k < KK; ++k) {
     VT zg[VPL], wg[VPL];
-    vload<VT, VPL>(Ys + lc[k] * tp + sub * VPL, zg);
+    if constexpr (!SD) vload<VT, VPL>(Ys + lc[k] * tp + sub * VPL, zg);
     vload<VT, VPL>(Ws + lc[k] * tp + sub * VPL, wg);
     const VT a = ag * va[k];
     dp[k] = VT(0);
 #pragma unroll
     for (int i = 0; i < VPL; ++i) {
-      acc[i] = fma(a, zg[i], acc[i]);
+      if constexpr (!SD) acc[i] = fma(a, zg[i], acc[i]);
       dp[k] = fma(ysd[i], wg[i], dp[k]);
     }
   }
@@ -891,6 +902,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   if (sub == 0)
 #pragma unroll
     for (int k = 0; k < KK; ++k) hacc[k] = h[k];
+  if constexpr (SD) return;
   const VT bd = (VT)A.bd, cp = (VT)A.cp, cw = (VT)A.cw;
 #pragma unroll
   for (int i = 0; i < VPL; ++i) {
@@ -912,8 +924,9 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
 // moment partials, where W_k's rows reach each entry from LDS.  A block covers one row tile of the
 // pass shape (so that its moment partials keep the step kernel's [tile][M] layout) as a sequence of
 // stencil tiles of one row pass each: stage the own and offset rows of W_k (the rows' packed entries
-// loaded with them), barrier, one row per lane group, barrier.  FP32 vectors, FP32 or BF16 values, a single probe tile.  W_k comes from a
-// buffer or (k = 0) from the probe hash, for own and offset rows alike.
+// loaded with them), barrier, one row per lane group, barrier.  FP32 vectors, FP32 or BF16 values,
+// a single probe tile.  W_k comes from a buffer or (k = 0) from the probe hash, for own and offset
+// rows alike.
 template <int VALT, int VPL, int GSRC, int PSRC, int MU, int KK>
 __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, StencilDesc S) {
   typedef float VT;
@@ -1689,13 +1702,27 @@ hipError_t launch_adjoint(const AdjDesc& A, int M, const Shape& sh, int vec_f64,
 
 template <typename VT, int VALT>
 static hipError_t adj_stencil_by_vpl(const AdjDesc& A, const StencilDesc& S, int M, const Shape& sh, bool y2,
-                                     hipStream_t s) {
+                                     bool sddmm, hipStream_t s) {
   const int tr = stencil_tile_rows(sh.lpr_log2);
   const int64_t ntiles = (A.d + tr - 1) / tr;
   const int64_t per = (ntiles + 7) / 8;
   const dim3 grid((unsigned)(per * 8));
   const size_t lds = 2 * (size_t)(tr + S.nofs) * (size_t)((1 << sh.lpr_log2) * sh.vpl) * sizeof(VT);
   if (tr > kStencilRows || lds > (size_t)kStencilLdsBytes || S.nofs > kHaloPasses * tr) return hipErrorInvalidValue;
+  if (sddmm) {  // the closing SDDMM: FP32 vectors only (adjoint_stencil_sddmm_supported)
+    if constexpr (sizeof(VT) == 4 && VALT != VAL_F64) {
+#define LD_STEN_SD(V_, K_)                                                                                       \
+  if (sh.vpl == V_ && S.K == K_) {                                                                               \
+    hipLaunchKernelGGL((adjoint_stencil_kernel<VT, VALT, V_, false, K_, true>), grid, dim3(kBlock), lds, s, A, S, \
+                       M, sh.lpr_log2, ntiles);                                                                 \
+    return hipGetLastError();                                                                                   \
+  }
+      LD_STEN_SD(2, 5) LD_STEN_SD(2, 7) LD_STEN_SD(2, 8)
+      LD_STEN_SD(4, 5) LD_STEN_SD(4, 7) LD_STEN_SD(4, 8)
+#undef LD_STEN_SD
+    }
+    return hipErrorInvalidValue;
+  }
   // K = 5 and 7 (2-D and 3-D grids) run exactly; other K up to kStencilK are planned as 8
 #define LD_STEN(V_, Y_, K_)                                                                                      \
   if (sh.vpl == V_ && y2 == Y_ && S.K == K_) {                                                                   \
@@ -1716,18 +1743,23 @@ static hipError_t adj_stencil_by_vpl(const AdjDesc& A, const StencilDesc& S, int
 }
 
 hipError_t launch_adjoint_stencil(const AdjDesc& A, const StencilDesc& S, int M, const Shape& sh, int vec_f64,
-                                  int valt, bool y2, hipStream_t s) {
+                                  int valt, bool y2, bool sddmm, hipStream_t s) {
   if (A.d <= 0) return hipSuccess;
+  if (sddmm && (y2 || !adjoint_stencil_sddmm_supported(vec_f64, valt, sh, S))) return hipErrorInvalidValue;
   if (vec_f64) {
-    if (valt == VAL_F64) return adj_stencil_by_vpl<double, VAL_F64>(A, S, M, sh, y2, s);
-    if (valt == VAL_F32) return adj_stencil_by_vpl<double, VAL_F32>(A, S, M, sh, y2, s);
-    if (valt == VAL_BF16) return adj_stencil_by_vpl<double, VAL_BF16>(A, S, M, sh, y2, s);
+    if (valt == VAL_F64) return adj_stencil_by_vpl<double, VAL_F64>(A, S, M, sh, y2, sddmm, s);
+    if (valt == VAL_F32) return adj_stencil_by_vpl<double, VAL_F32>(A, S, M, sh, y2, sddmm, s);
+    if (valt == VAL_BF16) return adj_stencil_by_vpl<double, VAL_BF16>(A, S, M, sh, y2, sddmm, s);
   } else {
-    if (valt == VAL_F64) return adj_stencil_by_vpl<float, VAL_F64>(A, S, M, sh, y2, s);
-    if (valt == VAL_F32) return adj_stencil_by_vpl<float, VAL_F32>(A, S, M, sh, y2, s);
-    if (valt == VAL_BF16) return adj_stencil_by_vpl<float, VAL_BF16>(A, S, M, sh, y2, s);
+    if (valt == VAL_F64) return adj_stencil_by_vpl<float, VAL_F64>(A, S, M, sh, y2, sddmm, s);
+    if (valt == VAL_F32) return adj_stencil_by_vpl<float, VAL_F32>(A, S, M, sh, y2, sddmm, s);
+    if (valt == VAL_BF16) return adj_stencil_by_vpl<float, VAL_BF16>(A, S, M, sh, y2, sddmm, s);
   }
   return hipErrorInvalidValue;
+}
+
+bool adjoint_stencil_sddmm_supported(int vec_f64, int valt, const Shape& sh, const StencilDesc& S) {
+  return !vec_f64 && valt != VAL_F64 && (sh.vpl == 2 || sh.vpl == 4) && (S.K == 5 || S.K == 7 || S.K == 8);
 }
 
 // Operand sources and moment forms the staged step is built for: the product-identity forward (k = 0
