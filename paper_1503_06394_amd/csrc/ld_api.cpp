@@ -1214,9 +1214,13 @@ struct StagedSteps {
     LD_HIP(launch_pattern_hash(B->row_ptr, B->col_idx, d, B->nnz, hash_dev, s));
     return LD_OK;
   }
+  // Whether a step of this form would run on the staged tiles.
+  bool staged_for(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu) const {
+    return sp && step_stencil_supported(L, vec_f64, valt, gsrc, dsrc, psrc, mu);
+  }
   // One step, staged when the plan and the step's form allow it.
   hipError_t step(const StepLaunch& L, int vec_f64, int valt, int gsrc, int dsrc, int psrc, int mu, hipStream_t s) {
-    if (sp && step_stencil_supported(L, vec_f64, valt, gsrc, dsrc, psrc, mu)) {
+    if (staged_for(L, vec_f64, valt, gsrc, dsrc, psrc, mu)) {
       ++steps;
       return launch_step_stencil(L, sd, valt, gsrc, psrc, mu, s);
     }
@@ -1461,11 +1465,12 @@ int run_taylor(const ld_csr* B, double a, double b, int n, int M, uint64_t seed,
     D.out = buf[k & 1];
     D.ag = -1.0 / scale;
     D.bd = 1.0 - B->diag_shift / scale;
-    D.cp = 0.0;  // the probe-hash third operand costs no memory traffic and is scaled away
+    D.cp = 0.0;  // no third operand: the general kernel takes the probe hash for it, scaled away
     D.mu_part = part_base + (int64_t)k * kstride;
     L.d0 = D;
-    LD_HIP(st.step(L, vec_f64, valt, k == 0 ? SRC_HASH : SRC_BUF, SRC_SAME, k == 0 ? SRC_NONE : SRC_HASH, MU_PROBE,
-                   s));
+    const int gsrc = k == 0 ? SRC_HASH : SRC_BUF;
+    const bool bare = k == 0 || st.staged_for(L, vec_f64, valt, gsrc, SRC_SAME, SRC_NONE, MU_PROBE);
+    LD_HIP(st.step(L, vec_f64, valt, gsrc, SRC_SAME, bare ? SRC_NONE : SRC_HASH, MU_PROBE, s));
     LD_HIP(tm.mark(T_STEP));
   }
   std::vector<double> red((size_t)M * rows, 0.0);
