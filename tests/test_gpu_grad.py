@@ -106,6 +106,8 @@ STENCIL_CASES = {
     # name: (builder, shift, M, degree, staged by default)
     "grid2d_ragged_f64": (lambda: _grid2d_rect(37, 41, "f64"), 0.3, 16, 24, True),
     "grid2d_f32_M32": (lambda: _grid2d_rect(64, 64, "f32"), 0.05, 32, 40, True),
+    "grid2d_ragged_bf16_M32": (lambda: _grid2d_rect(45, 37, "bf16"), 0.05, 32, 30, True),  # the headline's types
+    "grid2d_ragged_bf16_M18": (lambda: _grid2d_rect(29, 53, "bf16"), 0.2, 18, 25, True),  # 2 probes per lane
     "grid3d_f32_M64": (lambda: synth.grid_laplacian_3d(12, "f32"), 0.2, 64, 30, False),  # halo of 4 tiles
     "hex2d_f64_K7": (lambda: _hex2d(33, 29, "f64"), 0.1, 16, 22, True),
     "band3_f64_M8": (lambda: _banded(1500, 3, "f64", 4), 0.0, 8, 20, True),
