@@ -49,12 +49,17 @@ __device__ __forceinline__ uint64_t probe_word(uint64_t seed, uint64_t row, uint
   return z ^ (z >> 31);
 }
 
+// The signs of probes p0 .. p0 + N - 1 (within one 64-probe block) from their probe word.
 template <typename VT, int N>
-__device__ __forceinline__ void probe_signs(uint64_t seed, int64_t row, int p0, VT* r) {
-  const uint64_t w = probe_word(seed, (uint64_t)row, (uint32_t)(p0 >> 6));
+__device__ __forceinline__ void word_signs(uint64_t w, int p0, VT* r) {
   const uint32_t bits = (uint32_t)(w >> (p0 & 63));
 #pragma unroll
   for (int i = 0; i < N; ++i) r[i] = ((bits >> i) & 1u) ? VT(-1) : VT(1);
+}
+
+template <typename VT, int N>
+__device__ __forceinline__ void probe_signs(uint64_t seed, int64_t row, int p0, VT* r) {
+  word_signs<VT, N>(probe_word(seed, (uint64_t)row, (uint32_t)(p0 >> 6)), p0, r);
 }
 
 template <int VALT>
@@ -764,6 +769,20 @@ __device__ __forceinline__ int halo_offset(const StencilDesc& S, int j) {
   return off;
 }
 
+// Staged rows that are probe signs (W_0 = V) go to LDS as probe words: one hash per staged row
+// and 64-probe block, spread over the block's threads, instead of one per row in every lane that
+// stages it.  Word q * nblk + b holds block b of staged row q (own rows first, then the halo);
+// rows outside the matrix get 0 (no entry reaches them).
+__device__ __forceinline__ void stage_probe_words(uint64_t* wd, uint64_t seed, const StencilDesc& S, int64_t sr0,
+                                                  int TR, int nblk_log2, int64_t d) {
+  const int n = (TR + S.nofs) << nblk_log2;
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const int q = i >> nblk_log2, b = i & ((1 << nblk_log2) - 1);
+    const int64_t r = sr0 + (q < TR ? q : halo_offset(S, q - TR));
+    wd[i] = (r >= 0 && r < d) ? probe_word(seed, (uint64_t)r, (uint32_t)b) : 0ull;
+  }
+}
+
 // The shifted adjoint gathers rows of both y_{k+1} and w_k at every stored entry.  On a stencil
 // pattern the rows a tile's entries reach are its own rows and r0 + ofs[j] for a short offset list
 // (a few runs, passed by value), so the block copies those rows of both operands into LDS once, all
@@ -774,7 +793,7 @@ __device__ __forceinline__ int halo_offset(const StencilDesc& S, int j) {
 // on z = y_{k+1} + ck w_k and the SDDMM dots, sums each dot over the row's lanes with DPP
 // exchanges, and writes the accumulators back.  The diagonal entries' accumulators carry
 // d Gamma / d shift, summed after the steps.  SD: the closing SDDMM term y_1 w_0^T alone, w_0 the
-// probe block (own and offset rows from the probe hash, nothing staged but them), no product.
+// probe block (nothing staged but the probe words of the own and offset rows), no product.
 template <typename VT, int VALT, int VPL, bool Y2, int KK, bool SD = false>
 __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, StencilDesc S, int M, int lpr_log2,
                                                                  int64_t ntiles) {
@@ -800,6 +819,8 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   extern __shared__ __align__(16) unsigned char ld_stencil_smem[];
   VT* Ys = reinterpret_cast<VT*>(ld_stencil_smem);
   VT* Ws = Ys + (TR + S.nofs) * tp;
+  uint64_t* Wd = reinterpret_cast<uint64_t*>(ld_stencil_smem);  // SD: probe words of w_0 = V
+  const int nblk_log2 = tp > 128 ? 2 : (tp > 64 ? 1 : 0);
 
   const int lr = wave * RPW + grp;
   const bool has = lr < nown;
@@ -812,10 +833,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
   for (int i = 0; i < VPL; ++i) yown[i] = wown[i] = x2[i] = VT(0);
   if (has && pact) {
     vload<VT, VPL>(Y1 + roff, yown);
-    if constexpr (SD)
-      probe_signs<VT, VPL>(A.seed, row, p0, wown);
-    else
-      vload<VT, VPL>(W + roff, wown);
+    if constexpr (!SD) vload<VT, VPL>(W + roff, wown);
     if constexpr (Y2) vload_nt<VT, VPL>(static_cast<const VT*>(A.Y2) + roff, x2);
   }
   // Ys holds the product's operand z = y_{k+1} + ck w_k of every staged row, Ws holds w_k
@@ -829,10 +847,8 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
 #pragma unroll
     for (int i = 0; i < VPL; ++i) hy[h][i] = hw[h][i] = VT(0);
     const int64_t r = row0 + halo_offset(S, j);
-    if (j < S.nofs && r >= 0 && r < A.d && pact) {
-      if constexpr (SD) {
-        probe_signs<VT, VPL>(A.seed, r, p0, hw[h]);
-      } else {
+    if constexpr (!SD) {
+      if (j < S.nofs && r >= 0 && r < A.d && pact) {
         vload<VT, VPL>(Y1 + r * M + p0, hy[h]);
         vload<VT, VPL>(W + r * M + p0, hw[h]);
       }
@@ -853,25 +869,30 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
     va[k] = (VT)v;
     h[k] = hacc[k];
   }
-#pragma unroll
-  for (int h = 0; h < kHaloPasses; ++h) {
-    const int j = lr + h * TR;
-    if (j < S.nofs) {
-      if constexpr (!SD) {
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) hy[h][i] = fma(ck, hw[h][i], hy[h][i]);
-        vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, hy[h]);
-      }
-      vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
-    }
-  }
   VT zown[VPL];
 #pragma unroll
   for (int i = 0; i < VPL; ++i) zown[i] = fma(ck, wown[i], yown[i]);
-  if constexpr (!SD) vstore<VT, VPL>(Ys + lr * tp + sub * VPL, zown);
-  vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
+  if constexpr (SD) {
+    stage_probe_words(Wd, A.seed, S, row0, TR, nblk_log2, A.d);
+  } else {
+#pragma unroll
+    for (int h = 0; h < kHaloPasses; ++h) {
+      const int j = lr + h * TR;
+      if (j < S.nofs) {
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) hy[h][i] = fma(ck, hw[h][i], hy[h][i]);
+        vstore<VT, VPL>(Ys + (TR + j) * tp + sub * VPL, hy[h]);
+        vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
+      }
+    }
+    vstore<VT, VPL>(Ys + lr * tp + sub * VPL, zown);
+    vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
+  }
 
   __syncthreads();
+  if constexpr (SD) {
+    if (has && pact) word_signs<VT, VPL>(Wd[(lr << nblk_log2) + (p0 >> 6)], p0, wown);
+  }
 
   const VT ag = (VT)A.ag, ce = (VT)A.ce, gw = (VT)A.gw;
   VT ysd[VPL], acc[VPL];
@@ -884,8 +905,12 @@ __global__ void __launch_bounds__(kBlock) adjoint_stencil_kernel(AdjDesc A, Sten
 #pragma unroll
   for (int k = 0; k < KK; ++k) {
     VT zg[VPL], wg[VPL];
-    if constexpr (!SD) vload<VT, VPL>(Ys + lc[k] * tp + sub * VPL, zg);
-    vload<VT, VPL>(Ws + lc[k] * tp + sub * VPL, wg);
+    if constexpr (SD) {
+      word_signs<VT, VPL>(Wd[(lc[k] << nblk_log2) + (p0 >> 6)], p0, wg);
+    } else {
+      vload<VT, VPL>(Ys + lc[k] * tp + sub * VPL, zg);
+      vload<VT, VPL>(Ws + lc[k] * tp + sub * VPL, wg);
+    }
     const VT a = ag * va[k];
     dp[k] = VT(0);
 #pragma unroll
@@ -956,6 +981,8 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
 
   extern __shared__ __align__(16) unsigned char ld_step_smem[];
   VT* Ws = reinterpret_cast<VT*>(ld_step_smem);
+  uint64_t* Wd = reinterpret_cast<uint64_t*>(ld_step_smem);  // probe words (W_0 from the hash)
+  const int nblk_log2 = tp > 128 ? 2 : (tp > 64 ? 1 : 0);       // 64-probe blocks of the tile's probes
   const int lr = wave * RPW + grp;
 
   VT mu[VPL], mu2[VPL];
@@ -970,43 +997,45 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
     VT wown[VPL], pv[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) wown[i] = pv[i] = VT(0);
-    if (has && pact) {
-      if constexpr (GSRC == SRC_HASH)
-        probe_signs<VT, VPL>(D.seed, row, p0, wown);
-      else
-        vload<VT, VPL>(G + roff, wown);
+    if constexpr (GSRC != SRC_HASH) {
+      if (has && pact) vload<VT, VPL>(G + roff, wown);
     }
     if constexpr (PSRC == SRC_BUF) {
       if (has && pact) vload_nt<VT, VPL>(P + roff, pv);
     } else if constexpr (PSRC == SRC_HASH) {
       probe_signs<VT, VPL>(D.seed, row, p0, pv);
     }
-    VT hw[kHaloPasses][VPL];
-#pragma unroll
-    for (int h = 0; h < kHaloPasses; ++h) {
-      const int j = lr + h * TR;
-#pragma unroll
-      for (int i = 0; i < VPL; ++i) hw[h][i] = VT(0);
-      const int64_t r = sr0 + halo_offset(S, j);
-      if (j < S.nofs && r >= 0 && r < D.d && pact) {
-        if constexpr (GSRC == SRC_HASH)
-          probe_signs<VT, VPL>(D.seed, r, p0, hw[h]);
-        else
-          vload<VT, VPL>(G + r * M + p0, hw[h]);
-      }
-    }
     const int64_t e0 = row * (int64_t)KK;  // slot (tile * TR + lr) * KK of the padded layout
     typedef typename StencilEnt<VALT>::T ET;
     ET ew[KK];  // packed entries: loaded with the rows, decoded where they are used
+    if constexpr (GSRC == SRC_HASH) {
+      // W_0 = V: the packed entries in flight while the block hashes the staged rows' probe words
 #pragma unroll
-    for (int k = 0; k < KK; ++k) ew[k] = static_cast<const ET*>(S.ent)[e0 + k];
+      for (int k = 0; k < KK; ++k) ew[k] = static_cast<const ET*>(S.ent)[e0 + k];
+      stage_probe_words(Wd, D.seed, S, sr0, TR, nblk_log2, D.d);
+    } else {
+      VT hw[kHaloPasses][VPL];
 #pragma unroll
-    for (int h = 0; h < kHaloPasses; ++h) {
-      const int j = lr + h * TR;
-      if (j < S.nofs) vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
+      for (int h = 0; h < kHaloPasses; ++h) {
+        const int j = lr + h * TR;
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) hw[h][i] = VT(0);
+        const int64_t r = sr0 + halo_offset(S, j);
+        if (j < S.nofs && r >= 0 && r < D.d && pact) vload<VT, VPL>(G + r * M + p0, hw[h]);
+      }
+#pragma unroll
+      for (int k = 0; k < KK; ++k) ew[k] = static_cast<const ET*>(S.ent)[e0 + k];
+#pragma unroll
+      for (int h = 0; h < kHaloPasses; ++h) {
+        const int j = lr + h * TR;
+        if (j < S.nofs) vstore<VT, VPL>(Ws + (TR + j) * tp + sub * VPL, hw[h]);
+      }
+      vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
     }
-    vstore<VT, VPL>(Ws + lr * tp + sub * VPL, wown);
     __syncthreads();
+    if constexpr (GSRC == SRC_HASH) {
+      if (has && pact) word_signs<VT, VPL>(Wd[(lr << nblk_log2) + (p0 >> 6)], p0, wown);
+    }
     VT acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = bd * wown[i];
@@ -1016,7 +1045,10 @@ __global__ void __launch_bounds__(kBlock) step_stencil_kernel(StepLaunch L, Sten
       MV vk;
       StencilEnt<VALT>::dec(ew[k], lck, vk);
       VT g[VPL];
-      vload<VT, VPL>(Ws + lck * tp + sub * VPL, g);
+      if constexpr (GSRC == SRC_HASH)
+        word_signs<VT, VPL>(Wd[(lck << nblk_log2) + (p0 >> 6)], p0, g);
+      else
+        vload<VT, VPL>(Ws + lck * tp + sub * VPL, g);
       const VT a = ag * (VT)vk;
 #pragma unroll
       for (int i = 0; i < VPL; ++i) acc[i] = fma(a, g[i], acc[i]);
